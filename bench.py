@@ -1,0 +1,155 @@
+"""Throughput of online convolutional sparse coding on one MI355X.
+
+One step = one body of Algorithm 3 for one sample: the code update (J_z = 10
+code-ADMM iterations), the history fold and DictOCSC (J = 10 dictionary-ADMM
+iterations), on 128 x 128 grids with K = 100 filters of 11 x 11, in FP32.
+Samples are synthetic (Bernoulli-Gaussian codes on 100 x 100 content, the
+paper's K, filter size and beta), generated on the host and resident in HBM
+before the timed region.
+
+Prints one JSON line.  The roofline object covers the dominant kernel, the
+D-step sweep that streams the inverse history matrices C (K x K per
+frequency), timed with HIP events on the library's stream over the timed
+region.  The cpu_baseline object times the FP64 oracle on a bounded sample of
+the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "images/s coded+dict-updated (K=100, 128²) plain vs BF16/served; p99 latency"
+WORKLOAD = "ocsc_128x128_k100_f32"
+HBM_PEAK_GBS = 8000.0
+
+
+def dstep_bytes_per_launch(K: int, Pf: int, real_bytes: int) -> int:
+    """Algorithmic HBM bytes of one D-step sweep without a fold.
+
+    Per frequency: read C_p (K*K reals, packed Hermitian), read the right-hand
+    side (K complex), write d_p (K complex).
+    """
+    return Pf * (K * K * real_bytes + 2 * K * 2 * real_bytes)
+
+
+def oracle_baseline(wl, n_steps: int):
+    import numpy as np
+    import oracle.ocsc_oracle as O
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    xs = synth.images(wl, synth.pass_order(wl.n_images, wl.seed, 0)[:n_steps + 1])
+    m = O.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho,
+               iters_code=wl.iters_code, iters_dict=wl.iters_dict)
+    m.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
+    m.step(xs[0][None])                      # first step allocates; not timed
+    t0 = time.perf_counter()
+    for x in xs[1:]:
+        m.step(x[None])
+    dt = time.perf_counter() - t0
+    return {"value": n_steps / dt, "unit": "images/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_steps} steps of the {wl.name} workload (FP64 NumPy oracle, after one untimed step)",
+            "seconds": dt, "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--pool", type=int, default=64, help="distinct images resident on the device")
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps timed for cpu_baseline (0: skip)")
+    ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per D-step launch")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1706_06972_amd import ocsc as L
+
+    wl = synth.WORKLOADS[WORKLOAD]
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    n_img = max(1, min(args.pool, args.warmup + args.steps))
+    order = synth.pass_order(wl.n_images, wl.seed, 0)[:n_img]
+    xs = torch.as_tensor(synth.images(wl, order), dtype=torch.float32, device=dev).contiguous()
+    codes = torch.empty((1, wl.K, wl.pad_h, wl.pad_w), dtype=torch.float32, device=dev)
+
+    g = L.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
+               iters_dict=wl.iters_dict, max_batch=1, precision="f32", device=dev)
+    g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
+
+    def step(i):
+        x = xs[i % n_img:i % n_img + 1]
+        L.ocsc_code_update(g.ctx, x, 1, codes)
+        L.ocsc_history_accumulate(g.ctx)
+        L.ocsc_dict_update(g.ctx)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    L.ocsc_profile_enable(g.ctx, ["dstep", "history", "zstep", "codeplane", "vstep", "fft"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = {}
+    for cls in ("dstep", "history", "zstep", "codeplane", "vstep", "fft"):
+        ms, n = L.ocsc_profile_read(g.ctx, cls)
+        kern[cls] = {"avg_us": 1000.0 * ms / n if n else None, "launches": n,
+                     "ms_per_step": ms / args.steps}
+    L.ocsc_profile_enable(g.ctx, [])
+
+    Pf = wl.pad_h * (wl.pad_w // 2 + 1)
+    per_launch = dstep_bytes_per_launch(wl.K, Pf, 4)
+    avg_s = kern["dstep"]["avg_us"] * 1e-6
+    achieved = per_launch / avg_s / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as fh:
+            traffic = json.load(fh).get("dstep_bytes_per_launch")
+
+    value = args.steps / dt
+    out = {
+        "metric": METRIC, "value": value, "unit": "images/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (Bernoulli-Gaussian codes * unit-norm Gaussian 11x11 filters + noise)",
+        "config": {"workload": WORKLOAD, "grid": f"{wl.pad_h}x{wl.pad_w}", "content": f"{wl.content_h}x{wl.content_w}",
+                   "K": wl.K, "filter": f"{wl.filt_h}x{wl.filt_w}", "batch": 1, "iters_code": wl.iters_code,
+                   "iters_dict": wl.iters_dict, "lambda": wl.lam, "rho": wl.rho, "form": "plain",
+                   "distinct_images": n_img},
+        "roofline": {"kernel": "k_dict_sweep (D-step, no fold)", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": per_launch,
+                     "avg_launch_us": kern["dstep"]["avg_us"]},
+        "kernels": kern,
+    }
+    del g
+    torch.cuda.synchronize()
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = oracle_baseline(wl, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

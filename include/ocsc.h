@@ -1,0 +1,212 @@
+/*
+ * ocsc.h -- C ABI of libocsc: online convolutional sparse coding (OCSC) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the online CSC problem and Algorithm 3 of Wang, Yao, Kwok
+ * and Ni, "Scalable Online Convolutional Sparse Coding": per sample, the
+ * frequency-domain code update (eq. fcsc_code), the per-frequency history
+ * update (eqs. B_update and C_update) and the dictionary update DictOCSC
+ * (Algorithm 2, eq. sub_d_sol, Proposition 2).
+ *
+ * Conventions shared by every call
+ *   - Sizes: K filters of filt_h x filt_w taps; samples and codes live on a
+ *     pad_h x pad_w grid (P = pad_h * pad_w), both powers of two.  Spectra are
+ *     stored as the non-redundant half, Pf = pad_h * (pad_w/2 + 1) complex
+ *     values per plane (row-major, column index fastest).
+ *   - DFT: unnormalised forward transform, 1/P on the inverse.  Convolution is
+ *     circular on the padded grid; a filter occupies the top-left
+ *     filt_h x filt_w block of its plane.
+ *   - Real type: double for OCSC_FP64 contexts, float for OCSC_FP32 contexts.
+ *     Every "real" buffer below is of that type.
+ *   - Pointers named *_dev are device pointers (hipMalloc'd memory or a torch
+ *     tensor's data_ptr()) on the context's device; the caller owns them and
+ *     must keep them alive until the call's work on the context stream has
+ *     completed.  The library owns all learner state and workspace.
+ *   - Asynchrony: calls enqueue work on the context stream and return without
+ *     waiting, except ocsc_objective (copies B doubles to the host and waits),
+ *     ocsc_sync, and the state getters/setters (which wait for their copy).
+ *   - Errors: every call returns an ocsc_status.  Arguments and call order are
+ *     validated before any device work, so validation errors never leave the
+ *     context half-updated.  No C++ exception crosses the ABI.  The message of
+ *     the last failure is available from ocsc_last_error.
+ *   - Threads: a context must be used by one host thread at a time; distinct
+ *     contexts are independent.
+ */
+#ifndef OCSC_H_
+#define OCSC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ocsc_ctx ocsc_ctx;
+
+typedef enum {
+  OCSC_OK = 0,
+  OCSC_E_INVALID_ARG = -1, /* a size, pointer or hyper-parameter is out of range */
+  OCSC_E_STATE = -2,       /* calls made out of order (see each call) */
+  OCSC_E_OOM = -3,         /* device allocation failed */
+  OCSC_E_HIP = -4,         /* a HIP runtime call failed; text in ocsc_last_error */
+  OCSC_E_NUMERIC = -5,     /* non-finite input or result */
+  OCSC_E_UNSUPPORTED = -6  /* valid request this build has no kernel for */
+} ocsc_status;
+
+typedef enum {
+  OCSC_FP64 = 0, /* all arithmetic in double */
+  OCSC_FP32 = 1  /* all arithmetic in float; objective reductions in double */
+} ocsc_precision;
+
+typedef struct {
+  int32_t struct_size; /* = sizeof(ocsc_opts) */
+  int32_t iters_code;  /* code-ADMM iterations per sample (J_z), >= 1; default 10 */
+  int32_t iters_dict;  /* DictOCSC iterations per update (J of Algorithm 2), >= 1; default 10 */
+  int32_t max_batch;   /* largest B accepted by ocsc_code_update; default 1 */
+  int32_t precision;   /* ocsc_precision; default OCSC_FP64 */
+  int32_t flags;       /* OCSC_FLAG_* bits; default 0 */
+  double rho_dict;     /* dictionary-ADMM penalty rho_d; <= 0 selects rho * P (eq. sub_d_sol) */
+  void* stream;        /* hipStream_t to enqueue on; NULL is the default (null) stream */
+} ocsc_opts;
+
+/* opts.flags: create a private non-blocking stream and ignore opts.stream. */
+#define OCSC_FLAG_OWN_STREAM 1
+
+/* Fill *opts with the defaults listed above. */
+void ocsc_default_opts(ocsc_opts* opts);
+
+/*
+ * Create a learner (Algorithm 3, initialisation): history G = 0 and
+ * C_p = I / rho_d at every frequency, t = 0, dictionary spectrum zero until
+ * ocsc_set_dictionary.
+ *   K >= 1; 1 <= filt_h <= pad_h; 1 <= filt_w <= pad_w; pad_h, pad_w powers of
+ *   two in [32, 128]; lambda >= 0 (the l1 weight beta of eq. csc); rho > 0 (the
+ *   code-ADMM penalty).  opts may be NULL (defaults).  The device is the current
+ *   HIP device at the time of the call.
+ * Errors: OCSC_E_INVALID_ARG (nothing allocated, *out untouched),
+ *   OCSC_E_UNSUPPORTED (size/precision without a kernel), OCSC_E_OOM, OCSC_E_HIP.
+ */
+int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_w,
+              double lambda, double rho, const ocsc_opts* opts);
+
+/* Free the context and all library-owned device memory.  NULL is accepted. */
+int ocsc_destroy(ocsc_ctx* ctx);
+
+/*
+ * Set the dictionary from spatial filters D_dev: real [K][filt_h][filt_w].
+ * The spectrum F(zero-pad(D_k)) replaces the current dictionary (Algorithm 3,
+ * initialisation with D_0).  History and t are unchanged.
+ */
+int ocsc_set_dictionary(ocsc_ctx* ctx, const void* D_dev);
+
+/*
+ * Export the dictionary: D_dev_out real [K][filt_h][filt_w] receives the crop of
+ * the real inverse DFT of the current dictionary spectrum (Algorithm 3, last
+ * loop: D(:,k) = H(F^-1 D~(:,k))).
+ */
+int ocsc_get_dictionary(ocsc_ctx* ctx, void* D_dev_out);
+
+/*
+ * Code B samples against the current dictionary (eq. fcsc_code by scaled
+ * ADMM, iters_code iterations from U = W = 0 per sample; threshold lambda/rho).
+ *   x_dev: real [B][pad_h][pad_w] samples on the padded grid.
+ *   codes_dev_out: real [B][K][pad_h][pad_w] receives the sparse codes U, or NULL.
+ * The last Z-step spectra and the sample spectra are kept for the next
+ * ocsc_history_accumulate; codes of an earlier call that were not yet
+ * accumulated are discarded.  1 <= B <= max_batch.
+ */
+int ocsc_code_update(ocsc_ctx* ctx, const void* x_dev, int B, void* codes_dev_out);
+
+/*
+ * Fold the spectra kept by the last ocsc_code_update into the history, in
+ * sample order (eqs. B_update and C_update, unnormalised):
+ *   G_p += conj(z_p) x_p;  C_p <- C_p - (C_p u)(C_p u)^H / (1 + u^H C_p u), u = conj(z_p),
+ * so that C_p = (sum_i conj(z_ip) z_ip^T + rho_d I)^-1; t += B.
+ * OCSC_E_STATE if there are no pending codes (none coded, or already folded).
+ * The fold may be deferred into the first sweep of the next ocsc_dict_update;
+ * every observable result is the same.
+ */
+int ocsc_history_accumulate(ocsc_ctx* ctx);
+
+/*
+ * DictOCSC (Algorithm 2): iters_dict ADMM iterations from V = 0, Theta = 0 of
+ *   d_p = C_p (G_p + rho_d (F(V)_p - Theta_p))            (eq. sub_d_sol, column form)
+ *   V_k = alpha_k / max(||alpha_k||, 1), alpha_k = crop(Re F^-1(d_k + Theta_k))  (Prop. 2)
+ *   Theta += d - F(V)
+ * The last d becomes the dictionary spectrum.  OCSC_E_STATE if t = 0.
+ */
+int ocsc_dict_update(ocsc_ctx* ctx);
+
+/*
+ * Objective of eq. csc per sample against the current dictionary:
+ *   out_host[b] = 1/2 ||x_b - sum_k F^-1(D~_k F(U_bk))||^2 + lambda ||U_b||_1,
+ * evaluated through Parseval's theorem with double-precision accumulation.
+ *   x_dev: real [B][pad_h][pad_w]; codes_dev: real [B][K][pad_h][pad_w];
+ *   out_host: B doubles in host memory.  Waits for completion.
+ * May overwrite the library's code workspace, but not the spectra kept for
+ * ocsc_history_accumulate.  1 <= B <= max_batch.
+ */
+int ocsc_objective(ocsc_ctx* ctx, const void* x_dev, const void* codes_dev, int B,
+                   double* out_host);
+
+/* Wait until all work enqueued on the context stream has finished. */
+int ocsc_sync(ocsc_ctx* ctx);
+
+/* Text of the last failure on this context (or of the last failed ocsc_init
+ * when ctx is NULL).  Valid until the next call on the same context. */
+const char* ocsc_last_error(const ocsc_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * State access, for checkpoints and for checking intermediate results.
+ * Complex values are interleaved (re, im) pairs of the context's real type.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  OCSC_STATE_DICT_HAT = 0, /* complex [K][Pf]: dictionary spectrum D~ */
+  OCSC_STATE_G = 1,        /* complex [K][Pf]: history b^p (unnormalised sum) */
+  OCSC_STATE_CINV = 2,     /* real [Pf][K][K]: C_p = (H_p + rho_d I)^-1 packed as
+                              R[i][j] = Re C_ij (j >= i), R[j][i] = Im C_ij (j > i) */
+  OCSC_STATE_V = 3,        /* real [K][filt_h][filt_w]: last feasible V of DictOCSC */
+  OCSC_STATE_THETA = 4,    /* complex [K][Pf]: last scaled dual Theta of DictOCSC */
+  OCSC_STATE_ZHAT = 5,     /* complex [max_batch][K][Pf]: last Z-step spectra (read only) */
+  OCSC_STATE_XHAT = 6      /* complex [max_batch][Pf]: last sample spectra (read only) */
+} ocsc_state;
+
+/* Size in bytes of one state item. */
+int ocsc_state_bytes(const ocsc_ctx* ctx, int which, int64_t* bytes_out);
+/* Copy a state item to dst_dev (device memory of ocsc_state_bytes bytes).
+ * Pending history folds are applied first.  Waits for the copy. */
+int ocsc_get_state(ocsc_ctx* ctx, int which, void* dst_dev);
+/* Overwrite a state item from src_dev.  DICT_HAT, G, CINV, V and THETA only
+ * (OCSC_E_INVALID_ARG otherwise).  Pending codes are discarded.  Waits. */
+int ocsc_set_state(ocsc_ctx* ctx, int which, const void* src_dev);
+/* Number of samples folded into the history so far (t of Algorithm 3). */
+int ocsc_get_count(const ocsc_ctx* ctx, int64_t* t_out);
+/* Overwrite t (used when a checkpoint is restored). */
+int ocsc_set_count(ocsc_ctx* ctx, int64_t t);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing.  When enabled, the library brackets each launch with HIP
+ * events on the context stream and accumulates per-kernel-class durations.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  OCSC_KC_FFT = 0,       /* sample / dictionary / objective plane transforms */
+  OCSC_KC_ZSTEP = 1,     /* code Z-step, one launch per code iteration */
+  OCSC_KC_CODEPLANE = 2, /* fused inverse DFT, soft threshold, dual, forward DFT */
+  OCSC_KC_HISTORY = 3,   /* history fold, alone or fused with the first D-step sweep */
+  OCSC_KC_DSTEP = 4,     /* D-step sweep over C without a fold */
+  OCSC_KC_VSTEP = 5,     /* V-step, Theta update and next D-step right-hand side */
+  OCSC_KC_OTHER = 6,
+  OCSC_KC_COUNT = 7
+} ocsc_kernel_class;
+
+/* Time the kernel classes whose bit (1u << class) is set in class_mask; 0
+ * disables timing.  Every call clears the accumulators. */
+int ocsc_profile_enable(ocsc_ctx* ctx, unsigned class_mask);
+/* Total milliseconds and launch count of one kernel class since enabling.
+ * Waits for outstanding timed launches. */
+int ocsc_profile_read(ocsc_ctx* ctx, int kernel_class, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCSC_H_ */

@@ -1,0 +1,682 @@
+// ocsc.hip -- host runtime and C ABI of libocsc (see include/ocsc.h).
+//
+// One context owns the learner state of Algorithm 3 on one device and a HIP
+// stream; every call validates its arguments on the host, then enqueues the
+// kernels of kernels.hpp on that stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ocsc.h"
+#include "kernels.hpp"
+
+using namespace ocsc;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct ProfEntry {
+  int cls;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct ocsc_ctx {
+  // problem
+  int K = 0, Mh = 0, Mw = 0, Ph = 0, Pw = 0, Wc = 0, Pf = 0, P = 0;
+  double lam = 0, rho = 0, rho_d = 0;
+  int Jz = 10, Jd = 10, maxB = 1, prec = OCSC_FP64;
+  size_t sr = 8;   // bytes per real
+  int nvb = 0;     // V-step column blocks
+  int fpb = 1;     // frequencies per workgroup in the D-step sweep
+  size_t sweep_smem = 0, vapply_smem = 0;
+  // runtime
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // device state (typed by prec)
+  void *xh = nullptr, *Dh = nullptr, *gam = nullptr, *gam2 = nullptr, *S = nullptr, *Zh = nullptr,
+       *W = nullptr, *G = nullptr, *Cm = nullptr, *d = nullptr, *Th = nullptr, *rhs = nullptr,
+       *V = nullptr, *apart = nullptr, *twH = nullptr, *twW = nullptr, *xh_obj = nullptr;
+  double *obj_part = nullptr, *obj_out = nullptr;
+  int obj_nr = 0, obj_nl = 0;
+  // host-side bookkeeping
+  int64_t t = 0;
+  int pending_B = 0;    // coded samples not yet accumulated
+  int fold_B = 0;       // accumulated samples whose fold is still deferred
+  unsigned sweep_count = 0;
+  bool serpentine = true;
+  std::string err;
+  // profiling
+  unsigned prof_mask = 0;
+  std::vector<ProfEntry> prof_live;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[OCSC_KC_COUNT] = {0};
+  int64_t prof_n[OCSC_KC_COUNT] = {0};
+};
+
+namespace {
+
+int fail(ocsc_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_init_error = msg;
+  return code;
+}
+
+#define HIPX(ctx, call)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, OCSC_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+#define LAUNCHED(ctx)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, OCSC_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_));  \
+  } while (0)
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------- profiling
+hipEvent_t ev_get(ocsc_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int prof_collect(ocsc_ctx* c) {
+  for (auto& pe : c->prof_live) {
+    HIPX(c, hipEventSynchronize(pe.b));
+    float ms = 0;
+    HIPX(c, hipEventElapsedTime(&ms, pe.a, pe.b));
+    c->prof_ms[pe.cls] += ms;
+    c->prof_n[pe.cls] += 1;
+    c->ev_pool.push_back(pe.a);
+    c->ev_pool.push_back(pe.b);
+  }
+  c->prof_live.clear();
+  return OCSC_OK;
+}
+
+struct ProfScope {
+  ocsc_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr;
+  ProfScope(ocsc_ctx* c_, int cls_) : c(c_), cls(cls_) {
+    if (c->prof_mask & (1u << cls)) {
+      a = ev_get(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = ev_get(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->prof_live.push_back({cls, a, b});
+    if (c->prof_live.size() >= 4096) prof_collect(c);
+  }
+};
+
+// ---------------------------------------------------------------- dispatch
+constexpr int plane_threads(int ph, int pw) { return ph * pw >= 128 * 128 ? 512 : 256; }
+
+#define OCSC_SIZE_CASES(X) \
+  X(32, 32) X(32, 64) X(32, 128) X(64, 32) X(64, 64) X(64, 128) X(128, 32) X(128, 64) X(128, 128)
+
+template <typename T>
+int launch_rfft2(ocsc_ctx* c, const T* src, int sh, int sw, long sstride, cx<T>* dst, long dstride,
+                 int nplanes) {
+  if (nplanes <= 0) return OCSC_OK;
+  ProfScope ps(c, OCSC_KC_FFT);
+  const cx<T>* tH = (const cx<T>*)c->twH;
+  const cx<T>* tW = (const cx<T>*)c->twW;
+  switch (c->Ph * 1000 + c->Pw) {
+#define X(A, B)                                                                                   \
+  case A * 1000 + B:                                                                              \
+    hipLaunchKernelGGL((k_rfft2<T, A, B, plane_threads(A, B)>), dim3(nplanes), dim3(plane_threads(A, B)), 0, \
+                       c->stream, src, sh, sw, sstride, dst, dstride, tH, tW);                    \
+    break;
+    OCSC_SIZE_CASES(X)
+#undef X
+    default:
+      return fail(c, OCSC_E_UNSUPPORTED, "no transform kernel for this grid");
+  }
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
+template <typename T>
+int launch_irfft2_crop(ocsc_ctx* c, const cx<T>* src, long sstride, T* dst, int oh, int ow, long dstride,
+                       int nplanes) {
+  ProfScope ps(c, OCSC_KC_FFT);
+  const cx<T>* tH = (const cx<T>*)c->twH;
+  const cx<T>* tW = (const cx<T>*)c->twW;
+  switch (c->Ph * 1000 + c->Pw) {
+#define X(A, B)                                                                                         \
+  case A * 1000 + B:                                                                                    \
+    hipLaunchKernelGGL((k_irfft2_crop<T, A, B, plane_threads(A, B)>), dim3(nplanes), dim3(plane_threads(A, B)), 0, \
+                       c->stream, src, sstride, dst, oh, ow, dstride, tH, tW);                          \
+    break;
+    OCSC_SIZE_CASES(X)
+#undef X
+    default:
+      return fail(c, OCSC_E_UNSUPPORTED, "no transform kernel for this grid");
+  }
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
+template <typename T>
+int launch_code_plane(ocsc_ctx* c, int nplanes, T* Uout, int first, int last) {
+  ProfScope ps(c, OCSC_KC_CODEPLANE);
+  const cx<T>* tH = (const cx<T>*)c->twH;
+  const cx<T>* tW = (const cx<T>*)c->twW;
+  const T kappa = (T)(c->lam / c->rho);
+  switch (c->Ph * 1000 + c->Pw) {
+#define X(A, B)                                                                                        \
+  case A * 1000 + B:                                                                                   \
+    hipLaunchKernelGGL((k_code_plane<T, A, B, plane_threads(A, B)>), dim3(nplanes), dim3(plane_threads(A, B)), 0, \
+                       c->stream, (const cx<T>*)c->Zh, (T*)c->W, (cx<T>*)c->S, Uout, tH, tW, kappa,  \
+                       first, last);                                                                   \
+    break;
+    OCSC_SIZE_CASES(X)
+#undef X
+    default:
+      return fail(c, OCSC_E_UNSUPPORTED, "no code-plane kernel for this grid");
+  }
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
+template <typename T>
+int launch_zstep(ocsc_ctx* c, int B, int first) {
+  ProfScope ps(c, OCSC_KC_ZSTEP);
+  dim3 grid((c->Pf + 63) / 64, B);
+  const cx<T>* Dh = (const cx<T>*)c->Dh;
+  const T* gam = (const T*)c->gam;
+  const cx<T>* xh = (const cx<T>*)c->xh;
+  const cx<T>* S = (const cx<T>*)c->S;
+  cx<T>* Zh = (cx<T>*)c->Zh;
+  const int K = c->K, Pf = c->Pf;
+  if (K <= 16)
+    hipLaunchKernelGGL((k_code_zstep<T, 4, 4>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+  else if (K <= 32)
+    hipLaunchKernelGGL((k_code_zstep<T, 4, 8>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+  else if (K <= 64)
+    hipLaunchKernelGGL((k_code_zstep<T, 4, 16>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+  else if (K <= 128 && sizeof(T) == 4)
+    hipLaunchKernelGGL((k_code_zstep<T, 4, 32>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+  else if (K <= 128)
+    hipLaunchKernelGGL((k_code_zstep<T, 8, 16>), grid, dim3(512), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+  else if (K <= 256)
+    hipLaunchKernelGGL((k_code_zstep<T, 16, 16>), grid, dim3(1024), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+  else
+    return fail(c, OCSC_E_UNSUPPORTED, "code Z-step supports K <= 256");
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
+template <typename T>
+int launch_gamma(ocsc_ctx* c) {
+  ProfScope ps(c, OCSC_KC_OTHER);
+  hipLaunchKernelGGL((k_gamma<T>), dim3((c->Pf + 255) / 256), dim3(256), 0, c->stream, (const cx<T>*)c->Dh,
+                     (T*)c->gam, (T)c->rho, c->K, c->Pf);
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
+// One D-step sweep; nfold > 0 folds the kept spectra of nfold samples first.
+template <typename T>
+int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* dout, void* gam_out, int cls) {
+  ProfScope ps(c, cls);
+  const int nb = (c->Pf + c->fpb - 1) / c->fpb;
+  const int reverse = c->serpentine ? (int)(c->sweep_count & 1u) : 0;
+  c->sweep_count++;
+  hipLaunchKernelGGL((k_dict_sweep<T>), dim3(nb), dim3(256), c->sweep_smem, c->stream, (T*)c->Cm,
+                     (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh, nfold,
+                     (cx<T>*)dout, (T*)gam_out, (T)c->rho, c->K, c->Pf, c->fpb, reverse);
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
+template <typename T>
+int launch_vstep(ocsc_ctx* c, int first) {
+  ProfScope ps(c, OCSC_KC_VSTEP);
+  dim3 grid(c->nvb, c->K);
+  hipLaunchKernelGGL((k_vstep_alpha<T>), grid, dim3(256), 0, c->stream, (const cx<T>*)c->d,
+                     (const cx<T>*)c->Th, (T*)c->apart, (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph,
+                     c->Pw, c->Mh, c->Mw, first);
+  LAUNCHED(c);
+  hipLaunchKernelGGL((k_vstep_apply<T>), grid, dim3(256), c->vapply_smem, c->stream, (const cx<T>*)c->d,
+                     (cx<T>*)c->Th, (const cx<T>*)c->G, (cx<T>*)c->rhs, (const T*)c->apart, (T*)c->V,
+                     (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph, c->Pw, c->Mh, c->Mw, (T)c->rho_d,
+                     first);
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
+// Apply a deferred history fold on its own (no D-step).
+template <typename T>
+int flush_fold(ocsc_ctx* c) {
+  if (c->fold_B == 0) return OCSC_OK;
+  int rc = launch_sweep<T>(c, c->fold_B, nullptr, nullptr, nullptr, OCSC_KC_HISTORY);
+  if (rc) return rc;
+  c->fold_B = 0;
+  return OCSC_OK;
+}
+
+// ---------------------------------------------------------------- calls by type
+template <typename T>
+int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes) {
+  int rc = flush_fold<T>(c);
+  if (rc) return rc;
+  rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh, c->Pf, B);
+  if (rc) return rc;
+  for (int j = 0; j < c->Jz; ++j) {
+    rc = launch_zstep<T>(c, B, j == 0);
+    if (rc) return rc;
+    rc = launch_code_plane<T>(c, B * c->K, (T*)codes, j == 0, j == c->Jz - 1);
+    if (rc) return rc;
+  }
+  c->pending_B = B;
+  return OCSC_OK;
+}
+
+template <typename T>
+int dict_update_t(ocsc_ctx* c) {
+  for (int tau = 0; tau < c->Jd; ++tau) {
+    const bool last = tau == c->Jd - 1;
+    int rc;
+    if (tau == 0) {
+      rc = launch_sweep<T>(c, c->fold_B, c->G, c->d, last ? c->gam2 : nullptr,
+                           c->fold_B ? OCSC_KC_HISTORY : OCSC_KC_DSTEP);
+      c->fold_B = 0;
+    } else {
+      rc = launch_sweep<T>(c, 0, c->rhs, c->d, last ? c->gam2 : nullptr, OCSC_KC_DSTEP);
+    }
+    if (rc) return rc;
+    rc = launch_vstep<T>(c, tau == 0);
+    if (rc) return rc;
+  }
+  std::swap(c->Dh, c->d);
+  std::swap(c->gam, c->gam2);
+  return OCSC_OK;
+}
+
+template <typename T>
+int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {
+  int rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh_obj, c->Pf, B);
+  if (rc) return rc;
+  rc = launch_rfft2<T>(c, (const T*)codes, c->Ph, c->Pw, c->P, (cx<T>*)c->S, c->Pf, B * c->K);
+  if (rc) return rc;
+  {
+    ProfScope ps(c, OCSC_KC_OTHER);
+    hipLaunchKernelGGL((k_obj_resid<T>), dim3(c->obj_nr, B), dim3(256), 0, c->stream, (const cx<T>*)c->xh_obj,
+                       (const cx<T>*)c->Dh, (const cx<T>*)c->S, c->obj_part, c->K, c->Pw, c->Pf);
+    LAUNCHED(c);
+    double* lpart = c->obj_part + (size_t)c->maxB * c->obj_nr;
+    hipLaunchKernelGGL((k_abs_sum<T>), dim3(c->obj_nl, B), dim3(256), 0, c->stream, (const T*)codes, lpart,
+                       (long)c->K * c->P);
+    LAUNCHED(c);
+    hipLaunchKernelGGL(k_obj_final, dim3(B), dim3(256), 0, c->stream, c->obj_part, c->obj_nr, lpart, c->obj_nl,
+                       c->obj_out, 1.0 / c->P, c->lam);
+    LAUNCHED(c);
+  }
+  HIPX(c, hipMemcpyAsync(out, c->obj_out, sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
+  HIPX(c, hipStreamSynchronize(c->stream));
+  for (int b = 0; b < B; ++b)
+    if (!std::isfinite(out[b])) return fail(c, OCSC_E_NUMERIC, "objective is not finite");
+  return OCSC_OK;
+}
+
+template <typename T>
+int init_state_t(ocsc_ctx* c) {
+  const size_t n = (size_t)c->Pf * c->K * c->K;
+  hipLaunchKernelGGL((k_c_init<T>), dim3(2048), dim3(256), 0, c->stream, (T*)c->Cm, c->K, c->Pf,
+                     (T)(1.0 / c->rho_d));
+  LAUNCHED(c);
+  (void)n;
+  return launch_gamma<T>(c);
+}
+
+void free_all(ocsc_ctx* c) {
+  void** bufs[] = {&c->xh, &c->Dh, &c->gam, &c->gam2, &c->S, &c->Zh, &c->W, &c->G, &c->Cm, &c->d,
+                   &c->Th, &c->rhs, &c->V, &c->apart, &c->twH, &c->twW, &c->xh_obj};
+  for (void** b : bufs)
+    if (*b) {
+      (void)hipFree(*b);
+      *b = nullptr;
+    }
+  if (c->obj_part) (void)hipFree(c->obj_part);
+  if (c->obj_out) (void)hipFree(c->obj_out);
+  c->obj_part = c->obj_out = nullptr;
+  for (auto& pe : c->prof_live) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  c->prof_live.clear();
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
+}
+
+int state_bytes(const ocsc_ctx* c, int which, size_t* out) {
+  const size_t sc = 2 * c->sr;
+  switch (which) {
+    case OCSC_STATE_DICT_HAT:
+    case OCSC_STATE_G:
+    case OCSC_STATE_THETA: *out = (size_t)c->K * c->Pf * sc; return OCSC_OK;
+    case OCSC_STATE_CINV: *out = (size_t)c->Pf * c->K * c->K * c->sr; return OCSC_OK;
+    case OCSC_STATE_V: *out = (size_t)c->K * c->Mh * c->Mw * c->sr; return OCSC_OK;
+    case OCSC_STATE_ZHAT: *out = (size_t)c->maxB * c->K * c->Pf * sc; return OCSC_OK;
+    case OCSC_STATE_XHAT: *out = (size_t)c->maxB * c->Pf * sc; return OCSC_OK;
+    default: return OCSC_E_INVALID_ARG;
+  }
+}
+
+void* state_ptr(ocsc_ctx* c, int which) {
+  switch (which) {
+    case OCSC_STATE_DICT_HAT: return c->Dh;
+    case OCSC_STATE_G: return c->G;
+    case OCSC_STATE_CINV: return c->Cm;
+    case OCSC_STATE_V: return c->V;
+    case OCSC_STATE_THETA: return c->Th;
+    case OCSC_STATE_ZHAT: return c->Zh;
+    case OCSC_STATE_XHAT: return c->xh;
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+void ocsc_default_opts(ocsc_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(ocsc_opts);
+  o->iters_code = 10;
+  o->iters_dict = 10;
+  o->max_batch = 1;
+  o->precision = OCSC_FP64;
+  o->flags = 0;
+  o->rho_dict = 0.0;
+  o->stream = nullptr;
+}
+
+int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_w, double lambda, double rho,
+              const ocsc_opts* opts) {
+  g_init_error.clear();
+  if (!out) return fail(nullptr, OCSC_E_INVALID_ARG, "out is NULL");
+  ocsc_opts o;
+  ocsc_default_opts(&o);
+  if (opts) {
+    if (opts->struct_size != (int32_t)sizeof(ocsc_opts))
+      return fail(nullptr, OCSC_E_INVALID_ARG, "opts->struct_size does not match this library");
+    o = *opts;
+  }
+  if (K < 1) return fail(nullptr, OCSC_E_INVALID_ARG, "K must be >= 1");
+  if (!pow2_in(pad_h, 32, 1024) || !pow2_in(pad_w, 32, 1024))
+    return fail(nullptr, OCSC_E_INVALID_ARG, "pad_h and pad_w must be powers of two in [32, 1024]");
+  if (filt_h < 1 || filt_w < 1 || filt_h > pad_h || filt_w > pad_w)
+    return fail(nullptr, OCSC_E_INVALID_ARG, "need 1 <= filt <= pad");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(nullptr, OCSC_E_INVALID_ARG, "lambda must be >= 0");
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(nullptr, OCSC_E_INVALID_ARG, "rho must be > 0");
+  if (o.iters_code < 1 || o.iters_dict < 1) return fail(nullptr, OCSC_E_INVALID_ARG, "iteration counts must be >= 1");
+  if (o.max_batch < 1 || o.max_batch > 65535) return fail(nullptr, OCSC_E_INVALID_ARG, "max_batch must be in [1, 65535]");
+  if (o.precision != OCSC_FP64 && o.precision != OCSC_FP32)
+    return fail(nullptr, OCSC_E_INVALID_ARG, "unknown precision");
+  if (o.flags & ~OCSC_FLAG_OWN_STREAM) return fail(nullptr, OCSC_E_INVALID_ARG, "unknown bits in opts->flags");
+  if (!std::isfinite(o.rho_dict)) return fail(nullptr, OCSC_E_INVALID_ARG, "rho_dict must be finite");
+  if (pad_h > 128 || pad_w > 128)
+    return fail(nullptr, OCSC_E_UNSUPPORTED, "this build has plane kernels for grids up to 128 x 128");
+  const size_t sr = o.precision == OCSC_FP64 ? 8 : 4;
+  // D-step sweep: C_p of K x (K+1) reals must fit in LDS
+  int fpb = 1;
+  while (fpb < 16 && 256 / (fpb * 2) >= K) fpb *= 2;
+  auto sweep_bytes = [&](int f) {
+    return (((size_t)f * K * (K + 1) * sr + 15) & ~(size_t)15) + (size_t)f * 7 * K * 2 * sr;
+  };
+  const size_t max_lds = 160 * 1024 - 1024;
+  if (sweep_bytes(1) > max_lds)
+    return fail(nullptr, OCSC_E_UNSUPPORTED, "K too large for the LDS-resident D-step of this precision");
+  while (fpb > 1 && sweep_bytes(fpb) > 64 * 1024) fpb /= 2;
+
+  ocsc_ctx* c = new (std::nothrow) ocsc_ctx();
+  if (!c) return fail(nullptr, OCSC_E_OOM, "host allocation failed");
+  c->K = K; c->Mh = filt_h; c->Mw = filt_w; c->Ph = pad_h; c->Pw = pad_w;
+  c->Wc = pad_w / 2 + 1; c->Pf = pad_h * c->Wc; c->P = pad_h * pad_w;
+  c->lam = lambda; c->rho = rho;
+  c->rho_d = o.rho_dict > 0 ? o.rho_dict : rho * c->P;
+  c->Jz = o.iters_code; c->Jd = o.iters_dict; c->maxB = o.max_batch; c->prec = o.precision;
+  c->sr = sr;
+  c->nvb = (c->Wc + VB - 1) / VB;
+  c->fpb = fpb;
+  c->sweep_smem = sweep_bytes(fpb);
+  c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * VB * 2 * sr;
+  if (const char* s = std::getenv("OCSC_SERPENTINE")) c->serpentine = std::atoi(s) != 0;
+
+  auto bail = [&](int code, const std::string& m) {
+    g_init_error = m;
+    free_all(c);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return code;
+  };
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (!(o.flags & OCSC_FLAG_OWN_STREAM)) {
+    c->stream = (hipStream_t)o.stream;
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    c->own_stream = true;
+  }
+  if (c->sweep_smem > 64 * 1024) {
+    if (sr == 8)
+      e = hipFuncSetAttribute((const void*)k_dict_sweep<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)c->sweep_smem);
+    else
+      e = hipFuncSetAttribute((const void*)k_dict_sweep<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)c->sweep_smem);
+    if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+  }
+
+  const size_t sc = 2 * sr, K_ = K, Pf = c->Pf, B = c->maxB;
+  c->obj_nr = (c->Pf + 255) / 256;
+  c->obj_nl = 64;
+  struct { void** p; size_t n; } allocs[] = {
+      {&c->xh, B * Pf * sc},        {&c->Dh, K_ * Pf * sc},          {&c->gam, Pf * sr},
+      {&c->gam2, Pf * sr},          {&c->S, B * K_ * Pf * sc},       {&c->Zh, B * K_ * Pf * sc},
+      {&c->W, B * K_ * c->P * sr},  {&c->G, K_ * Pf * sc},           {&c->Cm, Pf * K_ * K_ * sr},
+      {&c->d, K_ * Pf * sc},        {&c->Th, K_ * Pf * sc},          {&c->rhs, K_ * Pf * sc},
+      {&c->V, K_ * filt_h * filt_w * sr},
+      {&c->apart, K_ * c->nvb * filt_h * filt_w * sr},
+      {&c->twH, (size_t)pad_h * sc}, {&c->twW, (size_t)pad_w * sc}, {&c->xh_obj, B * Pf * sc},
+      {(void**)&c->obj_part, B * (size_t)(c->obj_nr + c->obj_nl) * sizeof(double)},
+      {(void**)&c->obj_out, B * sizeof(double)}};
+  for (auto& a : allocs) {
+    e = hipMalloc(a.p, a.n);
+    if (e != hipSuccess) return bail(OCSC_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    e = hipMemsetAsync(*a.p, 0, a.n, c->stream);
+    if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+  }
+  // twiddle tables e^{-2 pi i j / N}, computed in double
+  {
+    std::vector<double> h(2 * (size_t)std::max(pad_h, pad_w));
+    auto upload = [&](void* dst, int N) -> hipError_t {
+      for (int j = 0; j < N; ++j) {
+        const double a = 2.0 * M_PI * (double)j / (double)N;
+        h[2 * j] = std::cos(a);
+        h[2 * j + 1] = -std::sin(a);
+      }
+      if (sr == 8) return hipMemcpy(dst, h.data(), (size_t)N * 16, hipMemcpyHostToDevice);
+      std::vector<float> f(2 * (size_t)N);
+      for (int j = 0; j < 2 * N; ++j) f[j] = (float)h[j];
+      return hipMemcpy(dst, f.data(), (size_t)N * 8, hipMemcpyHostToDevice);
+    };
+    e = upload(c->twH, pad_h);
+    if (e == hipSuccess) e = upload(c->twW, pad_w);
+    if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("twiddle upload: ") + hipGetErrorString(e));
+  }
+  int rc = sr == 8 ? init_state_t<double>(c) : init_state_t<float>(c);
+  if (rc) return bail(rc, c->err);
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("init sync: ") + hipGetErrorString(e));
+  *out = c;
+  return OCSC_OK;
+}
+
+int ocsc_destroy(ocsc_ctx* c) {
+  if (!c) return OCSC_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return OCSC_OK;
+}
+
+int ocsc_set_dictionary(ocsc_ctx* c, const void* D) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!D) return fail(c, OCSC_E_INVALID_ARG, "D_dev is NULL");
+  const long fs = (long)c->Mh * c->Mw;
+  int rc = c->sr == 8
+               ? launch_rfft2<double>(c, (const double*)D, c->Mh, c->Mw, fs, (cx<double>*)c->Dh, c->Pf, c->K)
+               : launch_rfft2<float>(c, (const float*)D, c->Mh, c->Mw, fs, (cx<float>*)c->Dh, c->Pf, c->K);
+  if (rc) return rc;
+  return c->sr == 8 ? launch_gamma<double>(c) : launch_gamma<float>(c);
+}
+
+int ocsc_get_dictionary(ocsc_ctx* c, void* D) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!D) return fail(c, OCSC_E_INVALID_ARG, "D_dev_out is NULL");
+  const long fs = (long)c->Mh * c->Mw;
+  return c->sr == 8 ? launch_irfft2_crop<double>(c, (const cx<double>*)c->Dh, c->Pf, (double*)D, c->Mh, c->Mw, fs, c->K)
+                    : launch_irfft2_crop<float>(c, (const cx<float>*)c->Dh, c->Pf, (float*)D, c->Mh, c->Mw, fs, c->K);
+}
+
+int ocsc_code_update(ocsc_ctx* c, const void* x, int B, void* codes) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!x) return fail(c, OCSC_E_INVALID_ARG, "x_dev is NULL");
+  if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
+  return c->sr == 8 ? code_update_t<double>(c, x, B, codes) : code_update_t<float>(c, x, B, codes);
+}
+
+int ocsc_history_accumulate(ocsc_ctx* c) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (c->pending_B == 0) return fail(c, OCSC_E_STATE, "no coded samples to accumulate");
+  c->fold_B = c->pending_B;
+  c->t += c->pending_B;
+  c->pending_B = 0;
+  return OCSC_OK;
+}
+
+int ocsc_dict_update(ocsc_ctx* c) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (c->t == 0) return fail(c, OCSC_E_STATE, "dict_update needs at least one accumulated sample");
+  return c->sr == 8 ? dict_update_t<double>(c) : dict_update_t<float>(c);
+}
+
+int ocsc_objective(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!x || !codes || !out) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
+  if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
+  return c->sr == 8 ? objective_t<double>(c, x, codes, B, out) : objective_t<float>(c, x, codes, B, out);
+}
+
+int ocsc_sync(ocsc_ctx* c) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  HIPX(c, hipStreamSynchronize(c->stream));
+  return OCSC_OK;
+}
+
+const char* ocsc_last_error(const ocsc_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+int ocsc_state_bytes(const ocsc_ctx* c, int which, int64_t* out) {
+  if (!c || !out) return OCSC_E_INVALID_ARG;
+  size_t n = 0;
+  if (state_bytes(c, which, &n)) return OCSC_E_INVALID_ARG;
+  *out = (int64_t)n;
+  return OCSC_OK;
+}
+
+int ocsc_get_state(ocsc_ctx* c, int which, void* dst) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  size_t n = 0;
+  if (!dst || state_bytes(c, which, &n)) return fail(c, OCSC_E_INVALID_ARG, "bad state item or NULL dst");
+  if (which == OCSC_STATE_CINV || which == OCSC_STATE_G) {
+    int rc = c->sr == 8 ? flush_fold<double>(c) : flush_fold<float>(c);
+    if (rc) return rc;
+  }
+  HIPX(c, hipMemcpyAsync(dst, state_ptr(c, which), n, hipMemcpyDeviceToDevice, c->stream));
+  HIPX(c, hipStreamSynchronize(c->stream));
+  return OCSC_OK;
+}
+
+int ocsc_set_state(ocsc_ctx* c, int which, const void* src) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  size_t n = 0;
+  if (!src || state_bytes(c, which, &n) || which == OCSC_STATE_ZHAT || which == OCSC_STATE_XHAT)
+    return fail(c, OCSC_E_INVALID_ARG, "bad state item or NULL src");
+  c->pending_B = 0;
+  c->fold_B = 0;
+  HIPX(c, hipMemcpyAsync(state_ptr(c, which), src, n, hipMemcpyDeviceToDevice, c->stream));
+  if (which == OCSC_STATE_DICT_HAT) {
+    int rc = c->sr == 8 ? launch_gamma<double>(c) : launch_gamma<float>(c);
+    if (rc) return rc;
+  }
+  HIPX(c, hipStreamSynchronize(c->stream));
+  return OCSC_OK;
+}
+
+int ocsc_get_count(const ocsc_ctx* c, int64_t* t) {
+  if (!c || !t) return OCSC_E_INVALID_ARG;
+  *t = c->t;
+  return OCSC_OK;
+}
+
+int ocsc_set_count(ocsc_ctx* c, int64_t t) {
+  if (!c || t < 0) return OCSC_E_INVALID_ARG;
+  c->t = t;
+  return OCSC_OK;
+}
+
+int ocsc_profile_enable(ocsc_ctx* c, unsigned mask) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  int rc = prof_collect(c);
+  if (rc) return rc;
+  c->prof_mask = mask & ((1u << OCSC_KC_COUNT) - 1);
+  for (int i = 0; i < OCSC_KC_COUNT; ++i) {
+    c->prof_ms[i] = 0;
+    c->prof_n[i] = 0;
+  }
+  return OCSC_OK;
+}
+
+int ocsc_profile_read(ocsc_ctx* c, int cls, double* ms, int64_t* n) {
+  if (!c || cls < 0 || cls >= OCSC_KC_COUNT || !ms || !n) return OCSC_E_INVALID_ARG;
+  int rc = prof_collect(c);
+  if (rc) return rc;
+  *ms = c->prof_ms[cls];
+  *n = c->prof_n[cls];
+  return OCSC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,314 @@
+"""Python binding of libocsc (ctypes): argument marshalling only.
+
+Every function here has the name and argument order of the C call in
+include/ocsc.h; device buffers are torch tensors (their ``data_ptr()`` is
+passed), the context stream is torch's current stream at ``ocsc_init`` unless
+another is given.  All arithmetic runs in the library's HIP kernels: if the
+built library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libocsc.so")
+
+OCSC_OK = 0
+OCSC_E_INVALID_ARG = -1
+OCSC_E_STATE = -2
+OCSC_E_OOM = -3
+OCSC_E_HIP = -4
+OCSC_E_NUMERIC = -5
+OCSC_E_UNSUPPORTED = -6
+
+OCSC_FP64 = 0
+OCSC_FP32 = 1
+OCSC_FLAG_OWN_STREAM = 1
+
+STATE = {"dict_hat": 0, "G": 1, "cinv": 2, "V": 3, "theta": 4, "zhat": 5, "xhat": 6}
+KERNEL_CLASS = {"fft": 0, "zstep": 1, "codeplane": 2, "history": 3, "dstep": 4, "vstep": 5, "other": 6}
+
+EXPORTS = [
+    "ocsc_default_opts", "ocsc_init", "ocsc_destroy", "ocsc_set_dictionary", "ocsc_get_dictionary",
+    "ocsc_code_update", "ocsc_history_accumulate", "ocsc_dict_update", "ocsc_objective", "ocsc_sync",
+    "ocsc_last_error", "ocsc_state_bytes", "ocsc_get_state", "ocsc_set_state", "ocsc_get_count",
+    "ocsc_set_count", "ocsc_profile_enable", "ocsc_profile_read",
+]
+
+
+class OcscOpts(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_int32),
+        ("iters_code", ctypes.c_int32),
+        ("iters_dict", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("rho_dict", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class OcscError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libocsc status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the built library (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"libocsc is not built ({path} missing); run `python -m paper_1706_06972_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ocsc_default_opts": (None, [ctypes.POINTER(OcscOpts)]),
+        "ocsc_init": (i32, [ctypes.POINTER(vp), i32, i32, i32, i32, i32, dbl, dbl, ctypes.POINTER(OcscOpts)]),
+        "ocsc_destroy": (i32, [vp]),
+        "ocsc_set_dictionary": (i32, [vp, vp]),
+        "ocsc_get_dictionary": (i32, [vp, vp]),
+        "ocsc_code_update": (i32, [vp, vp, i32, vp]),
+        "ocsc_history_accumulate": (i32, [vp]),
+        "ocsc_dict_update": (i32, [vp]),
+        "ocsc_objective": (i32, [vp, vp, vp, i32, ctypes.POINTER(dbl)]),
+        "ocsc_sync": (i32, [vp]),
+        "ocsc_last_error": (ctypes.c_char_p, [vp]),
+        "ocsc_state_bytes": (i32, [vp, i32, ctypes.POINTER(i64)]),
+        "ocsc_get_state": (i32, [vp, i32, vp]),
+        "ocsc_set_state": (i32, [vp, i32, vp]),
+        "ocsc_get_count": (i32, [vp, ctypes.POINTER(i64)]),
+        "ocsc_set_count": (i32, [vp, i64]),
+        "ocsc_profile_enable": (i32, [vp, ctypes.c_uint]),
+        "ocsc_profile_read": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(ctx, rc: int) -> None:
+    if rc != OCSC_OK:
+        msg = load().ocsc_last_error(ctx)
+        raise OcscError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# The C calls, one for one
+# ---------------------------------------------------------------------------
+
+def ocsc_default_opts() -> OcscOpts:
+    o = OcscOpts()
+    load().ocsc_default_opts(ctypes.byref(o))
+    return o
+
+
+def ocsc_init(K, filt_h, filt_w, pad_h, pad_w, lam, rho, *, iters_code=10, iters_dict=10,
+              max_batch=1, precision="f64", rho_dict=0.0, stream=None):
+    """Returns an opaque context handle (c_void_p)."""
+    L = load()
+    o = ocsc_default_opts()
+    o.iters_code, o.iters_dict, o.max_batch = iters_code, iters_dict, max_batch
+    o.precision = {"f64": OCSC_FP64, "f32": OCSC_FP32}[precision]
+    o.rho_dict = float(rho_dict)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    o.stream = stream
+    ctx = ctypes.c_void_p()
+    rc = L.ocsc_init(ctypes.byref(ctx), K, filt_h, filt_w, pad_h, pad_w, float(lam), float(rho), ctypes.byref(o))
+    _check(None, rc)
+    return ctx
+
+
+def ocsc_destroy(ctx) -> None:
+    _check(None, load().ocsc_destroy(ctx))
+
+
+def ocsc_set_dictionary(ctx, D) -> None:
+    _check(ctx, load().ocsc_set_dictionary(ctx, _ptr(D)))
+
+
+def ocsc_get_dictionary(ctx, D_out) -> None:
+    _check(ctx, load().ocsc_get_dictionary(ctx, _ptr(D_out)))
+
+
+def ocsc_code_update(ctx, x, B, codes_out=None) -> None:
+    _check(ctx, load().ocsc_code_update(ctx, _ptr(x), int(B), _ptr(codes_out)))
+
+
+def ocsc_history_accumulate(ctx) -> None:
+    _check(ctx, load().ocsc_history_accumulate(ctx))
+
+
+def ocsc_dict_update(ctx) -> None:
+    _check(ctx, load().ocsc_dict_update(ctx))
+
+
+def ocsc_objective(ctx, x, codes, B):
+    out = (ctypes.c_double * int(B))()
+    _check(ctx, load().ocsc_objective(ctx, _ptr(x), _ptr(codes), int(B), out))
+    return list(out)
+
+
+def ocsc_sync(ctx) -> None:
+    _check(ctx, load().ocsc_sync(ctx))
+
+
+def ocsc_last_error(ctx) -> str:
+    m = load().ocsc_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def ocsc_state_bytes(ctx, which) -> int:
+    n = ctypes.c_int64()
+    _check(ctx, load().ocsc_state_bytes(ctx, STATE.get(which, which), ctypes.byref(n)))
+    return n.value
+
+
+def ocsc_get_state(ctx, which, dst) -> None:
+    _check(ctx, load().ocsc_get_state(ctx, STATE.get(which, which), _ptr(dst)))
+
+
+def ocsc_set_state(ctx, which, src) -> None:
+    _check(ctx, load().ocsc_set_state(ctx, STATE.get(which, which), _ptr(src)))
+
+
+def ocsc_get_count(ctx) -> int:
+    n = ctypes.c_int64()
+    _check(ctx, load().ocsc_get_count(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def ocsc_set_count(ctx, t) -> None:
+    _check(ctx, load().ocsc_set_count(ctx, int(t)))
+
+
+def ocsc_profile_enable(ctx, classes=()) -> None:
+    mask = 0
+    for c in classes:
+        mask |= 1 << KERNEL_CLASS.get(c, c)
+    _check(ctx, load().ocsc_profile_enable(ctx, mask))
+
+
+def ocsc_profile_read(ctx, cls):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(ctx, load().ocsc_profile_read(ctx, KERNEL_CLASS.get(cls, cls), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper: owns a context, allocates output tensors.
+# ---------------------------------------------------------------------------
+
+class OCSC:
+    """A learner on the current CUDA/HIP device (see include/ocsc.h)."""
+
+    def __init__(self, K, filt_h, filt_w, pad_h, pad_w, lam, rho, *, iters_code=10, iters_dict=10,
+                 max_batch=1, precision="f64", rho_dict=0.0, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.K, self.filt, self.shape = K, (filt_h, filt_w), (pad_h, pad_w)
+        self.max_batch = max_batch
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        with torch.cuda.device(self.device):
+            self.ctx = ocsc_init(K, filt_h, filt_w, pad_h, pad_w, lam, rho, iters_code=iters_code,
+                                 iters_dict=iters_dict, max_batch=max_batch, precision=precision,
+                                 rho_dict=rho_dict)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            ocsc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a):
+        t = self.torch.as_tensor(a, dtype=self.dtype, device=self.device)
+        return t.contiguous()
+
+    def set_dictionary(self, D):
+        D = self._dev(D)
+        if tuple(D.shape) != (self.K,) + self.filt:
+            raise ValueError("dictionary must have shape (K, filt_h, filt_w)")
+        ocsc_set_dictionary(self.ctx, D)
+        ocsc_sync(self.ctx)
+
+    def get_dictionary(self):
+        D = self.torch.empty((self.K,) + self.filt, dtype=self.dtype, device=self.device)
+        ocsc_get_dictionary(self.ctx, D)
+        ocsc_sync(self.ctx)
+        return D
+
+    def code_update(self, x, codes=None, want_codes=True):
+        x = self._dev(x)
+        if x.dim() == 2:
+            x = x[None]
+        B = x.shape[0]
+        if tuple(x.shape[1:]) != self.shape:
+            raise ValueError("samples must have shape (B, pad_h, pad_w)")
+        if codes is None and want_codes:
+            codes = self.torch.empty((B, self.K) + self.shape, dtype=self.dtype, device=self.device)
+        ocsc_code_update(self.ctx, x, B, codes)
+        self._x_keep = x
+        return codes
+
+    def history_accumulate(self):
+        ocsc_history_accumulate(self.ctx)
+
+    def dict_update(self):
+        ocsc_dict_update(self.ctx)
+
+    def step(self, x, codes=None, want_codes=True):
+        c = self.code_update(x, codes, want_codes)
+        self.history_accumulate()
+        self.dict_update()
+        return c
+
+    def objective(self, x, codes):
+        x = self._dev(x)
+        if x.dim() == 2:
+            x = x[None]
+        codes = self._dev(codes)
+        if codes.dim() == 3:
+            codes = codes[None]
+        return ocsc_objective(self.ctx, x, codes, x.shape[0])
+
+    def sync(self):
+        ocsc_sync(self.ctx)
+
+    def state(self, which):
+        n = ocsc_state_bytes(self.ctx, which)
+        buf = self.torch.empty(n // self.dtype.itemsize, dtype=self.dtype, device=self.device)
+        ocsc_get_state(self.ctx, which, buf)
+        return buf
+
+    def set_state(self, which, flat):
+        ocsc_set_state(self.ctx, which, self._dev(flat).reshape(-1))
+
+    @property
+    def count(self):
+        return ocsc_get_count(self.ctx)
