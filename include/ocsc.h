@@ -19,7 +19,7 @@
  *   - Real type: double for OCSC_FP64 contexts, float for OCSC_FP32 contexts.
  *     Every "real" buffer below is of that type.
  *   - Pointers named *_dev are device pointers (hipMalloc'd memory or a torch
- *     tensor's data_ptr()) on the context's device; the caller owns them and
+ *     tensor's data_ptr()), 16-byte aligned, on the context's device; the caller owns them and
  *     must keep them alive until the call's work on the context stream has
  *     completed.  The library owns all learner state and workspace.
  *   - Asynchrony: calls enqueue work on the context stream and return without

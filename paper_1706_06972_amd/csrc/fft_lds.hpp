@@ -97,8 +97,9 @@ template <> struct Plan<128> { static constexpr int R1 = 16, R2 = 8; };
 // One Stockham stage of radix R on NLINES lines of length N in LDS.
 // Element n of line l is buf[l * LSTR + n * ESTR].  L is the product of the
 // radices of earlier stages.  tab[e * TS] = e^{-2 pi i e / N} for 0 <= e < N.
-// LINE_FAST: consecutive threads take consecutive lines (column sweeps);
-// otherwise consecutive butterflies of one line (row sweeps).
+// LINE_FAST: consecutive threads take consecutive lines; otherwise
+// consecutive butterflies of one line.  Both sweeps use LINE_FAST: along a
+// row the lines are LDW complex apart, which spreads a wave over the banks.
 template <int R, int N, int L, int NLINES, int LSTR, int ESTR, int TS, bool LINE_FAST, bool INV,
           int NT, typename T>
 __device__ __forceinline__ void stockham_stage(cx<T>* buf, const cx<T>* tab, int tid) {
@@ -167,7 +168,7 @@ template <int PH, int PW, int NT, typename T>
 __device__ void rfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
   using G = PlaneGeom<PH, PW>;
   constexpr int M = G::M, LDW = G::LDW;
-  fft_lines<M, PH, LDW, 1, 2, false, false, NT, T>(buf, twW, tid);
+  fft_lines<M, PH, LDW, 1, 2, true, false, NT, T>(buf, twW, tid);
   // split the packed spectrum of each row into the spectrum of the real row
   constexpr int HALF = M / 2 + 1;
   for (int task = tid; task < PH * HALF; task += NT) {
@@ -215,7 +216,7 @@ __device__ void irfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int t
     }
   }
   __syncthreads();
-  fft_lines<M, PH, LDW, 1, 2, false, true, NT, T>(buf, twW, tid);
+  fft_lines<M, PH, LDW, 1, 2, true, true, NT, T>(buf, twW, tid);
 }
 
 }  // namespace ocsc

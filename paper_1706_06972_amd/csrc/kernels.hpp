@@ -26,6 +26,70 @@ __device__ __forceinline__ void load_tables(cx<T>* sH, cx<T>* sW, const cx<T>* t
   for (int i = tid; i < PW; i += nt) sW[i] = twW[i];
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Global <-> LDS traffic of one PH x PW plane in 16-byte vectors.  Every
+// thread issues all of its loads before it stores any of them, so the plane's
+// HBM latency is paid once, not once per loop trip.
+template <typename T, int PH, int PW, int NT>
+struct PlaneIO {
+  using G = PlaneGeom<PH, PW>;
+  static constexpr int VR = 16 / (int)sizeof(T);   // reals per vector
+  static constexpr int NSV = G::PF * 2 / VR;       // vectors per half spectrum
+  static constexpr int NRV = G::P / VR;            // vectors per real plane
+  static constexpr int CS = (NSV + NT - 1) / NT;
+  static constexpr int CR = (NRV + NT - 1) / NT;
+  // LDS slot (complex index) of the first pixel pair of real vector e
+  static __device__ __forceinline__ int slot(int e) {
+    const int i = e * VR;
+    return (i / PW) * G::LDW + ((i % PW) >> 1);
+  }
+  static __device__ __forceinline__ void spec_in(cx<T>* buf, const cx<T>* src, int tid) {
+    const v4f* s = reinterpret_cast<const v4f*>(src);
+    v4f* d = reinterpret_cast<v4f*>(buf);
+    v4f r[CS];
+#pragma unroll
+    for (int q = 0; q < CS; ++q) {
+      const int e = tid + q * NT;
+      if (NSV % NT == 0 || e < NSV) r[q] = s[e];
+    }
+#pragma unroll
+    for (int q = 0; q < CS; ++q) {
+      const int e = tid + q * NT;
+      if (NSV % NT == 0 || e < NSV) d[e] = r[q];
+    }
+  }
+  static __device__ __forceinline__ void spec_out(cx<T>* dst, const cx<T>* buf, int tid) {
+    const v4f* s = reinterpret_cast<const v4f*>(buf);
+    v4f* d = reinterpret_cast<v4f*>(dst);
+#pragma unroll
+    for (int q = 0; q < CS; ++q) {
+      const int e = tid + q * NT;
+      if (NSV % NT == 0 || e < NSV) d[e] = s[e];
+    }
+  }
+  // real plane (row pitch PW) -> packed pixel pairs in LDS
+  static __device__ __forceinline__ void real_in(cx<T>* buf, const T* src, int tid) {
+    const v4f* s = reinterpret_cast<const v4f*>(src);
+    v4f r[CR];
+#pragma unroll
+    for (int q = 0; q < CR; ++q) {
+      const int e = tid + q * NT;
+      if (NRV % NT == 0 || e < NRV) r[q] = s[e];
+    }
+#pragma unroll
+    for (int q = 0; q < CR; ++q) {
+      const int e = tid + q * NT;
+      if (NRV % NT == 0 || e < NRV) {
+        const T* v = reinterpret_cast<const T*>(&r[q]);
+        cx<T>* o = buf + slot(e);
+#pragma unroll
+        for (int h = 0; h < VR / 2; ++h) o[h] = mk<T>(v[2 * h], v[2 * h + 1]);
+      }
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Batched forward R2C of real planes.  Plane q is read from
 // src + q * sstride as an sh x sw block (row pitch sw) placed at (0, 0) of a
@@ -36,25 +100,29 @@ __global__ __launch_bounds__(NT) void k_rfft2(const T* __restrict__ src, int sh,
                                               cx<T>* __restrict__ dst, long dstride,
                                               const cx<T>* __restrict__ twH, const cx<T>* __restrict__ twW) {
   using G = PlaneGeom<PH, PW>;
-  __shared__ cx<T> buf[PH * G::LDW];
+  using IO = PlaneIO<T, PH, PW, NT>;
+  __shared__ __align__(16) cx<T> buf[PH * G::LDW];
   __shared__ cx<T> sH[PH], sW[PW];
   const int tid = threadIdx.x;
   const long q = blockIdx.x;
   load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
   const T* s = src + q * sstride;
-  for (int e = tid; e < PH * G::M; e += NT) {
-    const int r = e / G::M, n = e % G::M, c = 2 * n;
-    T a = 0, b = 0;
-    if (r < sh) {
-      if (c < sw) a = s[r * sw + c];
-      if (c + 1 < sw) b = s[r * sw + c + 1];
+  if (sh == PH && sw == PW && (sstride % IO::VR) == 0) {
+    IO::real_in(buf, s, tid);
+  } else {
+    for (int e = tid; e < PH * G::M; e += NT) {
+      const int r = e / G::M, n = e % G::M, c = 2 * n;
+      T a = 0, b = 0;
+      if (r < sh) {
+        if (c < sw) a = s[r * sw + c];
+        if (c + 1 < sw) b = s[r * sw + c + 1];
+      }
+      buf[r * G::LDW + n] = mk<T>(a, b);
     }
-    buf[r * G::LDW + n] = mk<T>(a, b);
   }
   __syncthreads();
   rfft2_lds<PH, PW, NT, T>(buf, sH, sW, tid);
-  cx<T>* d = dst + q * dstride;
-  for (int e = tid; e < G::PF; e += NT) d[e] = buf[e];
+  IO::spec_out(dst + q * dstride, buf, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -67,13 +135,13 @@ __global__ __launch_bounds__(NT) void k_irfft2_crop(const cx<T>* __restrict__ sr
                                                     const cx<T>* __restrict__ twH,
                                                     const cx<T>* __restrict__ twW) {
   using G = PlaneGeom<PH, PW>;
-  __shared__ cx<T> buf[PH * G::LDW];
+  using IO = PlaneIO<T, PH, PW, NT>;
+  __shared__ __align__(16) cx<T> buf[PH * G::LDW];
   __shared__ cx<T> sH[PH], sW[PW];
   const int tid = threadIdx.x;
   const long q = blockIdx.x;
   load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
-  const cx<T>* s = src + q * sstride;
-  for (int e = tid; e < G::PF; e += NT) buf[e] = s[e];
+  IO::spec_in(buf, src + q * sstride, tid);
   __syncthreads();
   irfft2_lds<PH, PW, NT, T>(buf, sH, sW, tid);
   const T scale = (T)1 / (T)G::P;
@@ -97,38 +165,57 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
                                                    const cx<T>* __restrict__ twW, T kappa, int first,
                                                    int last) {
   using G = PlaneGeom<PH, PW>;
-  __shared__ cx<T> buf[PH * G::LDW];
+  using IO = PlaneIO<T, PH, PW, NT>;
+  constexpr int VR = IO::VR, CR = IO::CR, NRV = IO::NRV;
+  __shared__ __align__(16) cx<T> buf[PH * G::LDW];
   __shared__ cx<T> sH[PH], sW[PW];
   const int tid = threadIdx.x;
   const long q = blockIdx.x;
   load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
-  const cx<T>* z = Zh + q * G::PF;
-  for (int e = tid; e < G::PF; e += NT) buf[e] = z[e];
+  IO::spec_in(buf, Zh + q * G::PF, tid);
+  // the dual W of this plane is fetched while the inverse transform runs
+  v4f* wv = reinterpret_cast<v4f*>(W + q * G::P);
+  v4f wr[CR];
+#pragma unroll
+  for (int j = 0; j < CR; ++j) {
+    const int e = tid + j * NT;
+    if (NRV % NT == 0 || e < NRV) wr[j] = first ? v4f{0, 0, 0, 0} : wv[e];
+  }
   __syncthreads();
   irfft2_lds<PH, PW, NT, T>(buf, sH, sW, tid);
   const T scale = (T)1 / (T)G::P;
-  cx<T>* wp = reinterpret_cast<cx<T>*>(W + q * G::P);   // pixel pairs (2n, 2n+1)
-  cx<T>* up = Uout ? reinterpret_cast<cx<T>*>(Uout + q * G::P) : nullptr;
-  for (int e = tid; e < PH * G::M; e += NT) {
-    const int r = e / G::M, n = e % G::M;
-    const cx<T> y = buf[r * G::LDW + n];
-    const cx<T> w = first ? mk<T>(0, 0) : wp[e];
-    const T v0 = y.x * scale + w.x, v1 = y.y * scale + w.y;
-    const T u0 = copysign(fmax(fabs(v0) - kappa, (T)0), v0);
-    const T u1 = copysign(fmax(fabs(v1) - kappa, (T)0), v1);
-    if (last) {
-      if (up) up[e] = mk<T>(u0, u1);
-    } else {
-      const T w0 = v0 - u0, w1 = v1 - u1;
-      wp[e] = mk<T>(w0, w1);
-      buf[r * G::LDW + n] = mk<T>(u0 - w0, u1 - w1);
+  v4f* uv = Uout ? reinterpret_cast<v4f*>(Uout + q * G::P) : nullptr;
+#pragma unroll
+  for (int j = 0; j < CR; ++j) {
+    const int e = tid + j * NT;
+    if (NRV % NT == 0 || e < NRV) {
+      cx<T>* o = buf + IO::slot(e);
+      T* w = reinterpret_cast<T*>(&wr[j]);
+      v4f uo;
+      T* u = reinterpret_cast<T*>(&uo);
+#pragma unroll
+      for (int h = 0; h < VR / 2; ++h) {
+        const cx<T> y = o[h];
+        const T v0 = y.x * scale + w[2 * h], v1 = y.y * scale + w[2 * h + 1];
+        const T u0 = copysign(fmax(fabs(v0) - kappa, (T)0), v0);
+        const T u1 = copysign(fmax(fabs(v1) - kappa, (T)0), v1);
+        u[2 * h] = u0;
+        u[2 * h + 1] = u1;
+        w[2 * h] = v0 - u0;
+        w[2 * h + 1] = v1 - u1;
+        o[h] = mk<T>(u0 - w[2 * h], u1 - w[2 * h + 1]);
+      }
+      if (last) {
+        if (uv) uv[e] = uo;
+      } else {
+        wv[e] = wr[j];
+      }
     }
   }
   if (last) return;
   __syncthreads();
   rfft2_lds<PH, PW, NT, T>(buf, sH, sW, tid);
-  cx<T>* s = S + q * G::PF;
-  for (int e = tid; e < G::PF; e += NT) s[e] = buf[e];
+  IO::spec_out(S + q * G::PF, buf, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -136,51 +223,54 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
 // frequency p with a = Dh[:, p], s = S[:, p]:
 //   z = s + conj(a) * gam_p * (x_p - a^T s),   gam_p = 1 / (rho + ||a||^2),
 // which is the Sherman-Morrison solution of (conj(a) a^T + rho I) z =
-// conj(a) x_p + rho s.  A workgroup of NW waves serves 64 frequencies of one
-// sample; wave w holds filters k = w, w + NW, ... (at most KPW) in registers.
-// first: s = 0.
+// conj(a) x_p + rho s.  A workgroup of 256 threads serves 16 frequencies of
+// one sample: thread (kq, f) holds filters k = kq, kq + 16, ... (at most KPT)
+// of frequency f in registers, so each filter row is read as one 128-byte
+// (FP32) or 256-byte (FP64) segment.  first: s = 0.
 // ---------------------------------------------------------------------------
-template <typename T, int NW, int KPW>
-__global__ __launch_bounds__(64 * NW) void k_code_zstep(const cx<T>* __restrict__ Dh,
-                                                        const T* __restrict__ gam,
-                                                        const cx<T>* __restrict__ xh,
-                                                        const cx<T>* __restrict__ S,
-                                                        cx<T>* __restrict__ Zh, int K, int Pf,
-                                                        int first) {
-  __shared__ cx<T> red[NW][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+constexpr int ZF = 16;
+
+template <typename T, int KPT>
+__global__ __launch_bounds__(256) void k_code_zstep(const cx<T>* __restrict__ Dh,
+                                                   const T* __restrict__ gam,
+                                                   const cx<T>* __restrict__ xh,
+                                                   const cx<T>* __restrict__ S,
+                                                   cx<T>* __restrict__ Zh, int K, int Pf,
+                                                   int first) {
+  __shared__ cx<T> red[16][ZF + 1];
+  const int f = threadIdx.x % ZF, kq = threadIdx.x / ZF;
   const int b = blockIdx.y;
-  const int p = blockIdx.x * 64 + lane;
+  const int p = blockIdx.x * ZF + f;
   const bool ok = p < Pf;
-  cx<T> a[KPW], s[KPW];
+  cx<T> a[KPT], s[KPT];
   cx<T> acc = mk<T>(0, 0);
 #pragma unroll
-  for (int j = 0; j < KPW; ++j) {
-    const int k = wv + j * NW;
+  for (int j = 0; j < KPT; ++j) {
+    const int k = kq + j * 16;
     a[j] = mk<T>(0, 0);
     s[j] = mk<T>(0, 0);
     if (ok && k < K) {
-      a[j] = Dh[(long)k * Pf + p];
-      if (!first) s[j] = S[((long)b * K + k) * Pf + p];
-      acc = cadd<T>(acc, cmul<T>(a[j], s[j]));
+      a[j] = Dh[(size_t)k * Pf + p];
+      if (!first) s[j] = S[((size_t)b * K + k) * Pf + p];
     }
+    acc = cadd<T>(acc, cmul<T>(a[j], s[j]));
   }
-  red[wv][lane] = acc;
+  red[kq][f] = acc;
   __syncthreads();
-  if (wv == 0) {
-    cx<T> tot = red[0][lane];
+  if (kq == 0) {
+    cx<T> tot = red[0][f];
 #pragma unroll
-    for (int i = 1; i < NW; ++i) tot = cadd<T>(tot, red[i][lane]);
+    for (int i = 1; i < 16; ++i) tot = cadd<T>(tot, red[i][f]);
     cx<T> qv = mk<T>(0, 0);
-    if (ok) qv = cscale<T>(csub<T>(xh[(long)b * Pf + p], tot), gam[p]);
-    red[0][lane] = qv;
+    if (ok) qv = cscale<T>(csub<T>(xh[(size_t)b * Pf + p], tot), gam[p]);
+    red[0][f] = qv;
   }
   __syncthreads();
-  const cx<T> qv = red[0][lane];
+  const cx<T> qv = red[0][f];
 #pragma unroll
-  for (int j = 0; j < KPW; ++j) {
-    const int k = wv + j * NW;
-    if (ok && k < K) Zh[((long)b * K + k) * Pf + p] = cadd<T>(s[j], cmulc<T>(qv, a[j]));
+  for (int j = 0; j < KPT; ++j) {
+    const int k = kq + j * 16;
+    if (ok && k < K) Zh[((size_t)b * K + k) * Pf + p] = cadd<T>(s[j], cmulc<T>(qv, a[j]));
   }
 }
 
@@ -198,42 +288,64 @@ __global__ void k_gamma(const cx<T>* __restrict__ Dh, T* __restrict__ gam, T rho
 }
 
 // ---------------------------------------------------------------------------
-// Per-frequency Hermitian algebra on the R-form of C held in LDS.
+// Per-frequency Hermitian algebra on C held in LDS.
+//
+// C_p is stored (in HBM and in LDS alike) as K rows of pitch ld = K + 1 reals:
+// R[i][j] = Re C_ij for j >= i and R[j][i] = Im C_ij for j > i (the Hermitian
+// matrix in K*K reals; the pad column is unused).  Frequency p occupies fs
+// reals (fs = K*ld rounded up to 16 bytes), so a block of consecutive
+// frequencies is one contiguous run that stages into LDS by 16-byte copies.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct HermLds {
-  T* R;      // [K][K+1]
-  int K, ld;
-  __device__ __forceinline__ cx<T> elem(int i, int j) const {   // C_ij
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    const T a = R[lo * ld + hi];
-    const T braw = R[hi * ld + lo];
-    const T b = j > i ? braw : (j < i ? -braw : (T)0);
-    return mk<T>(a, b);
-  }
-};
 
-// y = C x for one frequency, by the lt-th of tpg threads of its group.  Rows are
-// split over up to 4 column chunks when the group has spare threads; partial
-// sums go through part[4][K].
+// Sum of v over the tpg threads of one group (tpg a power of two; groups are
+// aligned sub-waves or whole waves).  scratch: one T per wave of the block.
+// Every thread of the group gets the total.  Contains a block-wide barrier.
 template <typename T>
-__device__ __forceinline__ void herm_matvec(const HermLds<T>& C, const cx<T>* x, cx<T>* y, cx<T>* part,
-                                            int lt, int tpg) {
-  const int K = C.K;
-  int ns = tpg / K;
-  ns = ns < 1 ? 1 : (ns > 4 ? 4 : ns);
+__device__ __forceinline__ T group_sum(T v, int tpg, T* scratch) {
+  const int w = tpg < 64 ? tpg : 64;
+  for (int off = w >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (tpg <= 64) return v;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  const int nw = tpg >> 6, w0 = (wave / nw) * nw;
+  T s = 0;
+  for (int i = 0; i < nw; ++i) s += scratch[w0 + i];
+  __syncthreads();
+  return s;
+}
+
+// y = C x by the lt-th of the tpg threads serving one frequency.  Thread
+// (i, h) sums row i over the h-th of ns column chunks; at column j it reads
+// p = R[i][j] and q = R[j][i] and forms C_ij = (p, q) above the diagonal and
+// (q, -p) below it.  Partial sums pass through part[ns][K].
+template <typename T>
+__device__ __forceinline__ void herm_matvec(const T* __restrict__ R, int K, int ld, const cx<T>* x, cx<T>* y,
+                                            cx<T>* part, int lt, int tpg, int ns) {
   const int chunk = (K + ns - 1) / ns;
   for (int task = lt; task < K * ns; task += tpg) {
-    const int i = task % K, h = task / K;
+    const int h = task / K, i = task - h * K;
     const int j0 = h * chunk, j1 = min(K, j0 + chunk);
-    T ar = 0, ai = 0;
+    const T* rowp = R + i * ld;
+    const T* colp = R + i;
+    T yr = 0, yi = 0;
+#pragma unroll 4
     for (int j = j0; j < j1; ++j) {
-      const cx<T> c = C.elem(i, j);
+      const T p = rowp[j], q = colp[j * ld];
       const cx<T> xv = x[j];
-      ar += c.x * xv.x - c.y * xv.y;
-      ai += c.x * xv.y + c.y * xv.x;
+      const bool up = j > i;
+      const T a = up ? p : q;
+      const T b = up ? q : -p;
+      yr += a * xv.x - b * xv.y;
+      yi += a * xv.y + b * xv.x;
     }
-    part[h * K + i] = mk<T>(ar, ai);
+    if (i >= j0 && i < j1) {   // the loop took Im C_ii = -R[i][i]; it is zero
+      const T dg = rowp[i];
+      const cx<T> xv = x[i];
+      yr -= dg * xv.y;
+      yi += dg * xv.x;
+    }
+    part[h * K + i] = mk<T>(yr, yi);
   }
   __syncthreads();
   for (int i = lt; i < K; i += tpg) {
@@ -244,16 +356,112 @@ __device__ __forceinline__ void herm_matvec(const HermLds<T>& C, const cx<T>* x,
   __syncthreads();
 }
 
+// y1 = C x1 and y2 = C x2 in one pass over C (same thread layout as
+// herm_matvec); part holds 2 * ns * K partial sums.
+template <typename T>
+__device__ __forceinline__ void herm_matvec2(const T* __restrict__ R, int K, int ld, const cx<T>* x1,
+                                             const cx<T>* x2, cx<T>* y1, cx<T>* y2, cx<T>* part, int lt,
+                                             int tpg, int ns) {
+  const int chunk = (K + ns - 1) / ns;
+  cx<T>* part2 = part + ns * K;
+  for (int task = lt; task < K * ns; task += tpg) {
+    const int h = task / K, i = task - h * K;
+    const int j0 = h * chunk, j1 = min(K, j0 + chunk);
+    const T* rowp = R + i * ld;
+    const T* colp = R + i;
+    T ar = 0, ai = 0, br = 0, bi = 0;
+#pragma unroll 4
+    for (int j = j0; j < j1; ++j) {
+      const T p = rowp[j], q = colp[j * ld];
+      const cx<T> u = x1[j], v = x2[j];
+      const bool up = j > i;
+      const T a = up ? p : q;
+      const T b = up ? q : -p;
+      ar += a * u.x - b * u.y;
+      ai += a * u.y + b * u.x;
+      br += a * v.x - b * v.y;
+      bi += a * v.y + b * v.x;
+    }
+    if (i >= j0 && i < j1) {
+      const T dg = rowp[i];
+      const cx<T> u = x1[i], v = x2[i];
+      ar -= dg * u.y;
+      ai += dg * u.x;
+      br -= dg * v.y;
+      bi += dg * v.x;
+    }
+    part[h * K + i] = mk<T>(ar, ai);
+    part2[h * K + i] = mk<T>(br, bi);
+  }
+  __syncthreads();
+  for (int i = lt; i < K; i += tpg) {
+    cx<T> s1 = part[i], s2 = part2[i];
+    for (int h = 1; h < ns; ++h) {
+      s1 = cadd<T>(s1, part[h * K + i]);
+      s2 = cadd<T>(s2, part2[h * K + i]);
+    }
+    y1[i] = s1;
+    y2[i] = s2;
+  }
+  __syncthreads();
+}
+
+// C <- C - beta v v^H on the stored reals: R[i][j] (j >= i) loses
+// beta Re(v_i conj v_j); R[i][j] (j < i, holding Im C_ji) loses beta Im(v_j conj v_i).
+template <typename T>
+__device__ __forceinline__ void herm_rank1(T* __restrict__ R, int K, int ld, const cx<T>* v, T beta, int lt,
+                                           int tpg, int ns) {
+  const int chunk = (K + ns - 1) / ns;
+  for (int task = lt; task < K * ns; task += tpg) {
+    const int h = task / K, i = task - h * K;
+    const int j0 = h * chunk, j1 = min(K, j0 + chunk);
+    const cx<T> vi = v[i];
+    T* rowp = R + i * ld;
+    for (int j = j0; j < j1; ++j) {
+      const cx<T> vj = v[j];
+      rowp[j] -= beta * (j >= i ? (vi.x * vj.x + vi.y * vj.y) : (vj.y * vi.x - vj.x * vi.y));
+    }
+  }
+  __syncthreads();
+}
+
+// 16-byte vectors of one slot (fpb consecutive frequencies) held by one thread.
+constexpr int SWEEP_MAXV = 12;
+constexpr int SWEEP_VECS = 12;   // complex K-vectors of LDS per frequency group
+
+template <typename T>
+__device__ __forceinline__ void slot_fetch(v4f (&reg)[SWEEP_MAXV], const v4f* __restrict__ src, int nvec,
+                                           int tid) {
+#pragma unroll
+  for (int v = 0; v < SWEEP_MAXV; ++v) {
+    const int e = tid + v * 256;
+    if (e < nvec) reg[v] = src[e];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void slot_stage(const v4f (&reg)[SWEEP_MAXV], v4f* dst, int nvec, int tid) {
+#pragma unroll
+  for (int v = 0; v < SWEEP_MAXV; ++v) {
+    const int e = tid + v * 256;
+    if (e < nvec) dst[e] = reg[v];
+  }
+}
+
 // ---------------------------------------------------------------------------
-// One D-step sweep over all frequencies (eq. sub_d_sol, column form):
-//   d_p = C_p rhs_p,
-// FPB frequencies per workgroup, C_p staged in LDS.  When nfold > 0 the
-// history of nfold samples is folded first, in sample order (eqs. B_update
-// and C_update):  u = conj(z_p);  G_p += u x_p;  v = C_p u;
-// C_p <- C_p - v v^H / (1 + u^H v);  the updated C_p is written back and the
-// right-hand side is the updated G_p (the first DictOCSC iterate, V = Theta = 0).
-// With nfold = 0 and dout == nullptr the kernel only folds (stand-alone history
-// update).  gam_out (optional): 1 / (rho + ||d_p||^2) for the next code update.
+// D-step sweep over all frequencies (eq. sub_d_sol, column form):
+//   d_p = C_p rhs_p.
+// A workgroup walks a run of slots (fpb frequencies each; the fpb groups of
+// 256/fpb threads work side by side); while one slot is being solved the next
+// slot's C is already in flight into registers.  The runs of workgroups that
+// share an XCD are adjacent in frequency.
+//
+// nfold > 0: before the D-step the kept spectra of nfold samples are folded
+// into the history in sample order (eqs. B_update and C_update):
+//   u = conj(z_p);  G_p += u x_p;  v = C_p u;  C_p <- C_p - v v^H / (1 + u^H v),
+// the updated C_p is written back and the right-hand side is the updated G_p
+// (the first DictOCSC iterate, from V = Theta = 0).  dout == nullptr: fold only.
+// gam_out (optional): 1 / (rho + ||d_p||^2), used by the next code update.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* __restrict__ G,
@@ -261,81 +469,139 @@ __global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* _
                                                     const cx<T>* __restrict__ Zh,
                                                     const cx<T>* __restrict__ xh, int nfold,
                                                     cx<T>* __restrict__ dout, T* __restrict__ gam_out,
-                                                    T rho, int K, int Pf, int fpb, int reverse) {
+                                                    T rho, int K, int Pf, int fpb, int fs, int slots_per_wg,
+                                                    int reverse) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ld = K + 1;
   const int tpg = 256 / fpb;
-  const int g = threadIdx.x / tpg, lt = threadIdx.x % tpg;
-  // carve LDS: R blocks, then per-group vectors
+  const int tid = threadIdx.x;
+  const int g = tid / tpg, lt = tid % tpg;
+  int ns = tpg / K;
+  ns = ns < 1 ? 1 : (ns > 4 ? 4 : ns);
   T* Rall = reinterpret_cast<T*>(smem_raw);
-  const size_t rbytes = ((size_t)fpb * K * ld * sizeof(T) + 15) & ~(size_t)15;
+  const size_t rbytes = (size_t)fpb * fs * sizeof(T);   // fs*sizeof(T) is a multiple of 16
   cx<T>* vecs = reinterpret_cast<cx<T>*>(smem_raw + rbytes);
-  cx<T>* xv = vecs + (size_t)g * 7 * K;   // rhs / u
-  cx<T>* yv = xv + K;                     // result
-  cx<T>* vv = yv + K;                     // C u
-  cx<T>* part = vv + K;                   // [4][K]
-  __shared__ T sred[16];
+  cx<T>* xv = vecs + (size_t)g * SWEEP_VECS * K;   // rhs / u
+  cx<T>* yv = xv + K;                              // result / updated G
+  cx<T>* vv = yv + K;                              // C u
+  cx<T>* gv = vv + K;                              // C G
+  cx<T>* part = gv + K;                            // [8][K]
+  __shared__ T wsum[4];
+  T* R = Rall + (size_t)g * fs;
 
-  const int nb = (Pf + fpb - 1) / fpb;
-  int fb = xcd_block(blockIdx.x, nb);
-  if (reverse) fb = nb - 1 - fb;
-  const int p = fb * fpb + g;
-  const bool ok = p < Pf;
-  HermLds<T> C{Rall + (size_t)g * K * ld, K, ld};
-  const size_t kk = (size_t)K * K;
+  const int nslots = (Pf + fpb - 1) / fpb;
+  const int nwg = gridDim.x;
+  const int run = xcd_block(blockIdx.x, nwg);
+  const int s_begin = run * slots_per_wg;
+  const int s_end = min(nslots, s_begin + slots_per_wg);
+  const int nvec = (int)((size_t)fpb * fs * sizeof(T) / 16);
+  const bool plain = dout && nfold == 0;
+  v4f reg[SWEEP_MAXV];
+  cx<T> rpre = mk<T>(0, 0);
 
-  // stage C_p into LDS
-  if (ok) {
-    const T* src = Cm + (size_t)p * kk;
-    for (int e = lt; e < (int)kk; e += tpg) C.R[(e / K) * ld + (e % K)] = src[e];
+  auto slot_of = [&](int s) { return reverse ? nslots - 1 - s : s; };
+  auto slot_vecs = [&](int sl) {
+    return min(nvec, (int)(((size_t)min(fpb, Pf - sl * fpb) * fs * sizeof(T)) / 16));
+  };
+  if (s_begin < s_end) {
+    const int sl = slot_of(s_begin);
+    slot_fetch<T>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sl * fpb * fs), slot_vecs(sl), tid);
+    const int p = sl * fpb + g;
+    if (plain && lt < K && p < Pf) rpre = rhs[(size_t)lt * Pf + p];
   }
-  __syncthreads();
-
-  for (int b = 0; b < nfold; ++b) {
-    if (ok) {
-      const cx<T> xp = xh[(size_t)b * Pf + p];
-      for (int k = lt; k < K; k += tpg) {
-        const cx<T> z = Zh[((size_t)b * K + k) * Pf + p];
-        const cx<T> u = cconj<T>(z);
-        xv[k] = u;
-        G[(size_t)k * Pf + p] = cadd<T>(G[(size_t)k * Pf + p], cmul<T>(u, xp));
+  for (int s = s_begin; s < s_end; ++s) {
+    const int sl = slot_of(s);
+    const int p = sl * fpb + g;
+    const bool ok = p < Pf;
+    const int nv = slot_vecs(sl);
+    __syncthreads();   // previous slot finished with LDS
+    slot_stage<T>(reg, reinterpret_cast<v4f*>(Rall), nv, tid);
+    if (plain && lt < K) xv[lt] = rpre;
+    __syncthreads();
+    if (s + 1 < s_end) {   // next slot's C and right-hand side are in flight during this slot
+      const int sn = slot_of(s + 1);
+      slot_fetch<T>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sn * fpb * fs), slot_vecs(sn), tid);
+      const int pn = sn * fpb + g;
+      if (plain && lt < K && pn < Pf) rpre = rhs[(size_t)lt * Pf + pn];
+    }
+    if (plain) {
+      herm_matvec<T>(R, K, ld, xv, yv, part, lt, tpg, ns);
+    } else if (nfold == 1) {
+      // one sample: v = C u and g = C G_new in one pass; d = g - beta v (v^H G_new)
+      if (ok && lt < K) {
+        const cx<T> u = cconj<T>(Zh[(size_t)lt * Pf + p]);
+        const cx<T> gn = cadd<T>(G[(size_t)lt * Pf + p], cmul<T>(u, xh[p]));
+        G[(size_t)lt * Pf + p] = gn;
+        xv[lt] = u;
+        yv[lt] = gn;
       }
+      __syncthreads();
+      herm_matvec2<T>(R, K, ld, xv, yv, vv, gv, part, lt, tpg, ns);
+      T su = 0, tr = 0, ti = 0;
+      if (lt < K) {
+        const cx<T> u = xv[lt], v = vv[lt], gn = yv[lt];
+        su = u.x * v.x + u.y * v.y;                  // Re(conj(u) v)
+        tr = v.x * gn.x + v.y * gn.y;                // conj(v) G
+        ti = v.x * gn.y - v.y * gn.x;
+      }
+      su = group_sum<T>(su, tpg, wsum);
+      tr = group_sum<T>(tr, tpg, wsum);
+      ti = group_sum<T>(ti, tpg, wsum);
+      const T beta = (T)1 / ((T)1 + su);
+      if (dout && lt < K) {
+        const cx<T> v = vv[lt];
+        const cx<T> tv = mk<T>(beta * tr, beta * ti);
+        yv[lt] = csub<T>(gv[lt], cmul<T>(v, tv));
+      }
+      herm_rank1<T>(R, K, ld, vv, beta, lt, tpg, ns);
+      v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
+      const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
+      for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
+    } else {
+      // several samples, folded one after another in sample order
+      for (int b = 0; b < nfold; ++b) {
+        if (ok && lt < K) {
+          const cx<T> u = cconj<T>(Zh[((size_t)b * K + lt) * Pf + p]);
+          xv[lt] = u;
+          G[(size_t)lt * Pf + p] = cadd<T>(G[(size_t)lt * Pf + p], cmul<T>(u, xh[(size_t)b * Pf + p]));
+        }
+        __syncthreads();
+        herm_matvec<T>(R, K, ld, xv, vv, part, lt, tpg, ns);
+        T acc = 0;
+        if (lt < K) acc = xv[lt].x * vv[lt].x + xv[lt].y * vv[lt].y;   // Re(u^H v)
+        acc = group_sum<T>(acc, tpg, wsum);
+        herm_rank1<T>(R, K, ld, vv, (T)1 / ((T)1 + acc), lt, tpg, ns);
+      }
+      v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
+      const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
+      for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
+      if (dout && ok && lt < K) xv[lt] = G[(size_t)lt * Pf + p];
+      __syncthreads();
+      if (dout) herm_matvec<T>(R, K, ld, xv, yv, part, lt, tpg, ns);
     }
+    if (!dout) continue;
     __syncthreads();
-    herm_matvec<T>(C, xv, vv, part, lt, tpg);
-    if (lt == 0) {
-      T s = 0;
-      for (int i = 0; i < K; ++i) s += xv[i].x * vv[i].x + xv[i].y * vv[i].y;   // Re(u^H v)
-      sred[g] = (T)1 / ((T)1 + s);
+    if (ok && lt < K) dout[(size_t)lt * Pf + p] = yv[lt];
+    if (gam_out) {
+      T acc = 0;
+      if (lt < K) acc = yv[lt].x * yv[lt].x + yv[lt].y * yv[lt].y;
+      acc = group_sum<T>(acc, tpg, wsum);
+      if (lt == 0 && ok) gam_out[p] = (T)1 / (rho + acc);
     }
-    __syncthreads();
-    const T beta = sred[g];
-    for (int e = lt; e < (int)kk; e += tpg) {
-      const int i = e / K, j = e % K;
-      const cx<T> vi = vv[i], vj = vv[j];
-      if (j >= i) C.R[i * ld + j] -= beta * (vi.x * vj.x + vi.y * vj.y);   // Re(v_i conj v_j)
-      else C.R[i * ld + j] -= beta * (vj.y * vi.x - vj.x * vi.y);          // Im(v_j conj v_i)
-    }
-    __syncthreads();
   }
-  if (nfold > 0 && ok) {
-    T* dst = Cm + (size_t)p * kk;
-    for (int e = lt; e < (int)kk; e += tpg) dst[e] = C.R[(e / K) * ld + (e % K)];
-  }
-  if (!dout) return;
+}
 
-  // right-hand side
-  const cx<T>* r = nfold > 0 ? G : rhs;
-  if (ok)
-    for (int k = lt; k < K; k += tpg) xv[k] = r[(size_t)k * Pf + p];
-  __syncthreads();
-  herm_matvec<T>(C, xv, yv, part, lt, tpg);
-  if (ok)
-    for (int k = lt; k < K; k += tpg) dout[(size_t)k * Pf + p] = yv[k];
-  if (gam_out && lt == 0 && ok) {
-    T s = 0;
-    for (int i = 0; i < K; ++i) s += yv[i].x * yv[i].x + yv[i].y * yv[i].y;
-    gam_out[p] = (T)1 / (rho + s);
+// Packed [Pf][K][K] <-> the per-frequency layout of pitch ld = K + 1 and stride fs.
+template <typename T>
+__global__ void k_cinv_layout(const T* __restrict__ src, T* __restrict__ dst, int K, int Pf, int fs, int to_internal) {
+  const size_t kk = (size_t)K * K;
+  const size_t n = kk * Pf;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = e / kk, r = e % kk;
+    const size_t i = r / K, j = r % K;
+    const size_t in = p * fs + i * (K + 1) + j;
+    if (to_internal) dst[in] = src[e];
+    else dst[e] = src[in];
   }
 }
 
@@ -348,7 +614,8 @@ __global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* _
 //   X = d_k + Theta_k,  c_v = 1 at v = 0, PW/2 and 2 otherwise,
 // i.e. the crop of the real inverse DFT of a Hermitian spectrum.
 // ---------------------------------------------------------------------------
-constexpr int VB = 8;
+// Columns per block: one 128-byte line of complex values (16 FP32, 8 FP64).
+template <typename T> __host__ __device__ constexpr int vblock() { return 128 / (int)(2 * sizeof(T)); }
 constexpr int MAXF = 128;   // filter extent bound (filt <= pad <= 128)
 
 template <typename T>
@@ -357,35 +624,52 @@ __global__ __launch_bounds__(256) void k_vstep_alpha(const cx<T>* __restrict__ d
                                                      const cx<T>* __restrict__ twH,
                                                      const cx<T>* __restrict__ twW, int PH, int PW,
                                                      int Mh, int Mw, int first) {
+  constexpr int VB = vblock<T>();
   __shared__ cx<T> X[MAXF * VB];
-  __shared__ cx<T> t[MAXF * VB];
+  __shared__ cx<T> t[2 * MAXF * VB];
+  __shared__ cx<T> sH[MAXF], sW[MAXF];
   const int WC = PW / 2 + 1, Pf = PH * WC;
   const int vb = blockIdx.x, k = blockIdx.y, nvb = gridDim.x;
   const int v0 = vb * VB, nv = min(VB, WC - v0);
   const int tid = threadIdx.x;
+  for (int i = tid; i < PH; i += 256) sH[i] = twH[i];
+  for (int i = tid; i < PW; i += 256) sW[i] = twW[i];
   const cx<T>* dk = d + (size_t)k * Pf;
   const cx<T>* tk = Th + (size_t)k * Pf;
-  for (int e = tid; e < PH * VB; e += 256) {
-    const int u = e / VB, c = e % VB;
-    cx<T> x = mk<T>(0, 0);
-    if (c < nv) {
-      x = dk[u * WC + v0 + c];
-      if (!first) x = cadd<T>(x, tk[u * WC + v0 + c]);
+  constexpr int NQ = MAXF * VB / 256;
+  cx<T> xd[NQ], xt[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {   // all loads issued before any use
+    const int e = tid + q * 256, u = e / VB, c = e % VB;
+    xd[q] = mk<T>(0, 0);
+    xt[q] = mk<T>(0, 0);
+    if (e < PH * VB && c < nv) {
+      xd[q] = dk[u * WC + v0 + c];
+      if (!first) xt[q] = tk[u * WC + v0 + c];
     }
-    X[e] = x;
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + q * 256;
+    if (e < PH * VB) X[e] = cadd<T>(xd[q], xt[q]);
   }
   __syncthreads();
-  for (int e = tid; e < Mh * VB; e += 256) {
-    const int m = e / VB, c = e % VB;
+  // t[m][c] = sum_u X[u][c] e^{+2 pi i u m / PH}, the u-sum split over two threads
+  const int HU = PH / 2;
+  for (int e = tid; e < 2 * Mh * VB; e += 256) {
+    const int hh = e / (Mh * VB), mc = e % (Mh * VB);
+    const int m = mc / VB, c = mc % VB;
     T ar = 0, ai = 0;
-    for (int u = 0; u < PH; ++u) {
-      const cx<T> w = twH[(u * m) & (PH - 1)];   // e^{-2 pi i um/PH}; use its conjugate
+    for (int u = hh * HU; u < (hh + 1) * HU; ++u) {
+      const cx<T> w = sH[(u * m) & (PH - 1)];   // e^{-2 pi i um/PH}; use its conjugate
       const cx<T> x = X[u * VB + c];
       ar += x.x * w.x + x.y * w.y;
       ai += x.y * w.x - x.x * w.y;
     }
     t[e] = mk<T>(ar, ai);
   }
+  __syncthreads();
+  for (int e = tid; e < Mh * VB; e += 256) t[e] = cadd<T>(t[e], t[Mh * VB + e]);
   __syncthreads();
   const T invP = (T)1 / (T)(PH * PW);
   T* out = apart + ((size_t)k * nvb + vb) * Mh * Mw;
@@ -395,7 +679,7 @@ __global__ __launch_bounds__(256) void k_vstep_alpha(const cx<T>* __restrict__ d
     for (int c = 0; c < nv; ++c) {
       const int v = v0 + c;
       const T cv = (v == 0 || 2 * v == PW) ? (T)1 : (T)2;
-      const cx<T> w = twW[(v * n) & (PW - 1)];
+      const cx<T> w = sW[(v * n) & (PW - 1)];
       const cx<T> tv = t[m * VB + c];
       acc += cv * (tv.x * w.x + tv.y * w.y);   // Re(t * conj(w))
     }
@@ -414,19 +698,24 @@ __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d
                                                      const cx<T>* __restrict__ twH,
                                                      const cx<T>* __restrict__ twW, int PH, int PW,
                                                      int Mh, int Mw, T rho_d, int first) {
+  constexpr int VB = vblock<T>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* alpha = reinterpret_cast<T*>(smem_raw);                        // [Mh*Mw]
   cx<T>* rr = reinterpret_cast<cx<T>*>(smem_raw + (((size_t)Mh * Mw * sizeof(T) + 15) & ~(size_t)15));
   __shared__ T red[256];
+  __shared__ cx<T> sH[MAXF], sW[MAXF];
   const int WC = PW / 2 + 1, Pf = PH * WC;
   const int vb = blockIdx.x, k = blockIdx.y, nvb = gridDim.x;
   const int v0 = vb * VB, nv = min(VB, WC - v0);
   const int tid = threadIdx.x;
   const int MM = Mh * Mw;
+  for (int i = tid; i < PH; i += 256) sH[i] = twH[i];
+  for (int i = tid; i < PW; i += 256) sW[i] = twW[i];
   const T* ap = apart + (size_t)k * nvb * MM;
   T ss = 0;
   for (int e = tid; e < MM; e += 256) {
     T a = 0;
+#pragma unroll 8
     for (int j = 0; j < nvb; ++j) a += ap[(size_t)j * MM + e];
     alpha[e] = a;
     ss += a * a;
@@ -452,7 +741,7 @@ __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d
     if (c < nv) {
       const int v = v0 + c;
       for (int n = 0; n < Mw; ++n) {
-        const cx<T> w = twW[(v * n) & (PW - 1)];
+        const cx<T> w = sW[(v * n) & (PW - 1)];
         const T x = alpha[m * Mw + n];
         ar += x * w.x;
         ai += x * w.y;
@@ -462,23 +751,34 @@ __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d
   }
   __syncthreads();
   const size_t base = (size_t)k * Pf;
-  for (int e = tid; e < PH * VB; e += 256) {
-    const int u = e / VB, c = e % VB;
-    if (c >= nv) continue;
+  constexpr int NQ = MAXF * VB / 256;
+  cx<T> dq[NQ], tq[NQ], gq[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {   // all loads issued before any use
+    const int e = tid + q * 256, u = e / VB, c = e % VB;
+    dq[q] = tq[q] = gq[q] = mk<T>(0, 0);
+    if (e < PH * VB && c < nv) {
+      const size_t idx = base + (size_t)u * WC + v0 + c;
+      dq[q] = d[idx];
+      if (!first) tq[q] = Th[idx];
+      gq[q] = G[idx];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + q * 256, u = e / VB, c = e % VB;
+    if (e >= PH * VB || c >= nv) continue;
     T ar = 0, ai = 0;
     for (int m = 0; m < Mh; ++m) {
-      const cx<T> w = twH[(u * m) & (PH - 1)];
+      const cx<T> w = sH[(u * m) & (PH - 1)];
       const cx<T> x = rr[m * VB + c];
       ar += x.x * w.x - x.y * w.y;
       ai += x.x * w.y + x.y * w.x;
     }
     const size_t idx = base + (size_t)u * WC + v0 + c;
-    const cx<T> dv = d[idx];
-    cx<T> th = first ? mk<T>(0, 0) : Th[idx];
-    th = mk<T>(th.x + dv.x - ar, th.y + dv.y - ai);
+    const cx<T> th = mk<T>(tq[q].x + dq[q].x - ar, tq[q].y + dq[q].y - ai);
     Th[idx] = th;
-    const cx<T> gv = G[idx];
-    rhs[idx] = mk<T>(gv.x + rho_d * (ar - th.x), gv.y + rho_d * (ai - th.y));
+    rhs[idx] = mk<T>(gq[q].x + rho_d * (ar - th.x), gq[q].y + rho_d * (ai - th.y));
   }
 }
 
@@ -548,14 +848,15 @@ __global__ void k_obj_final(const double* __restrict__ rpart, int nr, const doub
   if (threadIdx.x == 0) out[b] = 0.5 * a[0] * invP + lam * c[0];
 }
 
-// C_p = I / rho_d in R-form for every frequency.
+// C_p = I / rho_d for every frequency, in the per-frequency layout (pitch K + 1, stride fs).
 template <typename T>
-__global__ void k_c_init(T* __restrict__ Cm, int K, int Pf, T inv_rho_d) {
-  const size_t kk = (size_t)K * K;
-  const size_t n = kk * Pf;
+__global__ void k_c_init(T* __restrict__ Cm, int K, int Pf, int fs, T inv_rho_d) {
+  const size_t n = (size_t)fs * Pf;
+  const int ld = K + 1;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-    const size_t r = e % kk;
-    Cm[e] = (r / K == r % K) ? inv_rho_d : (T)0;
+    const int r = (int)(e % fs);
+    const int i = r / ld, j = r % ld;
+    Cm[e] = (i < K && i == j) ? inv_rho_d : (T)0;
   }
 }
 

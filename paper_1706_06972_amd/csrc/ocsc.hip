@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -37,7 +38,9 @@ struct ocsc_ctx {
   int Jz = 10, Jd = 10, maxB = 1, prec = OCSC_FP64;
   size_t sr = 8;   // bytes per real
   int nvb = 0;     // V-step column blocks
-  int fpb = 1;     // frequencies per workgroup in the D-step sweep
+  int fpb = 1;     // frequencies solved side by side by one D-step workgroup
+  int fs = 0;      // reals per frequency of C (K rows of pitch K+1, 16-byte multiple)
+  int sweep_wgs = 0, slots_per_wg = 0;
   size_t sweep_smem = 0, vapply_smem = 0;
   // runtime
   int device = 0;
@@ -208,7 +211,7 @@ int launch_code_plane(ocsc_ctx* c, int nplanes, T* Uout, int first, int last) {
 template <typename T>
 int launch_zstep(ocsc_ctx* c, int B, int first) {
   ProfScope ps(c, OCSC_KC_ZSTEP);
-  dim3 grid((c->Pf + 63) / 64, B);
+  dim3 grid((c->Pf + ZF - 1) / ZF, B);
   const cx<T>* Dh = (const cx<T>*)c->Dh;
   const T* gam = (const T*)c->gam;
   const cx<T>* xh = (const cx<T>*)c->xh;
@@ -216,17 +219,15 @@ int launch_zstep(ocsc_ctx* c, int B, int first) {
   cx<T>* Zh = (cx<T>*)c->Zh;
   const int K = c->K, Pf = c->Pf;
   if (K <= 16)
-    hipLaunchKernelGGL((k_code_zstep<T, 4, 4>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 1>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
   else if (K <= 32)
-    hipLaunchKernelGGL((k_code_zstep<T, 4, 8>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 2>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
   else if (K <= 64)
-    hipLaunchKernelGGL((k_code_zstep<T, 4, 16>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
-  else if (K <= 128 && sizeof(T) == 4)
-    hipLaunchKernelGGL((k_code_zstep<T, 4, 32>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 4>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
   else if (K <= 128)
-    hipLaunchKernelGGL((k_code_zstep<T, 8, 16>), grid, dim3(512), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 8>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
   else if (K <= 256)
-    hipLaunchKernelGGL((k_code_zstep<T, 16, 16>), grid, dim3(1024), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 16>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
   else
     return fail(c, OCSC_E_UNSUPPORTED, "code Z-step supports K <= 256");
   LAUNCHED(c);
@@ -246,12 +247,12 @@ int launch_gamma(ocsc_ctx* c) {
 template <typename T>
 int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* dout, void* gam_out, int cls) {
   ProfScope ps(c, cls);
-  const int nb = (c->Pf + c->fpb - 1) / c->fpb;
   const int reverse = c->serpentine ? (int)(c->sweep_count & 1u) : 0;
   c->sweep_count++;
-  hipLaunchKernelGGL((k_dict_sweep<T>), dim3(nb), dim3(256), c->sweep_smem, c->stream, (T*)c->Cm,
+  hipLaunchKernelGGL((k_dict_sweep<T>), dim3(c->sweep_wgs), dim3(256), c->sweep_smem, c->stream, (T*)c->Cm,
                      (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh, nfold,
-                     (cx<T>*)dout, (T*)gam_out, (T)c->rho, c->K, c->Pf, c->fpb, reverse);
+                     (cx<T>*)dout, (T*)gam_out, (T)c->rho, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg,
+                     reverse);
   LAUNCHED(c);
   return OCSC_OK;
 }
@@ -348,12 +349,19 @@ int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* ou
 
 template <typename T>
 int init_state_t(ocsc_ctx* c) {
-  const size_t n = (size_t)c->Pf * c->K * c->K;
-  hipLaunchKernelGGL((k_c_init<T>), dim3(2048), dim3(256), 0, c->stream, (T*)c->Cm, c->K, c->Pf,
+  hipLaunchKernelGGL((k_c_init<T>), dim3(2048), dim3(256), 0, c->stream, (T*)c->Cm, c->K, c->Pf, c->fs,
                      (T)(1.0 / c->rho_d));
   LAUNCHED(c);
-  (void)n;
   return launch_gamma<T>(c);
+}
+
+// Packed [Pf][K][K] reals <-> the internal per-frequency layout of C.
+template <typename T>
+int cinv_layout_t(ocsc_ctx* c, const void* src, void* dst, int to_internal) {
+  hipLaunchKernelGGL((k_cinv_layout<T>), dim3(2048), dim3(256), 0, c->stream, (const T*)src, (T*)dst, c->K, c->Pf,
+                     c->fs, to_internal);
+  LAUNCHED(c);
+  return OCSC_OK;
 }
 
 void free_all(ocsc_ctx* c) {
@@ -448,16 +456,18 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   if (pad_h > 128 || pad_w > 128)
     return fail(nullptr, OCSC_E_UNSUPPORTED, "this build has plane kernels for grids up to 128 x 128");
   const size_t sr = o.precision == OCSC_FP64 ? 8 : 4;
-  // D-step sweep: C_p of K x (K+1) reals must fit in LDS
+  // D-step sweep: C_p (K rows of pitch K+1) must fit in LDS; a slot of fpb
+  // frequencies must fit the prefetch registers (256 threads x SWEEP_MAXV x 16 B)
+  const int vr = (int)(16 / sr);
+  const int fs = (K * (K + 1) + vr - 1) / vr * vr;
   int fpb = 1;
   while (fpb < 16 && 256 / (fpb * 2) >= K) fpb *= 2;
-  auto sweep_bytes = [&](int f) {
-    return (((size_t)f * K * (K + 1) * sr + 15) & ~(size_t)15) + (size_t)f * 7 * K * 2 * sr;
-  };
+  auto sweep_bytes = [&](int f) { return (size_t)f * fs * sr + (size_t)f * SWEEP_VECS * K * 2 * sr; };
   const size_t max_lds = 160 * 1024 - 1024;
-  if (sweep_bytes(1) > max_lds)
+  const size_t max_slot = (size_t)256 * SWEEP_MAXV * 16;
+  if (sweep_bytes(1) > max_lds || (size_t)fs * sr > max_slot)
     return fail(nullptr, OCSC_E_UNSUPPORTED, "K too large for the LDS-resident D-step of this precision");
-  while (fpb > 1 && sweep_bytes(fpb) > 64 * 1024) fpb /= 2;
+  while (fpb > 1 && (sweep_bytes(fpb) > 64 * 1024 || (size_t)fpb * fs * sr > max_slot)) fpb /= 2;
 
   ocsc_ctx* c = new (std::nothrow) ocsc_ctx();
   if (!c) return fail(nullptr, OCSC_E_OOM, "host allocation failed");
@@ -467,10 +477,21 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   c->rho_d = o.rho_dict > 0 ? o.rho_dict : rho * c->P;
   c->Jz = o.iters_code; c->Jd = o.iters_dict; c->maxB = o.max_batch; c->prec = o.precision;
   c->sr = sr;
-  c->nvb = (c->Wc + VB - 1) / VB;
+  const int vb = sr == 8 ? vblock<double>() : vblock<float>();
+  c->nvb = (c->Wc + vb - 1) / vb;
   c->fpb = fpb;
+  c->fs = fs;
   c->sweep_smem = sweep_bytes(fpb);
-  c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * VB * 2 * sr;
+  {
+    // one round of workgroups over the chip; each walks a run of slots
+    const int nslots = (c->Pf + fpb - 1) / fpb;
+    int occ = (int)((160 * 1024) / c->sweep_smem);
+    occ = occ < 1 ? 1 : (occ > 8 ? 8 : occ);
+    const int target = 256 * occ;
+    c->slots_per_wg = (nslots + target - 1) / target;
+    c->sweep_wgs = (nslots + c->slots_per_wg - 1) / c->slots_per_wg;
+  }
+  c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * vb * 2 * sr;
   if (const char* s = std::getenv("OCSC_SERPENTINE")) c->serpentine = std::atoi(s) != 0;
 
   auto bail = [&](int code, const std::string& m) {
@@ -505,7 +526,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   struct { void** p; size_t n; } allocs[] = {
       {&c->xh, B * Pf * sc},        {&c->Dh, K_ * Pf * sc},          {&c->gam, Pf * sr},
       {&c->gam2, Pf * sr},          {&c->S, B * K_ * Pf * sc},       {&c->Zh, B * K_ * Pf * sc},
-      {&c->W, B * K_ * c->P * sr},  {&c->G, K_ * Pf * sc},           {&c->Cm, Pf * K_ * K_ * sr},
+      {&c->W, B * K_ * c->P * sr},  {&c->G, K_ * Pf * sc},           {&c->Cm, Pf * (size_t)c->fs * sr},
       {&c->d, K_ * Pf * sc},        {&c->Th, K_ * Pf * sc},          {&c->rhs, K_ * Pf * sc},
       {&c->V, K_ * filt_h * filt_w * sr},
       {&c->apart, K_ * c->nvb * filt_h * filt_w * sr},
@@ -575,6 +596,7 @@ int ocsc_get_dictionary(ocsc_ctx* c, void* D) {
 int ocsc_code_update(ocsc_ctx* c, const void* x, int B, void* codes) {
   if (!c) return OCSC_E_INVALID_ARG;
   if (!x) return fail(c, OCSC_E_INVALID_ARG, "x_dev is NULL");
+  if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
   if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
   return c->sr == 8 ? code_update_t<double>(c, x, B, codes) : code_update_t<float>(c, x, B, codes);
 }
@@ -597,6 +619,7 @@ int ocsc_dict_update(ocsc_ctx* c) {
 int ocsc_objective(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {
   if (!c) return OCSC_E_INVALID_ARG;
   if (!x || !codes || !out) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
+  if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
   if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
   return c->sr == 8 ? objective_t<double>(c, x, codes, B, out) : objective_t<float>(c, x, codes, B, out);
 }
@@ -625,7 +648,12 @@ int ocsc_get_state(ocsc_ctx* c, int which, void* dst) {
     int rc = c->sr == 8 ? flush_fold<double>(c) : flush_fold<float>(c);
     if (rc) return rc;
   }
-  HIPX(c, hipMemcpyAsync(dst, state_ptr(c, which), n, hipMemcpyDeviceToDevice, c->stream));
+  if (which == OCSC_STATE_CINV) {
+    int rc = c->sr == 8 ? cinv_layout_t<double>(c, c->Cm, dst, 0) : cinv_layout_t<float>(c, c->Cm, dst, 0);
+    if (rc) return rc;
+  } else {
+    HIPX(c, hipMemcpyAsync(dst, state_ptr(c, which), n, hipMemcpyDeviceToDevice, c->stream));
+  }
   HIPX(c, hipStreamSynchronize(c->stream));
   return OCSC_OK;
 }
@@ -637,7 +665,12 @@ int ocsc_set_state(ocsc_ctx* c, int which, const void* src) {
     return fail(c, OCSC_E_INVALID_ARG, "bad state item or NULL src");
   c->pending_B = 0;
   c->fold_B = 0;
-  HIPX(c, hipMemcpyAsync(state_ptr(c, which), src, n, hipMemcpyDeviceToDevice, c->stream));
+  if (which == OCSC_STATE_CINV) {
+    int rc = c->sr == 8 ? cinv_layout_t<double>(c, src, c->Cm, 1) : cinv_layout_t<float>(c, src, c->Cm, 1);
+    if (rc) return rc;
+  } else {
+    HIPX(c, hipMemcpyAsync(state_ptr(c, which), src, n, hipMemcpyDeviceToDevice, c->stream));
+  }
   if (which == OCSC_STATE_DICT_HAT) {
     int rc = c->sr == 8 ? launch_gamma<double>(c) : launch_gamma<float>(c);
     if (rc) return rc;

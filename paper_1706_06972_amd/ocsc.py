@@ -67,6 +67,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise OSError(f"libocsc is not built ({path} missing); run `python -m paper_1706_06972_amd.build`")
+    # torch ships its own HIP runtime; importing it first makes the library's
+    # HIP calls resolve to that same runtime, so torch's device pointers and
+    # streams are valid handles for the library.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     sig = {
