@@ -425,26 +425,114 @@ __device__ __forceinline__ void herm_rank1(T* __restrict__ R, int K, int ld, con
   __syncthreads();
 }
 
+// Compile-time variants for a fixed K and group width TPG: the row pitch and
+// column chunk are constants, the column loop is unrolled, and every LDS
+// access is a base register plus an immediate offset.
+template <int KT, int TPG>
+struct HGeo {
+  static constexpr int LD = KT + 1;
+  static constexpr int RP = TPG >= 64 ? (KT + 63) / 64 * 64 : KT;   // row slots of a column chunk
+  static constexpr int NS0 = TPG / RP;
+  static constexpr int NS = NS0 < 1 ? 1 : (NS0 > 4 ? 4 : NS0);        // column chunks
+  static constexpr int CH = (KT + NS - 1) / NS;                       // columns per chunk
+  static constexpr int TASKS = RP * NS;
+};
+
+template <typename T, int KT, int TPG, int NX>
+__device__ __forceinline__ void herm_matvec_ct(const T* __restrict__ R, const cx<T>* const (&x)[NX],
+                                               cx<T>* const (&y)[NX], cx<T>* part, int lt) {
+  using H = HGeo<KT, TPG>;
+  for (int task = lt; task < H::TASKS; task += TPG) {
+    const int h = task / H::RP, i = task % H::RP;
+    if (i < KT) {
+      const int j0 = h * H::CH;
+      const T* rowp = R + i * H::LD + j0;   // R[i][j0 + jj]
+      const T* colp = R + j0 * H::LD + i;   // R[j0 + jj][i]
+      T ar[NX], ai[NX];
+#pragma unroll
+      for (int n = 0; n < NX; ++n) ar[n] = ai[n] = 0;
+#pragma unroll
+      for (int jj = 0; jj < H::CH; ++jj) {
+        if (H::CH * H::NS != KT && j0 + jj >= KT) break;
+        const T p = rowp[jj], q = colp[jj * H::LD];
+        const bool up = j0 + jj > i;
+        const T a = up ? p : q;
+        const T b = up ? q : -p;
+#pragma unroll
+        for (int n = 0; n < NX; ++n) {
+          const cx<T> xv = x[n][j0 + jj];
+          ar[n] += a * xv.x - b * xv.y;
+          ai[n] += a * xv.y + b * xv.x;
+        }
+      }
+      if (i >= j0 && i < j0 + H::CH) {   // the loop took Im C_ii = -R[i][i]; it is zero
+        const T dg = R[i * H::LD + i];
+#pragma unroll
+        for (int n = 0; n < NX; ++n) {
+          const cx<T> xv = x[n][i];
+          ar[n] -= dg * xv.y;
+          ai[n] += dg * xv.x;
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < NX; ++n) part[(n * H::NS + h) * KT + i] = mk<T>(ar[n], ai[n]);
+    }
+  }
+  __syncthreads();
+  for (int i = lt; i < KT; i += TPG) {
+#pragma unroll
+    for (int n = 0; n < NX; ++n) {
+      cx<T> sum = part[(n * H::NS) * KT + i];
+#pragma unroll
+      for (int h = 1; h < H::NS; ++h) sum = cadd<T>(sum, part[(n * H::NS + h) * KT + i]);
+      y[n][i] = sum;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int KT, int TPG>
+__device__ __forceinline__ void herm_rank1_ct(T* __restrict__ R, const cx<T>* v, T beta, int lt) {
+  using H = HGeo<KT, TPG>;
+  for (int task = lt; task < H::TASKS; task += TPG) {
+    const int h = task / H::RP, i = task % H::RP;
+    if (i < KT) {
+      const int j0 = h * H::CH;
+      const cx<T> vi = v[i];
+      T* rowp = R + i * H::LD + j0;
+#pragma unroll
+      for (int jj = 0; jj < H::CH; ++jj) {
+        if (H::CH * H::NS != KT && j0 + jj >= KT) break;
+        const cx<T> vj = v[j0 + jj];
+        const T re = vi.x * vj.x + vi.y * vj.y, im = vj.y * vi.x - vj.x * vi.y;
+        rowp[jj] -= beta * (j0 + jj >= i ? re : im);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // 16-byte vectors of one slot (fpb consecutive frequencies) held by one thread.
 constexpr int SWEEP_MAXV = 12;
 constexpr int SWEEP_VECS = 12;   // complex K-vectors of LDS per frequency group
 
-template <typename T>
-__device__ __forceinline__ void slot_fetch(v4f (&reg)[SWEEP_MAXV], const v4f* __restrict__ src, int nvec,
-                                           int tid) {
+// The prefetch is straight-line code: every lane loads (indices past the slot
+// are clamped to its last vector) and every lane stores (past the slot into a
+// private dummy vector).  Guarded loads and stores would leave the compiler
+// unable to prove that the previous slot's loads into the same registers have
+// landed, and it would then wait for all of them before each new load.
+template <int NV_MAX>
+__device__ __forceinline__ void slot_fetch(v4f (&reg)[NV_MAX], const v4f* __restrict__ src, int nvec, int tid) {
 #pragma unroll
-  for (int v = 0; v < SWEEP_MAXV; ++v) {
-    const int e = tid + v * 256;
-    if (e < nvec) reg[v] = src[e];
-  }
+  for (int v = 0; v < NV_MAX; ++v) reg[v] = src[min(tid + v * 256, nvec - 1)];
 }
 
-template <typename T>
-__device__ __forceinline__ void slot_stage(const v4f (&reg)[SWEEP_MAXV], v4f* dst, int nvec, int tid) {
+template <int NV_MAX>
+__device__ __forceinline__ void slot_stage(const v4f (&reg)[NV_MAX], v4f* dst, int nvec, int tid, v4f* dummy) {
 #pragma unroll
-  for (int v = 0; v < SWEEP_MAXV; ++v) {
+  for (int v = 0; v < NV_MAX; ++v) {
     const int e = tid + v * 256;
-    if (e < nvec) dst[e] = reg[v];
+    *(e < nvec ? dst + e : dummy) = reg[v];
   }
 }
 
@@ -463,14 +551,20 @@ __device__ __forceinline__ void slot_stage(const v4f (&reg)[SWEEP_MAXV], v4f* ds
 // (the first DictOCSC iterate, from V = Theta = 0).  dout == nullptr: fold only.
 // gam_out (optional): 1 / (rho + ||d_p||^2), used by the next code update.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* __restrict__ G,
+template <typename T, int KT, int FPB>
+__global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>* __restrict__ G,
                                                     const cx<T>* __restrict__ rhs,
                                                     const cx<T>* __restrict__ Zh,
                                                     const cx<T>* __restrict__ xh, int nfold,
                                                     cx<T>* __restrict__ dout, T* __restrict__ gam_out,
-                                                    T rho, int K, int Pf, int fpb, int fs, int slots_per_wg,
+                                                    T rho, int K_, int Pf, int fpb_, int fs_, int slots_per_wg,
                                                     int reverse) {
+  // KT > 0: K and fpb fixed at compile time (the arguments then equal them)
+  constexpr bool CT = KT > 0;
+  constexpr int VR = 16 / (int)sizeof(T);
+  const int K = CT ? KT : K_;
+  const int fpb = CT ? FPB : fpb_;
+  const int fs = CT ? (KT * (KT + 1) + VR - 1) / VR * VR : fs_;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ld = K + 1;
   const int tpg = 256 / fpb;
@@ -496,8 +590,14 @@ __global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* _
   const int s_end = min(nslots, s_begin + slots_per_wg);
   const int nvec = (int)((size_t)fpb * fs * sizeof(T) / 16);
   const bool plain = dout && nfold == 0;
-  v4f reg[SWEEP_MAXV];
+  // 16-byte vectors per thread for one slot (compile-time for a fixed K)
+  constexpr int NVM = CT ? ((FPB * ((KT * (KT + 1) + VR - 1) / VR * VR) * (int)sizeof(T) / 16) + 255) / 256
+                         : SWEEP_MAXV;
+  v4f reg[NVM];
+  __shared__ v4f dummy4[256];
+  __shared__ cx<T> dummyc[256];
   cx<T> rpre = mk<T>(0, 0);
+  const int kl = lt < K ? lt : K - 1;   // clamped filter index of this thread's rhs element
 
   auto slot_of = [&](int s) { return reverse ? nslots - 1 - s : s; };
   auto slot_vecs = [&](int sl) {
@@ -505,9 +605,9 @@ __global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* _
   };
   if (s_begin < s_end) {
     const int sl = slot_of(s_begin);
-    slot_fetch<T>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sl * fpb * fs), slot_vecs(sl), tid);
-    const int p = sl * fpb + g;
-    if (plain && lt < K && p < Pf) rpre = rhs[(size_t)lt * Pf + p];
+    slot_fetch<NVM>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sl * fpb * fs), slot_vecs(sl), tid);
+    const int p = min(sl * fpb + g, Pf - 1);
+    if (plain) rpre = rhs[(size_t)kl * Pf + p];
   }
   for (int s = s_begin; s < s_end; ++s) {
     const int sl = slot_of(s);
@@ -515,17 +615,23 @@ __global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* _
     const bool ok = p < Pf;
     const int nv = slot_vecs(sl);
     __syncthreads();   // previous slot finished with LDS
-    slot_stage<T>(reg, reinterpret_cast<v4f*>(Rall), nv, tid);
-    if (plain && lt < K) xv[lt] = rpre;
+    slot_stage<NVM>(reg, reinterpret_cast<v4f*>(Rall), nv, tid, dummy4 + tid);
+    if (plain) *(lt < K ? xv + lt : dummyc + tid) = rpre;
     __syncthreads();
     if (s + 1 < s_end) {   // next slot's C and right-hand side are in flight during this slot
       const int sn = slot_of(s + 1);
-      slot_fetch<T>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sn * fpb * fs), slot_vecs(sn), tid);
-      const int pn = sn * fpb + g;
-      if (plain && lt < K && pn < Pf) rpre = rhs[(size_t)lt * Pf + pn];
+      slot_fetch<NVM>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sn * fpb * fs), slot_vecs(sn), tid);
+      const int pn = min(sn * fpb + g, Pf - 1);
+      if (plain) rpre = rhs[(size_t)kl * Pf + pn];
     }
     if (plain) {
-      herm_matvec<T>(R, K, ld, xv, yv, part, lt, tpg, ns);
+      if constexpr (CT) {
+        const cx<T>* const xs[1] = {xv};
+        cx<T>* const ys[1] = {yv};
+        herm_matvec_ct<T, KT, 256 / FPB, 1>(R, xs, ys, part, lt);
+      } else {
+        herm_matvec<T>(R, K, ld, xv, yv, part, lt, tpg, ns);
+      }
     } else if (nfold == 1) {
       // one sample: v = C u and g = C G_new in one pass; d = g - beta v (v^H G_new)
       if (ok && lt < K) {
@@ -536,7 +642,13 @@ __global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* _
         yv[lt] = gn;
       }
       __syncthreads();
-      herm_matvec2<T>(R, K, ld, xv, yv, vv, gv, part, lt, tpg, ns);
+      if constexpr (CT) {
+        const cx<T>* const xs[2] = {xv, yv};
+        cx<T>* const ys[2] = {vv, gv};
+        herm_matvec_ct<T, KT, 256 / FPB, 2>(R, xs, ys, part, lt);
+      } else {
+        herm_matvec2<T>(R, K, ld, xv, yv, vv, gv, part, lt, tpg, ns);
+      }
       T su = 0, tr = 0, ti = 0;
       if (lt < K) {
         const cx<T> u = xv[lt], v = vv[lt], gn = yv[lt];
@@ -553,7 +665,8 @@ __global__ __launch_bounds__(256) void k_dict_sweep(T* __restrict__ Cm, cx<T>* _
         const cx<T> tv = mk<T>(beta * tr, beta * ti);
         yv[lt] = csub<T>(gv[lt], cmul<T>(v, tv));
       }
-      herm_rank1<T>(R, K, ld, vv, beta, lt, tpg, ns);
+      if constexpr (CT) herm_rank1_ct<T, KT, 256 / FPB>(R, vv, beta, lt);
+      else herm_rank1<T>(R, K, ld, vv, beta, lt, tpg, ns);
       v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
       const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
       for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
@@ -779,6 +892,137 @@ __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d
     const cx<T> th = mk<T>(tq[q].x + dq[q].x - ar, tq[q].y + dq[q].y - ai);
     Th[idx] = th;
     rhs[idx] = mk<T>(gq[q].x + rho_d * (ar - th.x), gq[q].y + rho_d * (ai - th.y));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused V-step (Proposition 2), one workgroup per filter k, for filters of at
+// most VF x VF taps.  With X = d_k + Theta_k held in LDS:
+//   t[m][v]  = sum_u X[u][v] e^{+2 pi i u m / PH}                   (m < M_h)
+//   alpha    = (1/P) Re sum_v c_v t[m][v] e^{+2 pi i v n / PW}        (the crop of
+//              the real inverse DFT; c_v = 1 at v = 0, PW/2 and 2 otherwise)
+//   V_k      = alpha / max(||alpha||, 1)
+//   r[m][v]  = sum_n V_k[m][n] e^{-2 pi i v n / PW};  F(V)[u][v] = sum_m r[m][v] e^{-2 pi i u m / PH}
+//   Theta   <- X - F(V)  (= Theta + d - F(V));  rhs <- G + rho_d (F(V) - Theta)
+// No other workgroup is involved, so the whole step is one launch.
+// ---------------------------------------------------------------------------
+constexpr int VF = 16;
+
+template <typename T, int PH, int PW, int NT, int NQ>
+__global__ __launch_bounds__(NT) void k_vstep_filter(const cx<T>* __restrict__ d, cx<T>* __restrict__ Th,
+                                                     const cx<T>* __restrict__ G, cx<T>* __restrict__ rhs,
+                                                     T* __restrict__ V, const cx<T>* __restrict__ twH,
+                                                     const cx<T>* __restrict__ twW, int Mh, int Mw, T rho_d,
+                                                     int first) {
+  using Gm = PlaneGeom<PH, PW>;
+  constexpr int WC = Gm::WC, PF = Gm::PF;
+  constexpr int FPT = (PF + NT - 1) / NT;   // frequencies per thread in the update
+  __shared__ __align__(16) cx<T> X[PF];
+  __shared__ cx<T> tq[NQ * VF * WC];       // partial t over u-quarters; later r
+  __shared__ cx<T> sH[PH], sW[PW];
+  __shared__ T al[VF * VF];
+  __shared__ T red[NT / 64];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const size_t base = (size_t)k * PF;
+  // G of this thread's frequencies is fetched now and used at the end
+  cx<T> gq[FPT];
+#pragma unroll
+  for (int j = 0; j < FPT; ++j) {
+    const int e = min(tid + j * NT, PF - 1);
+    gq[j] = G[base + e];
+  }
+  load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
+  {
+    cx<T> dq[FPT], tqv[FPT];
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int e = min(tid + j * NT, PF - 1);
+      dq[j] = d[base + e];
+      tqv[j] = first ? mk<T>(0, 0) : Th[base + e];
+    }
+#pragma unroll
+    for (int j = 0; j < FPT; ++j) {
+      const int e = tid + j * NT;
+      if (PF % NT == 0 || e < PF) X[e] = cadd<T>(dq[j], tqv[j]);
+    }
+  }
+  __syncthreads();
+  // t over NQ slices of u
+  constexpr int US = PH / NQ;
+  for (int task = tid; task < NQ * Mh * WC; task += NT) {
+    const int q = task / (Mh * WC), r = task - q * (Mh * WC);
+    const int m = r / WC, v = r - m * WC;
+    T ar = 0, ai = 0;
+#pragma unroll 8
+    for (int u = q * US; u < (q + 1) * US; ++u) {
+      const cx<T> w = sH[(u * m) & (PH - 1)];   // e^{-2 pi i um/PH}; its conjugate is used
+      const cx<T> x = X[u * WC + v];
+      ar += x.x * w.x + x.y * w.y;
+      ai += x.y * w.x - x.x * w.y;
+    }
+    tq[(q * VF + m) * WC + v] = mk<T>(ar, ai);
+  }
+  __syncthreads();
+  const T invP = (T)1 / (T)(PH * PW);
+  T ss = 0;
+  for (int task = tid; task < Mh * Mw; task += NT) {
+    const int m = task / Mw, n = task - m * Mw;
+    T acc = 0;
+    for (int v = 0; v < WC; ++v) {
+      cx<T> tv = tq[m * WC + v];
+#pragma unroll
+      for (int q = 1; q < NQ; ++q) tv = cadd<T>(tv, tq[(q * VF + m) * WC + v]);
+      const cx<T> w = sW[(v * n) & (PW - 1)];
+      const T cv = (v == 0 || 2 * v == PW) ? (T)1 : (T)2;
+      acc += cv * (tv.x * w.x + tv.y * w.y);   // Re(t * conj(w))
+    }
+    acc *= invP;
+    al[task] = acc;
+    ss += acc * acc;
+  }
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = ss;
+  __syncthreads();
+  T nrm2 = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) nrm2 += red[w];
+  const T nrm = sqrt(nrm2);
+  const T scale = (T)1 / (nrm > (T)1 ? nrm : (T)1);
+  for (int task = tid; task < Mh * Mw; task += NT) {
+    const T vv = al[task] * scale;
+    al[task] = vv;
+    V[(size_t)k * Mh * Mw + task] = vv;
+  }
+  __syncthreads();
+  // r[m][v] = sum_n V[m][n] e^{-2 pi i v n / PW}   (into tq)
+  for (int task = tid; task < Mh * WC; task += NT) {
+    const int m = task / WC, v = task - m * WC;
+    T ar = 0, ai = 0;
+    for (int n = 0; n < Mw; ++n) {
+      const cx<T> w = sW[(v * n) & (PW - 1)];
+      const T x = al[m * Mw + n];
+      ar += x * w.x;
+      ai += x * w.y;
+    }
+    tq[m * WC + v] = mk<T>(ar, ai);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < FPT; ++j) {
+    const int e = tid + j * NT;
+    if (PF % NT != 0 && e >= PF) continue;
+    const int u = e / WC, v = e - u * WC;
+    T ar = 0, ai = 0;
+    for (int m = 0; m < Mh; ++m) {
+      const cx<T> w = sH[(u * m) & (PH - 1)];
+      const cx<T> x = tq[m * WC + v];
+      ar += x.x * w.x - x.y * w.y;
+      ai += x.x * w.y + x.y * w.x;
+    }
+    const cx<T> xv = X[e];
+    const cx<T> th = mk<T>(xv.x - ar, xv.y - ai);
+    Th[base + e] = th;
+    rhs[base + e] = mk<T>(gq[j].x + rho_d * (ar - th.x), gq[j].y + rho_d * (ai - th.y));
   }
 }
 

@@ -42,6 +42,7 @@ struct ocsc_ctx {
   int fs = 0;      // reals per frequency of C (K rows of pitch K+1, 16-byte multiple)
   int sweep_wgs = 0, slots_per_wg = 0;
   size_t sweep_smem = 0, vapply_smem = 0;
+  bool vstep_fused = false;   // one workgroup per filter (filters up to 16 x 16)
   // runtime
   int device = 0;
   hipStream_t stream = nullptr;
@@ -249,17 +250,67 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* dout, void* gam_
   ProfScope ps(c, cls);
   const int reverse = c->serpentine ? (int)(c->sweep_count & 1u) : 0;
   c->sweep_count++;
-  hipLaunchKernelGGL((k_dict_sweep<T>), dim3(c->sweep_wgs), dim3(256), c->sweep_smem, c->stream, (T*)c->Cm,
-                     (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh, nfold,
-                     (cx<T>*)dout, (T*)gam_out, (T)c->rho, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg,
-                     reverse);
+#define OCSC_SWEEP(KT, FPB)                                                                                  \
+  hipLaunchKernelGGL((k_dict_sweep<T, KT, FPB>), dim3(c->sweep_wgs), dim3(256), c->sweep_smem, c->stream,     \
+                     (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh,     \
+                     nfold, (cx<T>*)dout, (T*)gam_out, (T)c->rho, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg, \
+                     reverse)
+  // compile-time specialisations for the common filter counts; the generic kernel otherwise
+  if (sizeof(T) == 4 && c->K == 100 && c->fpb == 1) OCSC_SWEEP(100, 1);
+  else if (sizeof(T) == 4 && c->K == 16 && c->fpb == 16) OCSC_SWEEP(16, 16);
+  else if (sizeof(T) == 8 && c->K == 16 && c->fpb == 8) OCSC_SWEEP(16, 8);
+  else OCSC_SWEEP(0, 0);
+#undef OCSC_SWEEP
   LAUNCHED(c);
   return OCSC_OK;
+}
+
+// LDS of the fused V-step for one plane size and real type (bytes)
+template <typename T, int PH, int PW, int NQ>
+constexpr size_t vstep_filter_lds() {
+  using Gm = PlaneGeom<PH, PW>;
+  return sizeof(cx<T>) * ((size_t)Gm::PF + (size_t)NQ * VF * Gm::WC + PH + PW) + sizeof(T) * (VF * VF + 16);
+}
+template <typename T> constexpr int vstep_nq() { return sizeof(T) == 4 ? 4 : 2; }
+
+template <typename T>
+bool vstep_fused_ok(int ph, int pw, int mh, int mw) {
+  if (mh > VF || mw > VF) return false;
+  size_t lds = 0;
+  switch (ph * 1000 + pw) {
+#define X(A, B) \
+  case A * 1000 + B: lds = vstep_filter_lds<T, A, B, vstep_nq<T>()>(); break;
+    OCSC_SIZE_CASES(X)
+#undef X
+    default: return false;
+  }
+  return lds <= 150 * 1024;
 }
 
 template <typename T>
 int launch_vstep(ocsc_ctx* c, int first) {
   ProfScope ps(c, OCSC_KC_VSTEP);
+  if (c->vstep_fused) {
+    const cx<T>* tH = (const cx<T>*)c->twH;
+    const cx<T>* tW = (const cx<T>*)c->twW;
+    constexpr int NQ = vstep_nq<T>();
+    switch (c->Ph * 1000 + c->Pw) {
+#define X(A, B)                                                                                                 \
+  case A * 1000 + B:                                                                                            \
+    if constexpr (vstep_filter_lds<T, A, B, NQ>() <= 150 * 1024) {                                              \
+      hipLaunchKernelGGL((k_vstep_filter<T, A, B, 1024, NQ>), dim3(c->K), dim3(1024), 0, c->stream,            \
+                         (const cx<T>*)c->d, (cx<T>*)c->Th, (const cx<T>*)c->G, (cx<T>*)c->rhs, (T*)c->V, tH, tW, \
+                         c->Mh, c->Mw, (T)c->rho_d, first);                                                     \
+    }                                                                                                           \
+    break;
+      OCSC_SIZE_CASES(X)
+#undef X
+      default:
+        return fail(c, OCSC_E_UNSUPPORTED, "no V-step kernel for this grid");
+    }
+    LAUNCHED(c);
+    return OCSC_OK;
+  }
   dim3 grid(c->nvb, c->K);
   hipLaunchKernelGGL((k_vstep_alpha<T>), grid, dim3(256), 0, c->stream, (const cx<T>*)c->d,
                      (const cx<T>*)c->Th, (T*)c->apart, (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph,
@@ -493,6 +544,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   }
   c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * vb * 2 * sr;
   if (const char* s = std::getenv("OCSC_SERPENTINE")) c->serpentine = std::atoi(s) != 0;
+  c->vstep_fused = sr == 8 ? vstep_fused_ok<double>(pad_h, pad_w, filt_h, filt_w)
+                           : vstep_fused_ok<float>(pad_h, pad_w, filt_h, filt_w);
 
   auto bail = [&](int code, const std::string& m) {
     g_init_error = m;
@@ -511,13 +564,13 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     c->own_stream = true;
   }
   if (c->sweep_smem > 64 * 1024) {
-    if (sr == 8)
-      e = hipFuncSetAttribute((const void*)k_dict_sweep<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)c->sweep_smem);
-    else
-      e = hipFuncSetAttribute((const void*)k_dict_sweep<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)c->sweep_smem);
-    if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    const void* fns[5] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>,
+                          (const void*)k_dict_sweep<float, 100, 1>, (const void*)k_dict_sweep<float, 16, 16>,
+                          (const void*)k_dict_sweep<double, 16, 8>};
+    for (const void* fn : fns) {
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->sweep_smem);
+      if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
   }
 
   const size_t sc = 2 * sr, K_ = K, Pf = c->Pf, B = c->maxB;
