@@ -16,6 +16,7 @@ the same workload on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,36 @@ sys.path.insert(0, ROOT)
 METRIC = "images/s coded+dict-updated (K=100, 128²) plain vs BF16/served; p99 latency"
 WORKLOAD = "ocsc_128x128_k100_f32"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1706_06972_amd", "csrc", "kernels.hpp")
+HBM_SUMMARY = os.path.join(ROOT, "profiles", f"{WORKLOAD}_hbm_bytes.md")
+
+
+def kernel_source_sha256() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per plain D-step launch from the committed counter summary.
+
+    The summary records the SHA-256 of the kernel source it was measured on;
+    if the source has changed since, the figure no longer describes this
+    kernel and None is returned.
+    """
+    if not os.path.exists(HBM_SUMMARY):
+        return None
+    vals = {}
+    with open(HBM_SUMMARY) as fh:
+        for line in fh:
+            if ":" in line and line.split(":", 1)[0].strip() in ("dstep_traffic_bytes_per_launch", "kernels_hpp_sha256"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernels_hpp_sha256") != kernel_source_sha256():
+        return None
+    try:
+        return int(float(vals["dstep_traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def dstep_bytes_per_launch(K: int, Pf: int, real_bytes: int) -> int:
@@ -147,7 +178,7 @@ def main():
     per_launch = dstep_bytes_per_launch(wl.K, Pf, 4)
     avg_s = dstep_avg_us * 1e-6
     achieved = per_launch / avg_s / 1e9
-    traffic = None
+    traffic = recorded_traffic()
     if args.traffic and os.path.exists(args.traffic):
         with open(args.traffic) as fh:
             traffic = json.load(fh).get("dstep_bytes_per_launch")

@@ -23,7 +23,8 @@
  *     must keep them alive until the call's work on the context stream has
  *     completed.  The library owns all learner state and workspace.
  *   - Asynchrony: calls enqueue work on the context stream and return without
- *     waiting, except ocsc_objective (copies B doubles to the host and waits),
+ *     waiting, except those that return values in host memory
+ *     (ocsc_objective, ocsc_objective_terms, ocsc_surrogate, ocsc_diagnostics),
  *     ocsc_sync, and the state getters/setters (which wait for their copy).
  *   - Errors: every call returns an ocsc_status.  Arguments and call order are
  *     validated before any device work, so validation errors never leave the
@@ -71,6 +72,14 @@ typedef struct {
 
 /* opts.flags: create a private non-blocking stream and ignore opts.stream. */
 #define OCSC_FLAG_OWN_STREAM 1
+/* opts.flags: also keep the history H_p = sum_i conj(z_ip) z_ip^T (Proposition 1)
+ * and the running sums of ||x_i||^2 and ||U_i||_1, so that ocsc_surrogate can
+ * evaluate the online objective.  Costs a second K x K real matrix per
+ * frequency and, with a batch of B, B extra rank-one updates per history fold. */
+#define OCSC_FLAG_KEEP_HISTORY 2
+/* opts.flags: warm-start DictOCSC: each ocsc_dict_update continues from the
+ * V and Theta of the previous one instead of V = Theta = 0. */
+#define OCSC_FLAG_WARM_START 4
 
 /* Fill *opts with the defaults listed above. */
 void ocsc_default_opts(ocsc_opts* opts);
@@ -123,13 +132,15 @@ int ocsc_code_update(ocsc_ctx* ctx, const void* x_dev, int B, void* codes_dev_ou
  *   G_p += conj(z_p) x_p;  C_p <- C_p - (C_p u)(C_p u)^H / (1 + u^H C_p u), u = conj(z_p),
  * so that C_p = (sum_i conj(z_ip) z_ip^T + rho_d I)^-1; t += B.
  * OCSC_E_STATE if there are no pending codes (none coded, or already folded).
- * The fold may be deferred into the first sweep of the next ocsc_dict_update;
- * every observable result is the same.
+ * With OCSC_FLAG_KEEP_HISTORY, H_p += conj(z_p) z_p^T as well.
+ * The fold of G and C may be deferred into the first sweep of the next
+ * ocsc_dict_update; every observable result is the same up to rounding.
  */
 int ocsc_history_accumulate(ocsc_ctx* ctx);
 
 /*
- * DictOCSC (Algorithm 2): iters_dict ADMM iterations from V = 0, Theta = 0 of
+ * DictOCSC (Algorithm 2): iters_dict ADMM iterations from V = 0, Theta = 0
+ * (with OCSC_FLAG_WARM_START: from the V and Theta the previous call left) of
  *   d_p = C_p (G_p + rho_d (F(V)_p - Theta_p))            (eq. sub_d_sol, column form)
  *   V_k = alpha_k / max(||alpha_k||, 1), alpha_k = crop(Re F^-1(d_k + Theta_k))  (Prop. 2)
  *   Theta += d - F(V)
@@ -148,6 +159,41 @@ int ocsc_dict_update(ocsc_ctx* ctx);
  */
 int ocsc_objective(ocsc_ctx* ctx, const void* x_dev, const void* codes_dev, int B,
                    double* out_host);
+
+/*
+ * The two terms of the objective above, separately: out_host[2b] receives
+ * 1/2 ||x_b - sum_k F^-1(D~_k F(U_bk))||^2 and out_host[2b + 1] receives
+ * ||U_b||_1 (without lambda).  The first term gives the reconstruction PSNR
+ * of the paper's evaluation (section 4): 10 log10(peak^2 P / (2 term)).
+ * out_host: 2B doubles in host memory.  Same rules as ocsc_objective.
+ */
+int ocsc_objective_terms(ocsc_ctx* ctx, const void* x_dev, const void* codes_dev, int B,
+                         double* out_host);
+
+/*
+ * Online surrogate of Proposition 1 (unnormalised), in double:
+ *   F_t(D~) = 1/(2P) sum_p c_p [d_p^H H_p d_p - 2 Re d_p^H G_p]
+ *             + 1/2 sum_i ||x_i||^2 + lambda sum_i ||U_i||_1,
+ * with d_p = D~[:, p], sums over the t samples folded so far and c_p the
+ * Parseval weight of the half spectrum (1 on the columns 0 and pad_w/2, else 2).
+ * D~ = F(zero-pad(D_dev)) for spatial filters D_dev real [K][filt_h][filt_w]
+ * (device), or the current dictionary spectrum when D_dev is NULL.
+ * out_host: one double in host memory.  Waits for completion.
+ * OCSC_E_STATE unless the context was created with OCSC_FLAG_KEEP_HISTORY.
+ */
+int ocsc_surrogate(ocsc_ctx* ctx, const void* D_dev, double* out_host);
+
+/*
+ * Diagnostics of the dictionary update, in double; out_host (host memory)
+ * receives 2 + 2K values:
+ *   [0]            ||F^-1(D~ - F(zero-pad(V)))||_F, the primal residual of the
+ *                  last DictOCSC iterate (equals the last change of Theta);
+ *   [1]            ||F^-1 D~||_F over the padded grid;
+ *   [2 + k]        ||V_k||_2 (each <= 1 by Proposition 2);
+ *   [2 + K + k]    ||D_k||_2 of the exported filters (ocsc_get_dictionary).
+ * Waits for completion.
+ */
+int ocsc_diagnostics(ocsc_ctx* ctx, double* out_host);
 
 /* Wait until all work enqueued on the context stream has finished. */
 int ocsc_sync(ocsc_ctx* ctx);
@@ -168,16 +214,25 @@ typedef enum {
   OCSC_STATE_V = 3,        /* real [K][filt_h][filt_w]: last feasible V of DictOCSC */
   OCSC_STATE_THETA = 4,    /* complex [K][Pf]: last scaled dual Theta of DictOCSC */
   OCSC_STATE_ZHAT = 5,     /* complex [max_batch][K][Pf]: last Z-step spectra (read only) */
-  OCSC_STATE_XHAT = 6      /* complex [max_batch][Pf]: last sample spectra (read only) */
+  OCSC_STATE_XHAT = 6,     /* complex [max_batch][Pf]: last sample spectra (read only) */
+  OCSC_STATE_H = 7,        /* real [Pf][K][K]: history H_p, packed like CINV (needs
+                              OCSC_FLAG_KEEP_HISTORY) */
+  OCSC_STATE_SUMS = 8,     /* double [2]: sum_i ||x_i||^2 and sum_i ||U_i||_1 (needs
+                              OCSC_FLAG_KEEP_HISTORY) */
+  OCSC_STATE_RHS = 9       /* complex [K][Pf]: D-step right-hand side G + rho_d (F(V) - Theta)
+                              carried between dictionary updates (needs OCSC_FLAG_WARM_START) */
 } ocsc_state;
 
 /* Size in bytes of one state item. */
 int ocsc_state_bytes(const ocsc_ctx* ctx, int which, int64_t* bytes_out);
 /* Copy a state item to dst_dev (device memory of ocsc_state_bytes bytes).
- * Pending history folds are applied first.  Waits for the copy. */
+ * Pending history folds are applied first.  Waits for the copy.  Items that
+ * need a flag the context lacks: OCSC_E_INVALID_ARG. */
 int ocsc_get_state(ocsc_ctx* ctx, int which, void* dst_dev);
-/* Overwrite a state item from src_dev.  DICT_HAT, G, CINV, V and THETA only
- * (OCSC_E_INVALID_ARG otherwise).  Pending codes are discarded.  Waits. */
+/* Overwrite a state item from src_dev.  Every item but ZHAT and XHAT
+ * (OCSC_E_INVALID_ARG otherwise).  Pending codes are discarded.  Waits.
+ * A checkpoint is DICT_HAT, G, CINV and the count; with OCSC_FLAG_KEEP_HISTORY
+ * also H and SUMS; with OCSC_FLAG_WARM_START also V, THETA and RHS. */
 int ocsc_set_state(ocsc_ctx* ctx, int which, const void* src_dev);
 /* Number of samples folded into the history so far (t of Algorithm 3). */
 int ocsc_get_count(const ocsc_ctx* ctx, int64_t* t_out);

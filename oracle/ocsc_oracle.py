@@ -36,7 +36,8 @@ Conventions (readings of the paper where it is silent or garbled):
   the exact minimiser of the per-frequency quadratic plus the ADMM penalty;
   ``rho_d`` defaults to rho * P as in eq. sub_d_sol.
 * DictOCSC (Algorithm 2) starts every call from V = 0, Theta = 0 and returns the
-  last D-step iterate, which codes the next sample.
+  last D-step iterate, which codes the next sample.  ``warm_start=True`` is a
+  variant that carries V and Theta from one call to the next.
 * V-step (Proposition 2): ``alpha_k = crop(Re F^-1(d_k + theta_k))``,
   ``V_k = alpha_k / max(||alpha_k||_2, 1)``.
 """
@@ -181,16 +182,19 @@ def dict_vstep(d: np.ndarray, Th: np.ndarray, filt, shape, half: bool = True) ->
 
 
 def dict_update(G: np.ndarray, C: np.ndarray, rho_d: float, iters: int, filt, shape,
-                half: bool = True, trace: list | None = None):
+                half: bool = True, trace: list | None = None,
+                V0: np.ndarray | None = None, Th0: np.ndarray | None = None):
     """DictOCSC: ``iters`` ADMM iterations from V = 0, Theta = 0.
 
     Returns (d, V, Th): the last D-step iterate (the new dictionary spectrum),
     the last feasible V and the last scaled dual.  If ``trace`` is a list, the
-    per-iteration (d, V, Th) are appended to it.
+    per-iteration (d, V, Th) are appended to it.  Given V0 and Th0 the
+    iterations start from them instead (warm start, a variant: Algorithm 2
+    itself starts from zero).
     """
     K = G.shape[0]
-    V = np.zeros((K,) + tuple(filt))
-    Th = np.zeros_like(G)
+    V = np.zeros((K,) + tuple(filt)) if V0 is None else np.array(V0, dtype=np.float64)
+    Th = np.zeros_like(G) if Th0 is None else np.array(Th0, dtype=np.complex128)
     d = None
     for _ in range(iters):
         Vh = dft2(zero_pad(V, shape), half)
@@ -213,6 +217,33 @@ def objective(x: np.ndarray, U: np.ndarray, Dh: np.ndarray, lam: float,
     rec = idft2_real(np.sum(Dh * dft2(U, half), axis=0), shape, half)
     r = x - rec
     return 0.5 * float(np.sum(r * r)) + lam * float(np.sum(np.abs(U)))
+
+
+def objective_terms(x: np.ndarray, U: np.ndarray, Dh: np.ndarray, half: bool = True):
+    """The two terms of eq. csc separately: (1/2 ||x - reconstruction||^2, ||U||_1)."""
+    shape = x.shape
+    rec = idft2_real(np.sum(Dh * dft2(U, half), axis=0), shape, half)
+    r = x - rec
+    return 0.5 * float(np.sum(r * r)), float(np.sum(np.abs(U)))
+
+
+def psnr(x: np.ndarray, rec: np.ndarray, peak: float = 255.0) -> float:
+    """Peak signal-to-noise ratio of a reconstruction (section 4):
+    ``10 log10(peak^2 P / ||rec - x||^2)``."""
+    err = float(np.sum((rec - x) ** 2))
+    return 10.0 * np.log10(peak * peak * x.size / err)
+
+
+def dict_diagnostics(Dh: np.ndarray, V: np.ndarray, filt, shape, half: bool = True) -> dict:
+    """Primal residual ``||F^-1(D~ - F zp V)||``, ``||F^-1 D~||`` over the padded
+    grid, the norms of the V_k and of the exported filters crop(F^-1 D~_k)."""
+    r = idft2_real(Dh - dft2(zero_pad(V, shape), half), shape, half)
+    full = idft2_real(Dh, shape, half)
+    D = crop(full, *filt)
+    return {"primal_residual": float(np.sqrt(np.sum(r * r))),
+            "dict_norm": float(np.sqrt(np.sum(full * full))),
+            "V_norms": np.sqrt(np.sum(V * V, axis=(-2, -1))),
+            "D_norms": np.sqrt(np.sum(D * D, axis=(-2, -1)))}
 
 
 def surrogate(Dh: np.ndarray, H: np.ndarray, G: np.ndarray, sum_xh2: float,
@@ -245,7 +276,7 @@ class OCSC:
     """
 
     def __init__(self, K, filt_h, filt_w, pad_h, pad_w, lam, rho, rho_dict=None,
-                 iters_code=10, iters_dict=10, half=True, keep_history=False):
+                 iters_code=10, iters_dict=10, half=True, keep_history=False, warm_start=False):
         if K < 1 or not (1 <= filt_h <= pad_h and 1 <= filt_w <= pad_w):
             raise ValueError("bad sizes")
         if lam < 0 or rho <= 0:
@@ -257,6 +288,7 @@ class OCSC:
         self.rho_d = float(rho_dict) if rho_dict and rho_dict > 0 else self.rho * self.P
         self.iters_code, self.iters_dict = iters_code, iters_dict
         self.half = half
+        self.warm_start = warm_start
         wf = pad_w // 2 + 1 if half else pad_w
         fshape = (pad_h, wf)
         self.G = np.zeros((K,) + fshape, dtype=np.complex128)
@@ -304,8 +336,9 @@ class OCSC:
     def dict_update(self, trace: list | None = None) -> None:
         if self.t == 0:
             raise RuntimeError("dict_update needs at least one accumulated sample")
+        warm = (self.V, self.Th) if self.warm_start else (None, None)
         d, V, Th = dict_update(self.G, self.C, self.rho_d, self.iters_dict, self.filt,
-                               self.shape, self.half, trace)
+                               self.shape, self.half, trace, *warm)
         self.Dh, self.V, self.Th = d, V, Th
 
     def step(self, xs: np.ndarray) -> np.ndarray:
@@ -320,6 +353,15 @@ class OCSC:
         if xs.ndim == 2:
             xs, Us = xs[None], Us[None]
         return np.array([objective(x, U, self.Dh, self.lam, self.half) for x, U in zip(xs, Us)])
+
+    def objective_terms(self, xs: np.ndarray, Us: np.ndarray) -> list:
+        xs = np.asarray(xs, np.float64)
+        if xs.ndim == 2:
+            xs, Us = xs[None], Us[None]
+        return [objective_terms(x, U, self.Dh, self.half) for x, U in zip(xs, Us)]
+
+    def diagnostics(self) -> dict:
+        return dict_diagnostics(self.Dh, self.V, self.filt, self.shape, self.half)
 
     def surrogate_at(self, Dh: np.ndarray) -> float:
         if self.H is None:

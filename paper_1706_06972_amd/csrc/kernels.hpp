@@ -514,13 +514,42 @@ __device__ __forceinline__ void herm_rank1_ct(T* __restrict__ R, const cx<T>* v,
 
 // 16-byte vectors of one slot (fpb consecutive frequencies) held by one thread.
 constexpr int SWEEP_MAXV = 12;
-constexpr int SWEEP_VECS = 12;   // complex K-vectors of LDS per frequency group
+
+// 16-byte vectors of one slot per thread: exact for the compile-time
+// specialisations, SWEEP_MAXV for the generic kernel.
+template <typename T, int KT, int FPB>
+__host__ __device__ constexpr int sweep_nvm() {
+  if constexpr (KT > 0) {
+    constexpr int VR = 16 / (int)sizeof(T);
+    constexpr int fs = (KT * (KT + 1) + VR - 1) / VR * VR;
+    return (FPB * fs * (int)sizeof(T) / 16 + 255) / 256;
+  } else {
+    return SWEEP_MAXV;
+  }
+}
+
+// LDS of one D-step workgroup:
+//   [C of fpb frequencies, padded to nvm * 256 16-byte vectors]
+//   [per frequency group: x (max(K, group width)), y, C u, C G (K each), partial sums (8K)] complex.
+// The padding and the wide x take the stores of lanes past the slot or past K,
+// so staging needs no guard.
+__host__ __device__ inline size_t sweep_r_bytes(int fpb, int fs, int sr, int nvm) {
+  const size_t a = (size_t)fpb * fs * sr, b = (size_t)nvm * 256 * 16;
+  return a > b ? a : b;
+}
+__host__ __device__ inline int sweep_group_vecs(int K, int fpb) {
+  const int tpg = 256 / fpb;
+  return (K > tpg ? K : tpg) + 11 * K;
+}
+__host__ __device__ inline size_t sweep_lds_bytes(int K, int fpb, int fs, int sr, int nvm) {
+  return sweep_r_bytes(fpb, fs, sr, nvm) + (size_t)fpb * sweep_group_vecs(K, fpb) * 2 * sr;
+}
 
 // The prefetch is straight-line code: every lane loads (indices past the slot
-// are clamped to its last vector) and every lane stores (past the slot into a
-// private dummy vector).  Guarded loads and stores would leave the compiler
-// unable to prove that the previous slot's loads into the same registers have
-// landed, and it would then wait for all of them before each new load.
+// are clamped to its last vector) and every lane stores (past the slot into
+// the padding).  Guarded loads and stores would leave the compiler unable to
+// prove that the previous slot's loads into the same registers have landed,
+// and it would then wait for all of them before each new load.
 template <int NV_MAX>
 __device__ __forceinline__ void slot_fetch(v4f (&reg)[NV_MAX], const v4f* __restrict__ src, int nvec, int tid) {
 #pragma unroll
@@ -528,12 +557,9 @@ __device__ __forceinline__ void slot_fetch(v4f (&reg)[NV_MAX], const v4f* __rest
 }
 
 template <int NV_MAX>
-__device__ __forceinline__ void slot_stage(const v4f (&reg)[NV_MAX], v4f* dst, int nvec, int tid, v4f* dummy) {
+__device__ __forceinline__ void slot_stage(const v4f (&reg)[NV_MAX], v4f* dst, int tid) {
 #pragma unroll
-  for (int v = 0; v < NV_MAX; ++v) {
-    const int e = tid + v * 256;
-    *(e < nvec ? dst + e : dummy) = reg[v];
-  }
+  for (int v = 0; v < NV_MAX; ++v) dst[tid + v * 256] = reg[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -548,16 +574,19 @@ __device__ __forceinline__ void slot_stage(const v4f (&reg)[NV_MAX], v4f* dst, i
 // into the history in sample order (eqs. B_update and C_update):
 //   u = conj(z_p);  G_p += u x_p;  v = C_p u;  C_p <- C_p - v v^H / (1 + u^H v),
 // the updated C_p is written back and the right-hand side is the updated G_p
-// (the first DictOCSC iterate, from V = Theta = 0).  dout == nullptr: fold only.
-// gam_out (optional): 1 / (rho + ||d_p||^2), used by the next code update.
+// (the first DictOCSC iterate, from V = Theta = 0).  With rfold (warm start)
+// the right-hand side is instead the carried G + rho_d (F(V) - Theta), which
+// the fold advances by the same increments as G and writes back.
+// dout == nullptr: fold only.
 // ---------------------------------------------------------------------------
 template <typename T, int KT, int FPB>
 __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>* __restrict__ G,
                                                     const cx<T>* __restrict__ rhs,
                                                     const cx<T>* __restrict__ Zh,
                                                     const cx<T>* __restrict__ xh, int nfold,
-                                                    cx<T>* __restrict__ dout, T* __restrict__ gam_out,
-                                                    T rho, int K_, int Pf, int fpb_, int fs_, int slots_per_wg,
+                                                    cx<T>* __restrict__ rfold,
+                                                    cx<T>* __restrict__ dout,
+                                                    int K_, int Pf, int fpb_, int fs_, int slots_per_wg,
                                                     int reverse) {
   // KT > 0: K and fpb fixed at compile time (the arguments then equal them)
   constexpr bool CT = KT > 0;
@@ -572,11 +601,13 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
   const int g = tid / tpg, lt = tid % tpg;
   int ns = tpg / K;
   ns = ns < 1 ? 1 : (ns > 4 ? 4 : ns);
+  // 16-byte vectors per thread for one slot (compile-time for a fixed K)
+  constexpr int NVM = sweep_nvm<T, KT, FPB>();
   T* Rall = reinterpret_cast<T*>(smem_raw);
-  const size_t rbytes = (size_t)fpb * fs * sizeof(T);   // fs*sizeof(T) is a multiple of 16
-  cx<T>* vecs = reinterpret_cast<cx<T>*>(smem_raw + rbytes);
-  cx<T>* xv = vecs + (size_t)g * SWEEP_VECS * K;   // rhs / u
-  cx<T>* yv = xv + K;                              // result / updated G
+  cx<T>* vecs = reinterpret_cast<cx<T>*>(smem_raw + sweep_r_bytes(fpb, fs, (int)sizeof(T), NVM));
+  const int XV = K > tpg ? K : tpg;
+  cx<T>* xv = vecs + (size_t)g * sweep_group_vecs(K, fpb);   // rhs / u (XV entries)
+  cx<T>* yv = xv + XV;                             // result / updated G
   cx<T>* vv = yv + K;                              // C u
   cx<T>* gv = vv + K;                              // C G
   cx<T>* part = gv + K;                            // [8][K]
@@ -590,12 +621,7 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
   const int s_end = min(nslots, s_begin + slots_per_wg);
   const int nvec = (int)((size_t)fpb * fs * sizeof(T) / 16);
   const bool plain = dout && nfold == 0;
-  // 16-byte vectors per thread for one slot (compile-time for a fixed K)
-  constexpr int NVM = CT ? ((FPB * ((KT * (KT + 1) + VR - 1) / VR * VR) * (int)sizeof(T) / 16) + 255) / 256
-                         : SWEEP_MAXV;
   v4f reg[NVM];
-  __shared__ v4f dummy4[256];
-  __shared__ cx<T> dummyc[256];
   cx<T> rpre = mk<T>(0, 0);
   const int kl = lt < K ? lt : K - 1;   // clamped filter index of this thread's rhs element
 
@@ -615,8 +641,8 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
     const bool ok = p < Pf;
     const int nv = slot_vecs(sl);
     __syncthreads();   // previous slot finished with LDS
-    slot_stage<NVM>(reg, reinterpret_cast<v4f*>(Rall), nv, tid, dummy4 + tid);
-    if (plain) *(lt < K ? xv + lt : dummyc + tid) = rpre;
+    slot_stage<NVM>(reg, reinterpret_cast<v4f*>(Rall), tid);
+    if (plain) xv[lt] = rpre;
     __syncthreads();
     if (s + 1 < s_end) {   // next slot's C and right-hand side are in flight during this slot
       const int sn = slot_of(s + 1);
@@ -636,10 +662,17 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       // one sample: v = C u and g = C G_new in one pass; d = g - beta v (v^H G_new)
       if (ok && lt < K) {
         const cx<T> u = cconj<T>(Zh[(size_t)lt * Pf + p]);
-        const cx<T> gn = cadd<T>(G[(size_t)lt * Pf + p], cmul<T>(u, xh[p]));
+        const cx<T> du = cmul<T>(u, xh[p]);
+        const cx<T> gn = cadd<T>(G[(size_t)lt * Pf + p], du);
         G[(size_t)lt * Pf + p] = gn;
         xv[lt] = u;
-        yv[lt] = gn;
+        if (rfold) {
+          const cx<T> rn = cadd<T>(rfold[(size_t)lt * Pf + p], du);
+          rfold[(size_t)lt * Pf + p] = rn;
+          yv[lt] = rn;
+        } else {
+          yv[lt] = gn;
+        }
       }
       __syncthreads();
       if constexpr (CT) {
@@ -672,11 +705,14 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
     } else {
       // several samples, folded one after another in sample order
+      cx<T> dsum = mk<T>(0, 0);
       for (int b = 0; b < nfold; ++b) {
         if (ok && lt < K) {
           const cx<T> u = cconj<T>(Zh[((size_t)b * K + lt) * Pf + p]);
+          const cx<T> du = cmul<T>(u, xh[(size_t)b * Pf + p]);
           xv[lt] = u;
-          G[(size_t)lt * Pf + p] = cadd<T>(G[(size_t)lt * Pf + p], cmul<T>(u, xh[(size_t)b * Pf + p]));
+          G[(size_t)lt * Pf + p] = cadd<T>(G[(size_t)lt * Pf + p], du);
+          dsum = cadd<T>(dsum, du);
         }
         __syncthreads();
         herm_matvec<T>(R, K, ld, xv, vv, part, lt, tpg, ns);
@@ -688,19 +724,19 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
       const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
       for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
-      if (dout && ok && lt < K) xv[lt] = G[(size_t)lt * Pf + p];
+      if (rfold && ok && lt < K) {
+        const cx<T> rn = cadd<T>(rfold[(size_t)lt * Pf + p], dsum);
+        rfold[(size_t)lt * Pf + p] = rn;
+        if (dout) xv[lt] = rn;
+      } else if (dout && ok && lt < K) {
+        xv[lt] = G[(size_t)lt * Pf + p];
+      }
       __syncthreads();
       if (dout) herm_matvec<T>(R, K, ld, xv, yv, part, lt, tpg, ns);
     }
     if (!dout) continue;
     __syncthreads();
     if (ok && lt < K) dout[(size_t)lt * Pf + p] = yv[lt];
-    if (gam_out) {
-      T acc = 0;
-      if (lt < K) acc = yv[lt].x * yv[lt].x + yv[lt].y * yv[lt].y;
-      acc = group_sum<T>(acc, tpg, wsum);
-      if (lt == 0 && ok) gam_out[p] = (T)1 / (rho + acc);
-    }
   }
 }
 
@@ -1073,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_abs_sum(const T* __restrict__ U, double
 }
 
 __global__ void k_obj_final(const double* __restrict__ rpart, int nr, const double* __restrict__ lpart, int nl,
-                            double* __restrict__ out, double invP, double lam) {
+                            double* __restrict__ out, double invP, double lam, int terms) {
   __shared__ double a[256], c[256];
   const int b = blockIdx.x;
   double s1 = 0, s2 = 0;
@@ -1089,7 +1125,14 @@ __global__ void k_obj_final(const double* __restrict__ rpart, int nr, const doub
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[b] = 0.5 * a[0] * invP + lam * c[0];
+  if (threadIdx.x == 0) {
+    if (terms) {
+      out[2 * b] = 0.5 * a[0] * invP;
+      out[2 * b + 1] = c[0];
+    } else {
+      out[b] = 0.5 * a[0] * invP + lam * c[0];
+    }
+  }
 }
 
 // C_p = I / rho_d for every frequency, in the per-frequency layout (pitch K + 1, stride fs).

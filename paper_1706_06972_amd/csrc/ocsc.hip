@@ -12,10 +12,12 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
 #include "../../include/ocsc.h"
+#include "diag.hpp"
 #include "kernels.hpp"
 
 using namespace ocsc;
@@ -43,16 +45,23 @@ struct ocsc_ctx {
   int sweep_wgs = 0, slots_per_wg = 0;
   size_t sweep_smem = 0, vapply_smem = 0;
   bool vstep_fused = false;   // one workgroup per filter (filters up to 16 x 16)
+  bool keep_hist = false;     // OCSC_FLAG_KEEP_HISTORY
+  bool warm = false;          // OCSC_FLAG_WARM_START
   // runtime
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // device state (typed by prec)
-  void *xh = nullptr, *Dh = nullptr, *gam = nullptr, *gam2 = nullptr, *S = nullptr, *Zh = nullptr,
+  void *xh = nullptr, *Dh = nullptr, *gam = nullptr, *S = nullptr, *Zh = nullptr,
        *W = nullptr, *G = nullptr, *Cm = nullptr, *d = nullptr, *Th = nullptr, *rhs = nullptr,
        *V = nullptr, *apart = nullptr, *twH = nullptr, *twW = nullptr, *xh_obj = nullptr;
   double *obj_part = nullptr, *obj_out = nullptr;
   int obj_nr = 0, obj_nl = 0;
+  // kept history and diagnostics: H (layout of C), codes when the caller keeps
+  // none, per-sample partial sums of the pending codes, running sums, the
+  // spectrum of given filters, exported filters, reduction partials, results
+  void *Hm = nullptr, *Ubuf = nullptr, *Dv = nullptr, *Dexp = nullptr;
+  double *pend = nullptr, *hacc = nullptr, *dpart = nullptr, *dres = nullptr;
   // host-side bookkeeping
   int64_t t = 0;
   int pending_B = 0;    // coded samples not yet accumulated
@@ -244,22 +253,40 @@ int launch_gamma(ocsc_ctx* c) {
   return OCSC_OK;
 }
 
+// Compile-time specialisations of the D-step sweep (real type, K, fpb); the
+// generic kernel serves every other shape.
+#define OCSC_SWEEP_SPECS(X) X(float, 100, 1) X(float, 16, 16) X(double, 16, 8)
+
+int sweep_nvm_for(int K, int fpb, size_t sr) {
+#define X(T, KT, FPB) \
+  if (sr == sizeof(T) && K == KT && fpb == FPB) return sweep_nvm<T, KT, FPB>();
+  OCSC_SWEEP_SPECS(X)
+#undef X
+  return SWEEP_MAXV;
+}
+
 // One D-step sweep; nfold > 0 folds the kept spectra of nfold samples first.
 template <typename T>
-int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* dout, void* gam_out, int cls) {
+int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dout, int cls) {
   ProfScope ps(c, cls);
   const int reverse = c->serpentine ? (int)(c->sweep_count & 1u) : 0;
   c->sweep_count++;
 #define OCSC_SWEEP(KT, FPB)                                                                                  \
   hipLaunchKernelGGL((k_dict_sweep<T, KT, FPB>), dim3(c->sweep_wgs), dim3(256), c->sweep_smem, c->stream,     \
                      (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh,     \
-                     nfold, (cx<T>*)dout, (T*)gam_out, (T)c->rho, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg, \
+                     nfold, (cx<T>*)rfold, (cx<T>*)dout, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg, \
                      reverse)
-  // compile-time specialisations for the common filter counts; the generic kernel otherwise
-  if (sizeof(T) == 4 && c->K == 100 && c->fpb == 1) OCSC_SWEEP(100, 1);
-  else if (sizeof(T) == 4 && c->K == 16 && c->fpb == 16) OCSC_SWEEP(16, 16);
-  else if (sizeof(T) == 8 && c->K == 16 && c->fpb == 8) OCSC_SWEEP(16, 8);
-  else OCSC_SWEEP(0, 0);
+  bool done = false;
+#define X(TT, KT, FPB)                                                          \
+  if constexpr (std::is_same<T, TT>::value) {                                  \
+    if (!done && c->K == KT && c->fpb == FPB) {                                \
+      OCSC_SWEEP(KT, FPB);                                                     \
+      done = true;                                                             \
+    }                                                                          \
+  }
+  OCSC_SWEEP_SPECS(X)
+#undef X
+  if (!done) OCSC_SWEEP(0, 0);
 #undef OCSC_SWEEP
   LAUNCHED(c);
   return OCSC_OK;
@@ -328,7 +355,7 @@ int launch_vstep(ocsc_ctx* c, int first) {
 template <typename T>
 int flush_fold(ocsc_ctx* c) {
   if (c->fold_B == 0) return OCSC_OK;
-  int rc = launch_sweep<T>(c, c->fold_B, nullptr, nullptr, nullptr, OCSC_KC_HISTORY);
+  int rc = launch_sweep<T>(c, c->fold_B, nullptr, c->warm ? c->rhs : nullptr, nullptr, OCSC_KC_HISTORY);
   if (rc) return rc;
   c->fold_B = 0;
   return OCSC_OK;
@@ -341,11 +368,23 @@ int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes) {
   if (rc) return rc;
   rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh, c->Pf, B);
   if (rc) return rc;
+  T* Uout = codes ? (T*)codes : (T*)c->Ubuf;   // Ubuf is null unless the history is kept
   for (int j = 0; j < c->Jz; ++j) {
     rc = launch_zstep<T>(c, B, j == 0);
     if (rc) return rc;
-    rc = launch_code_plane<T>(c, B * c->K, (T*)codes, j == 0, j == c->Jz - 1);
+    rc = launch_code_plane<T>(c, B * c->K, Uout, j == 0, j == c->Jz - 1);
     if (rc) return rc;
+  }
+  if (c->keep_hist) {
+    // per-sample partial sums of ||x_b||^2 (Parseval) and ||U_b||_1, added to
+    // the running sums when the samples are accumulated
+    ProfScope ps(c, OCSC_KC_OTHER);
+    hipLaunchKernelGGL((k_wsq<T>), dim3(64, B), dim3(256), 0, c->stream, (const cx<T>*)c->xh,
+                       (const cx<T>*)nullptr, c->pend, 1, c->Pf, c->Pw);
+    LAUNCHED(c);
+    hipLaunchKernelGGL((k_abs_sum<T>), dim3(64, B), dim3(256), 0, c->stream, (const T*)Uout,
+                       c->pend + (size_t)c->maxB * 64, (long)c->K * c->P);
+    LAUNCHED(c);
   }
   c->pending_B = B;
   return OCSC_OK;
@@ -354,26 +393,29 @@ int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes) {
 template <typename T>
 int dict_update_t(ocsc_ctx* c) {
   for (int tau = 0; tau < c->Jd; ++tau) {
-    const bool last = tau == c->Jd - 1;
     int rc;
-    if (tau == 0) {
-      rc = launch_sweep<T>(c, c->fold_B, c->G, c->d, last ? c->gam2 : nullptr,
-                           c->fold_B ? OCSC_KC_HISTORY : OCSC_KC_DSTEP);
+    if (tau == 0 && c->fold_B) {
+      // fold fused with the first sweep; its right-hand side is G (cold start)
+      // or the carried one (warm start)
+      rc = launch_sweep<T>(c, c->fold_B, nullptr, c->warm ? c->rhs : nullptr, c->d, OCSC_KC_HISTORY);
       c->fold_B = 0;
     } else {
-      rc = launch_sweep<T>(c, 0, c->rhs, c->d, last ? c->gam2 : nullptr, OCSC_KC_DSTEP);
+      const void* r = (tau == 0 && !c->warm) ? c->G : c->rhs;
+      rc = launch_sweep<T>(c, 0, r, nullptr, c->d, OCSC_KC_DSTEP);
     }
     if (rc) return rc;
-    rc = launch_vstep<T>(c, tau == 0);
+    rc = launch_vstep<T>(c, tau == 0 && !c->warm);
     if (rc) return rc;
   }
   std::swap(c->Dh, c->d);
-  std::swap(c->gam, c->gam2);
-  return OCSC_OK;
+  // 1 / (rho + ||a_p||^2) of the new dictionary for the next code update
+  // (the same kernel as after ocsc_set_dictionary, so a restored learner
+  // continues bit for bit)
+  return launch_gamma<T>(c);
 }
 
 template <typename T>
-int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {
+int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* out, int terms) {
   int rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh_obj, c->Pf, B);
   if (rc) return rc;
   rc = launch_rfft2<T>(c, (const T*)codes, c->Ph, c->Pw, c->P, (cx<T>*)c->S, c->Pf, B * c->K);
@@ -388,13 +430,88 @@ int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* ou
                        (long)c->K * c->P);
     LAUNCHED(c);
     hipLaunchKernelGGL(k_obj_final, dim3(B), dim3(256), 0, c->stream, c->obj_part, c->obj_nr, lpart, c->obj_nl,
-                       c->obj_out, 1.0 / c->P, c->lam);
+                       c->obj_out, 1.0 / c->P, c->lam, terms);
     LAUNCHED(c);
   }
-  HIPX(c, hipMemcpyAsync(out, c->obj_out, sizeof(double) * B, hipMemcpyDeviceToHost, c->stream));
+  const int nout = terms ? 2 * B : B;
+  HIPX(c, hipMemcpyAsync(out, c->obj_out, sizeof(double) * nout, hipMemcpyDeviceToHost, c->stream));
   HIPX(c, hipStreamSynchronize(c->stream));
-  for (int b = 0; b < B; ++b)
+  for (int b = 0; b < nout; ++b)
     if (!std::isfinite(out[b])) return fail(c, OCSC_E_NUMERIC, "objective is not finite");
+  return OCSC_OK;
+}
+
+// Kept history: H_p += sum_b conj(z_bp) z_bp^T and the running sums, at
+// accumulation time (the fold of G and C may still be deferred).
+template <typename T>
+int keep_history_t(ocsc_ctx* c, int B) {
+  ProfScope ps(c, OCSC_KC_OTHER);
+  hipLaunchKernelGGL((k_hist_herk<T>), dim3(c->Pf), dim3(256), sizeof(cx<T>) * 8 * c->K, c->stream, (T*)c->Hm,
+                     (const cx<T>*)c->Zh, B, c->K, c->Pf, c->fs);
+  LAUNCHED(c);
+  hipLaunchKernelGGL(k_hist_sums, dim3(1), dim3(256), 0, c->stream, c->pend, B * 64,
+                     c->pend + (size_t)c->maxB * 64, B * 64, c->hacc, 1.0 / c->P);
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
+template <typename T>
+int surrogate_t(ocsc_ctx* c, const void* D, double* out) {
+  int rc = flush_fold<T>(c);   // G must include every accumulated sample
+  if (rc) return rc;
+  const cx<T>* dsp = (const cx<T>*)c->Dh;
+  if (D) {
+    rc = launch_rfft2<T>(c, (const T*)D, c->Mh, c->Mw, (long)c->Mh * c->Mw, (cx<T>*)c->Dv, c->Pf, c->K);
+    if (rc) return rc;
+    dsp = (const cx<T>*)c->Dv;
+  }
+  {
+    ProfScope ps(c, OCSC_KC_OTHER);
+    hipLaunchKernelGGL((k_surr_quad<T>), dim3(c->Pf), dim3(256), sizeof(double) * 2 * c->K, c->stream,
+                       (const T*)c->Hm, (const cx<T>*)c->G, dsp, c->dpart, c->K, c->Pf, c->Pw, c->fs);
+    LAUNCHED(c);
+    hipLaunchKernelGGL(k_surr_final, dim3(1), dim3(256), 0, c->stream, c->dpart, c->Pf, c->hacc, c->dres,
+                       1.0 / c->P, c->lam);
+    LAUNCHED(c);
+  }
+  HIPX(c, hipMemcpyAsync(out, c->dres, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPX(c, hipStreamSynchronize(c->stream));
+  if (!std::isfinite(out[0])) return fail(c, OCSC_E_NUMERIC, "surrogate is not finite");
+  return OCSC_OK;
+}
+
+template <typename T>
+int diagnostics_t(ocsc_ctx* c, double* out) {
+  const long fsz = (long)c->Mh * c->Mw;
+  int rc = launch_rfft2<T>(c, (const T*)c->V, c->Mh, c->Mw, fsz, (cx<T>*)c->Dv, c->Pf, c->K);
+  if (rc) return rc;
+  rc = launch_irfft2_crop<T>(c, (const cx<T>*)c->Dh, c->Pf, (T*)c->Dexp, c->Mh, c->Mw, fsz, c->K);
+  if (rc) return rc;
+  {
+    ProfScope ps(c, OCSC_KC_OTHER);
+    const double invP = 1.0 / c->P;
+    hipLaunchKernelGGL((k_wsq<T>), dim3(DIAG_BLOCKS), dim3(256), 0, c->stream, (const cx<T>*)c->Dh,
+                       (const cx<T>*)c->Dv, c->dpart, c->K, c->Pf, c->Pw);
+    LAUNCHED(c);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, c->stream, c->dpart, DIAG_BLOCKS, c->dres, invP, 1);
+    LAUNCHED(c);
+    hipLaunchKernelGGL((k_wsq<T>), dim3(DIAG_BLOCKS), dim3(256), 0, c->stream, (const cx<T>*)c->Dh,
+                       (const cx<T>*)nullptr, c->dpart, c->K, c->Pf, c->Pw);
+    LAUNCHED(c);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, c->stream, c->dpart, DIAG_BLOCKS, c->dres + 1, invP, 1);
+    LAUNCHED(c);
+    hipLaunchKernelGGL((k_plane_norm<T>), dim3(c->K), dim3(256), 0, c->stream, (const T*)c->V, (int)fsz,
+                       c->dres + 2);
+    LAUNCHED(c);
+    hipLaunchKernelGGL((k_plane_norm<T>), dim3(c->K), dim3(256), 0, c->stream, (const T*)c->Dexp, (int)fsz,
+                       c->dres + 2 + c->K);
+    LAUNCHED(c);
+  }
+  const size_t n = 2 + 2 * (size_t)c->K;
+  HIPX(c, hipMemcpyAsync(out, c->dres, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPX(c, hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(out[i])) return fail(c, OCSC_E_NUMERIC, "diagnostics are not finite");
   return OCSC_OK;
 }
 
@@ -416,8 +533,10 @@ int cinv_layout_t(ocsc_ctx* c, const void* src, void* dst, int to_internal) {
 }
 
 void free_all(ocsc_ctx* c) {
-  void** bufs[] = {&c->xh, &c->Dh, &c->gam, &c->gam2, &c->S, &c->Zh, &c->W, &c->G, &c->Cm, &c->d,
-                   &c->Th, &c->rhs, &c->V, &c->apart, &c->twH, &c->twW, &c->xh_obj};
+  void** bufs[] = {&c->xh, &c->Dh, &c->gam, &c->S,    &c->Zh,   &c->W,      &c->G,
+                   &c->Cm, &c->d,  &c->Th,  &c->rhs,  &c->V,    &c->apart, &c->twH, &c->twW,
+                   &c->xh_obj, &c->Hm, &c->Ubuf, &c->Dv, &c->Dexp, (void**)&c->pend, (void**)&c->hacc,
+                   (void**)&c->dpart, (void**)&c->dres};
   for (void** b : bufs)
     if (*b) {
       (void)hipFree(*b);
@@ -445,6 +564,18 @@ int state_bytes(const ocsc_ctx* c, int which, size_t* out) {
     case OCSC_STATE_V: *out = (size_t)c->K * c->Mh * c->Mw * c->sr; return OCSC_OK;
     case OCSC_STATE_ZHAT: *out = (size_t)c->maxB * c->K * c->Pf * sc; return OCSC_OK;
     case OCSC_STATE_XHAT: *out = (size_t)c->maxB * c->Pf * sc; return OCSC_OK;
+    case OCSC_STATE_H:
+      if (!c->keep_hist) return OCSC_E_INVALID_ARG;
+      *out = (size_t)c->Pf * c->K * c->K * c->sr;
+      return OCSC_OK;
+    case OCSC_STATE_SUMS:
+      if (!c->keep_hist) return OCSC_E_INVALID_ARG;
+      *out = 2 * sizeof(double);
+      return OCSC_OK;
+    case OCSC_STATE_RHS:
+      if (!c->warm) return OCSC_E_INVALID_ARG;
+      *out = (size_t)c->K * c->Pf * sc;
+      return OCSC_OK;
     default: return OCSC_E_INVALID_ARG;
   }
 }
@@ -458,6 +589,9 @@ void* state_ptr(ocsc_ctx* c, int which) {
     case OCSC_STATE_THETA: return c->Th;
     case OCSC_STATE_ZHAT: return c->Zh;
     case OCSC_STATE_XHAT: return c->xh;
+    case OCSC_STATE_H: return c->Hm;
+    case OCSC_STATE_SUMS: return c->hacc;
+    case OCSC_STATE_RHS: return c->rhs;
     default: return nullptr;
   }
 }
@@ -502,7 +636,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   if (o.max_batch < 1 || o.max_batch > 65535) return fail(nullptr, OCSC_E_INVALID_ARG, "max_batch must be in [1, 65535]");
   if (o.precision != OCSC_FP64 && o.precision != OCSC_FP32)
     return fail(nullptr, OCSC_E_INVALID_ARG, "unknown precision");
-  if (o.flags & ~OCSC_FLAG_OWN_STREAM) return fail(nullptr, OCSC_E_INVALID_ARG, "unknown bits in opts->flags");
+  if (o.flags & ~(OCSC_FLAG_OWN_STREAM | OCSC_FLAG_KEEP_HISTORY | OCSC_FLAG_WARM_START))
+    return fail(nullptr, OCSC_E_INVALID_ARG, "unknown bits in opts->flags");
   if (!std::isfinite(o.rho_dict)) return fail(nullptr, OCSC_E_INVALID_ARG, "rho_dict must be finite");
   if (pad_h > 128 || pad_w > 128)
     return fail(nullptr, OCSC_E_UNSUPPORTED, "this build has plane kernels for grids up to 128 x 128");
@@ -513,7 +648,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   const int fs = (K * (K + 1) + vr - 1) / vr * vr;
   int fpb = 1;
   while (fpb < 16 && 256 / (fpb * 2) >= K) fpb *= 2;
-  auto sweep_bytes = [&](int f) { return (size_t)f * fs * sr + (size_t)f * SWEEP_VECS * K * 2 * sr; };
+  auto sweep_bytes = [&](int f) { return sweep_lds_bytes(K, f, fs, (int)sr, sweep_nvm_for(K, f, sr)); };
   const size_t max_lds = 160 * 1024 - 1024;
   const size_t max_slot = (size_t)256 * SWEEP_MAXV * 16;
   if (sweep_bytes(1) > max_lds || (size_t)fs * sr > max_slot)
@@ -536,7 +671,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   {
     // one round of workgroups over the chip; each walks a run of slots
     const int nslots = (c->Pf + fpb - 1) / fpb;
-    int occ = (int)((160 * 1024) / c->sweep_smem);
+    int occ = (int)((160 * 1024) / (c->sweep_smem + 64));   // + the kernel's static LDS
     occ = occ < 1 ? 1 : (occ > 8 ? 8 : occ);
     const int target = 256 * occ;
     c->slots_per_wg = (nslots + target - 1) / target;
@@ -544,6 +679,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   }
   c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * vb * 2 * sr;
   if (const char* s = std::getenv("OCSC_SERPENTINE")) c->serpentine = std::atoi(s) != 0;
+  c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0;
+  c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
   c->vstep_fused = sr == 8 ? vstep_fused_ok<double>(pad_h, pad_w, filt_h, filt_w)
                            : vstep_fused_ok<float>(pad_h, pad_w, filt_h, filt_w);
 
@@ -564,9 +701,11 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     c->own_stream = true;
   }
   if (c->sweep_smem > 64 * 1024) {
-    const void* fns[5] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>,
-                          (const void*)k_dict_sweep<float, 100, 1>, (const void*)k_dict_sweep<float, 16, 16>,
-                          (const void*)k_dict_sweep<double, 16, 8>};
+    const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>
+#define X(T, KT, FPB) , (const void*)k_dict_sweep<T, KT, FPB>
+                         OCSC_SWEEP_SPECS(X)
+#undef X
+    };
     for (const void* fn : fns) {
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->sweep_smem);
       if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
@@ -578,15 +717,23 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   c->obj_nl = 64;
   struct { void** p; size_t n; } allocs[] = {
       {&c->xh, B * Pf * sc},        {&c->Dh, K_ * Pf * sc},          {&c->gam, Pf * sr},
-      {&c->gam2, Pf * sr},          {&c->S, B * K_ * Pf * sc},       {&c->Zh, B * K_ * Pf * sc},
+      {&c->S, B * K_ * Pf * sc},       {&c->Zh, B * K_ * Pf * sc},
       {&c->W, B * K_ * c->P * sr},  {&c->G, K_ * Pf * sc},           {&c->Cm, Pf * (size_t)c->fs * sr},
       {&c->d, K_ * Pf * sc},        {&c->Th, K_ * Pf * sc},          {&c->rhs, K_ * Pf * sc},
       {&c->V, K_ * filt_h * filt_w * sr},
       {&c->apart, K_ * c->nvb * filt_h * filt_w * sr},
       {&c->twH, (size_t)pad_h * sc}, {&c->twW, (size_t)pad_w * sc}, {&c->xh_obj, B * Pf * sc},
       {(void**)&c->obj_part, B * (size_t)(c->obj_nr + c->obj_nl) * sizeof(double)},
-      {(void**)&c->obj_out, B * sizeof(double)}};
+      {(void**)&c->obj_out, 2 * B * sizeof(double)},
+      {&c->Dv, K_ * Pf * sc},       {&c->Dexp, K_ * filt_h * filt_w * sr},
+      {(void**)&c->dpart, (size_t)std::max<int>(c->Pf, DIAG_BLOCKS) * sizeof(double)},
+      {(void**)&c->dres, (2 + 2 * K_) * sizeof(double)},
+      {(void**)&c->hacc, 2 * sizeof(double)},
+      {&c->Hm, c->keep_hist ? Pf * (size_t)c->fs * sr : 0},
+      {&c->Ubuf, c->keep_hist ? B * K_ * c->P * sr : 0},
+      {(void**)&c->pend, c->keep_hist ? 2 * B * 64 * sizeof(double) : 0}};
   for (auto& a : allocs) {
+    if (a.n == 0) continue;
     e = hipMalloc(a.p, a.n);
     if (e != hipSuccess) return bail(OCSC_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
     e = hipMemsetAsync(*a.p, 0, a.n, c->stream);
@@ -657,6 +804,10 @@ int ocsc_code_update(ocsc_ctx* c, const void* x, int B, void* codes) {
 int ocsc_history_accumulate(ocsc_ctx* c) {
   if (!c) return OCSC_E_INVALID_ARG;
   if (c->pending_B == 0) return fail(c, OCSC_E_STATE, "no coded samples to accumulate");
+  if (c->keep_hist) {
+    int rc = c->sr == 8 ? keep_history_t<double>(c, c->pending_B) : keep_history_t<float>(c, c->pending_B);
+    if (rc) return rc;
+  }
   c->fold_B = c->pending_B;
   c->t += c->pending_B;
   c->pending_B = 0;
@@ -674,7 +825,29 @@ int ocsc_objective(ocsc_ctx* c, const void* x, const void* codes, int B, double*
   if (!x || !codes || !out) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
   if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
-  return c->sr == 8 ? objective_t<double>(c, x, codes, B, out) : objective_t<float>(c, x, codes, B, out);
+  return c->sr == 8 ? objective_t<double>(c, x, codes, B, out, 0) : objective_t<float>(c, x, codes, B, out, 0);
+}
+
+int ocsc_objective_terms(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!x || !codes || !out) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
+  if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
+  return c->sr == 8 ? objective_t<double>(c, x, codes, B, out, 1) : objective_t<float>(c, x, codes, B, out, 1);
+}
+
+int ocsc_surrogate(ocsc_ctx* c, const void* D, double* out) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!out) return fail(c, OCSC_E_INVALID_ARG, "out_host is NULL");
+  if ((uintptr_t)D & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  if (!c->keep_hist) return fail(c, OCSC_E_STATE, "the surrogate needs a context created with OCSC_FLAG_KEEP_HISTORY");
+  return c->sr == 8 ? surrogate_t<double>(c, D, out) : surrogate_t<float>(c, D, out);
+}
+
+int ocsc_diagnostics(ocsc_ctx* c, double* out) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!out) return fail(c, OCSC_E_INVALID_ARG, "out_host is NULL");
+  return c->sr == 8 ? diagnostics_t<double>(c, out) : diagnostics_t<float>(c, out);
 }
 
 int ocsc_sync(ocsc_ctx* c) {
@@ -697,12 +870,13 @@ int ocsc_get_state(ocsc_ctx* c, int which, void* dst) {
   if (!c) return OCSC_E_INVALID_ARG;
   size_t n = 0;
   if (!dst || state_bytes(c, which, &n)) return fail(c, OCSC_E_INVALID_ARG, "bad state item or NULL dst");
-  if (which == OCSC_STATE_CINV || which == OCSC_STATE_G) {
+  if (which == OCSC_STATE_CINV || which == OCSC_STATE_G || which == OCSC_STATE_RHS) {
     int rc = c->sr == 8 ? flush_fold<double>(c) : flush_fold<float>(c);
     if (rc) return rc;
   }
-  if (which == OCSC_STATE_CINV) {
-    int rc = c->sr == 8 ? cinv_layout_t<double>(c, c->Cm, dst, 0) : cinv_layout_t<float>(c, c->Cm, dst, 0);
+  if (which == OCSC_STATE_CINV || which == OCSC_STATE_H) {
+    void* m = which == OCSC_STATE_H ? c->Hm : c->Cm;
+    int rc = c->sr == 8 ? cinv_layout_t<double>(c, m, dst, 0) : cinv_layout_t<float>(c, m, dst, 0);
     if (rc) return rc;
   } else {
     HIPX(c, hipMemcpyAsync(dst, state_ptr(c, which), n, hipMemcpyDeviceToDevice, c->stream));
@@ -716,10 +890,13 @@ int ocsc_set_state(ocsc_ctx* c, int which, const void* src) {
   size_t n = 0;
   if (!src || state_bytes(c, which, &n) || which == OCSC_STATE_ZHAT || which == OCSC_STATE_XHAT)
     return fail(c, OCSC_E_INVALID_ARG, "bad state item or NULL src");
+  // a deferred fold is applied before the item is replaced
+  int rf = c->sr == 8 ? flush_fold<double>(c) : flush_fold<float>(c);
+  if (rf) return rf;
   c->pending_B = 0;
-  c->fold_B = 0;
-  if (which == OCSC_STATE_CINV) {
-    int rc = c->sr == 8 ? cinv_layout_t<double>(c, src, c->Cm, 1) : cinv_layout_t<float>(c, src, c->Cm, 1);
+  if (which == OCSC_STATE_CINV || which == OCSC_STATE_H) {
+    void* m = which == OCSC_STATE_H ? c->Hm : c->Cm;
+    int rc = c->sr == 8 ? cinv_layout_t<double>(c, src, m, 1) : cinv_layout_t<float>(c, src, m, 1);
     if (rc) return rc;
   } else {
     HIPX(c, hipMemcpyAsync(state_ptr(c, which), src, n, hipMemcpyDeviceToDevice, c->stream));

@@ -26,13 +26,17 @@ OCSC_E_UNSUPPORTED = -6
 OCSC_FP64 = 0
 OCSC_FP32 = 1
 OCSC_FLAG_OWN_STREAM = 1
+OCSC_FLAG_KEEP_HISTORY = 2
+OCSC_FLAG_WARM_START = 4
 
-STATE = {"dict_hat": 0, "G": 1, "cinv": 2, "V": 3, "theta": 4, "zhat": 5, "xhat": 6}
+STATE = {"dict_hat": 0, "G": 1, "cinv": 2, "V": 3, "theta": 4, "zhat": 5, "xhat": 6, "H": 7, "sums": 8,
+         "rhs": 9}
 KERNEL_CLASS = {"fft": 0, "zstep": 1, "codeplane": 2, "history": 3, "dstep": 4, "vstep": 5, "other": 6}
 
 EXPORTS = [
     "ocsc_default_opts", "ocsc_init", "ocsc_destroy", "ocsc_set_dictionary", "ocsc_get_dictionary",
-    "ocsc_code_update", "ocsc_history_accumulate", "ocsc_dict_update", "ocsc_objective", "ocsc_sync",
+    "ocsc_code_update", "ocsc_history_accumulate", "ocsc_dict_update", "ocsc_objective",
+    "ocsc_objective_terms", "ocsc_surrogate", "ocsc_diagnostics", "ocsc_sync",
     "ocsc_last_error", "ocsc_state_bytes", "ocsc_get_state", "ocsc_set_state", "ocsc_get_count",
     "ocsc_set_count", "ocsc_profile_enable", "ocsc_profile_read",
 ]
@@ -83,6 +87,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ocsc_history_accumulate": (i32, [vp]),
         "ocsc_dict_update": (i32, [vp]),
         "ocsc_objective": (i32, [vp, vp, vp, i32, ctypes.POINTER(dbl)]),
+        "ocsc_objective_terms": (i32, [vp, vp, vp, i32, ctypes.POINTER(dbl)]),
+        "ocsc_surrogate": (i32, [vp, vp, ctypes.POINTER(dbl)]),
+        "ocsc_diagnostics": (i32, [vp, ctypes.POINTER(dbl)]),
         "ocsc_sync": (i32, [vp]),
         "ocsc_last_error": (ctypes.c_char_p, [vp]),
         "ocsc_state_bytes": (i32, [vp, i32, ctypes.POINTER(i64)]),
@@ -126,11 +133,12 @@ def ocsc_default_opts() -> OcscOpts:
 
 
 def ocsc_init(K, filt_h, filt_w, pad_h, pad_w, lam, rho, *, iters_code=10, iters_dict=10,
-              max_batch=1, precision="f64", rho_dict=0.0, stream=None):
+              max_batch=1, precision="f64", rho_dict=0.0, flags=0, stream=None):
     """Returns an opaque context handle (c_void_p)."""
     L = load()
     o = ocsc_default_opts()
     o.iters_code, o.iters_dict, o.max_batch = iters_code, iters_dict, max_batch
+    o.flags = int(flags)
     o.precision = {"f64": OCSC_FP64, "f32": OCSC_FP32}[precision]
     o.rho_dict = float(rho_dict)
     if stream is None:
@@ -171,6 +179,27 @@ def ocsc_objective(ctx, x, codes, B):
     out = (ctypes.c_double * int(B))()
     _check(ctx, load().ocsc_objective(ctx, _ptr(x), _ptr(codes), int(B), out))
     return list(out)
+
+
+def ocsc_objective_terms(ctx, x, codes, B):
+    """[(1/2 ||x_b - reconstruction_b||^2, ||U_b||_1) for each sample b]."""
+    out = (ctypes.c_double * (2 * int(B)))()
+    _check(ctx, load().ocsc_objective_terms(ctx, _ptr(x), _ptr(codes), int(B), out))
+    return [(out[2 * b], out[2 * b + 1]) for b in range(int(B))]
+
+
+def ocsc_surrogate(ctx, D=None) -> float:
+    out = ctypes.c_double()
+    _check(ctx, load().ocsc_surrogate(ctx, _ptr(D), ctypes.byref(out)))
+    return out.value
+
+
+def ocsc_diagnostics(ctx, K):
+    """Dict with the primal residual, the dictionary norm and per-filter norms."""
+    out = (ctypes.c_double * (2 + 2 * int(K)))()
+    _check(ctx, load().ocsc_diagnostics(ctx, out))
+    v = list(out)
+    return {"primal_residual": v[0], "dict_norm": v[1], "V_norms": v[2:2 + K], "D_norms": v[2 + K:2 + 2 * K]}
 
 
 def ocsc_sync(ctx) -> None:
@@ -227,7 +256,8 @@ class OCSC:
     """A learner on the current CUDA/HIP device (see include/ocsc.h)."""
 
     def __init__(self, K, filt_h, filt_w, pad_h, pad_w, lam, rho, *, iters_code=10, iters_dict=10,
-                 max_batch=1, precision="f64", rho_dict=0.0, device="cuda"):
+                 max_batch=1, precision="f64", rho_dict=0.0, keep_history=False, warm_start=False,
+                 device="cuda"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -235,9 +265,10 @@ class OCSC:
         self.max_batch = max_batch
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         with torch.cuda.device(self.device):
+            flags = (OCSC_FLAG_KEEP_HISTORY if keep_history else 0) | (OCSC_FLAG_WARM_START if warm_start else 0)
             self.ctx = ocsc_init(K, filt_h, filt_w, pad_h, pad_w, lam, rho, iters_code=iters_code,
                                  iters_dict=iters_dict, max_batch=max_batch, precision=precision,
-                                 rho_dict=rho_dict)
+                                 rho_dict=rho_dict, flags=flags)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
@@ -301,18 +332,47 @@ class OCSC:
             codes = codes[None]
         return ocsc_objective(self.ctx, x, codes, x.shape[0])
 
+    def objective_terms(self, x, codes):
+        x = self._dev(x)
+        if x.dim() == 2:
+            x = x[None]
+        codes = self._dev(codes)
+        if codes.dim() == 3:
+            codes = codes[None]
+        return ocsc_objective_terms(self.ctx, x, codes, x.shape[0])
+
+    def surrogate(self, D=None):
+        """Online surrogate F_t at the current dictionary, or at spatial filters D."""
+        if D is not None:
+            D = self._dev(D)
+            if tuple(D.shape) != (self.K,) + self.filt:
+                raise ValueError("filters must have shape (K, filt_h, filt_w)")
+        return ocsc_surrogate(self.ctx, D)
+
+    def diagnostics(self):
+        return ocsc_diagnostics(self.ctx, self.K)
+
     def sync(self):
         ocsc_sync(self.ctx)
 
     def state(self, which):
         n = ocsc_state_bytes(self.ctx, which)
-        buf = self.torch.empty(n // self.dtype.itemsize, dtype=self.dtype, device=self.device)
+        dt = self.torch.float64 if which in ("sums", STATE["sums"]) else self.dtype
+        buf = self.torch.empty(n // dt.itemsize, dtype=dt, device=self.device)
         ocsc_get_state(self.ctx, which, buf)
         return buf
 
     def set_state(self, which, flat):
-        ocsc_set_state(self.ctx, which, self._dev(flat).reshape(-1))
+        if which in ("sums", STATE["sums"]):
+            t = self.torch.as_tensor(flat, dtype=self.torch.float64, device=self.device).contiguous()
+        else:
+            t = self._dev(flat)
+        ocsc_set_state(self.ctx, which, t.reshape(-1))
 
     @property
     def count(self):
         return ocsc_get_count(self.ctx)
+
+    @count.setter
+    def count(self, t):
+        ocsc_set_count(self.ctx, t)

@@ -58,7 +58,7 @@ def test_init_rejects_bad_opts():
     o.struct_size = 8
     assert init_rc(opts=ctypes.byref(o))[0] == B.OCSC_E_INVALID_ARG
     for field, val in (("iters_code", 0), ("iters_dict", 0), ("max_batch", 0), ("precision", 7),
-                       ("flags", 2)):
+                       ("flags", 8), ("flags", B.OCSC_FLAG_KEEP_HISTORY | 16)):
         o = B.ocsc_default_opts()
         setattr(o, field, val)
         assert init_rc(opts=ctypes.byref(o))[0] == B.OCSC_E_INVALID_ARG, field
@@ -79,6 +79,10 @@ def test_null_context_calls():
     for name in ("ocsc_history_accumulate", "ocsc_dict_update", "ocsc_sync"):
         assert getattr(L, name)(None) == B.OCSC_E_INVALID_ARG
     assert L.ocsc_code_update(None, None, 1, None) == B.OCSC_E_INVALID_ARG
+    out = (ctypes.c_double * 4)()
+    assert L.ocsc_surrogate(None, None, out) == B.OCSC_E_INVALID_ARG
+    assert L.ocsc_diagnostics(None, out) == B.OCSC_E_INVALID_ARG
+    assert L.ocsc_objective_terms(None, None, None, 1, out) == B.OCSC_E_INVALID_ARG
 
 
 def test_no_device_is_a_hip_error_not_a_crash():
