@@ -544,6 +544,10 @@ __host__ __device__ inline int sweep_group_vecs(int K, int fpb) {
 __host__ __device__ inline size_t sweep_lds_bytes(int K, int fpb, int fs, int sr, int nvm) {
   return sweep_r_bytes(fpb, fs, sr, nvm) + (size_t)fpb * sweep_group_vecs(K, fpb) * 2 * sr;
 }
+// A plain sweep (no fold) instead holds [C][run of right-hand sides: spw*fpb*K][partial sums: 4K per group].
+__host__ __device__ inline size_t sweep_plain_lds_bytes(int K, int fpb, int fs, int sr, int nvm, int spw) {
+  return sweep_r_bytes(fpb, fs, sr, nvm) + ((size_t)spw * fpb * K + (size_t)fpb * 4 * K) * 2 * sr;
+}
 
 // The prefetch is straight-line code: every lane loads (indices past the slot
 // are clamped to its last vector) and every lane stores (past the slot into
@@ -560,6 +564,47 @@ template <int NV_MAX>
 __device__ __forceinline__ void slot_stage(const v4f (&reg)[NV_MAX], v4f* dst, int tid) {
 #pragma unroll
   for (int v = 0; v < NV_MAX; ++v) dst[tid + v * 256] = reg[v];
+}
+
+// A plain sweep keeps the right-hand sides of a workgroup's whole run of
+// frequencies [f0, f0 + nrun) in LDS as rb[i][k] (i = p - f0), loaded once at
+// the start; each d_p overwrites its right-hand side and the run is stored
+// once at the end.  Per filter row the run is one contiguous stretch of
+// [K][Pf], so HBM sees whole cache lines instead of one 8-byte value per
+// frequency.  All loads of a batch are issued before the first LDS store.
+constexpr int RUN_BATCH = 8;
+
+template <typename T>
+__device__ __forceinline__ void run_load(cx<T>* rb, const cx<T>* __restrict__ src, int f0, int nrun, int K,
+                                         int Pf, int tid) {
+  const int n = K * nrun;
+  for (int c0 = 0; c0 < n; c0 += RUN_BATCH * 256) {
+    cx<T> r[RUN_BATCH];
+#pragma unroll
+    for (int j = 0; j < RUN_BATCH; ++j) {
+      const int e = min(c0 + tid + j * 256, n - 1);
+      const int k = e / nrun, i = e - k * nrun;
+      r[j] = src[(size_t)k * Pf + f0 + i];
+    }
+#pragma unroll
+    for (int j = 0; j < RUN_BATCH; ++j) {
+      const int e = c0 + tid + j * 256;
+      if (e < n) {
+        const int k = e / nrun, i = e - k * nrun;
+        rb[i * K + k] = r[j];
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void run_store(const cx<T>* rb, cx<T>* __restrict__ dst, int f0, int nrun, int K,
+                                          int Pf, int tid) {
+  const int n = K * nrun;
+  for (int e = tid; e < n; e += 256) {
+    const int k = e / nrun, i = e - k * nrun;
+    dst[(size_t)k * Pf + f0 + i] = rb[i * K + k];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -622,18 +667,20 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
   const int nvec = (int)((size_t)fpb * fs * sizeof(T) / 16);
   const bool plain = dout && nfold == 0;
   v4f reg[NVM];
-  cx<T> rpre = mk<T>(0, 0);
-  const int kl = lt < K ? lt : K - 1;   // clamped filter index of this thread's rhs element
 
   auto slot_of = [&](int s) { return reverse ? nslots - 1 - s : s; };
   auto slot_vecs = [&](int sl) {
     return min(nvec, (int)(((size_t)min(fpb, Pf - sl * fpb) * fs * sizeof(T)) / 16));
   };
+  // plain sweep: the run's right-hand sides in LDS (see run_load)
+  const int f0 = (reverse ? nslots - s_end : s_begin) * fpb;
+  const int nrun = min(Pf, (reverse ? nslots - s_begin : s_end) * fpb) - f0;
+  cx<T>* rb = vecs;
+  cx<T>* rpart = vecs + (size_t)slots_per_wg * fpb * K + (size_t)g * 4 * K;
   if (s_begin < s_end) {
     const int sl = slot_of(s_begin);
     slot_fetch<NVM>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sl * fpb * fs), slot_vecs(sl), tid);
-    const int p = min(sl * fpb + g, Pf - 1);
-    if (plain) rpre = rhs[(size_t)kl * Pf + p];
+    if (plain) run_load<T>(rb, rhs, f0, nrun, K, Pf, tid);
   }
   for (int s = s_begin; s < s_end; ++s) {
     const int sl = slot_of(s);
@@ -642,21 +689,20 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
     const int nv = slot_vecs(sl);
     __syncthreads();   // previous slot finished with LDS
     slot_stage<NVM>(reg, reinterpret_cast<v4f*>(Rall), tid);
-    if (plain) xv[lt] = rpre;
     __syncthreads();
-    if (s + 1 < s_end) {   // next slot's C and right-hand side are in flight during this slot
+    if (s + 1 < s_end) {   // next slot's C is in flight during this slot
       const int sn = slot_of(s + 1);
       slot_fetch<NVM>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sn * fpb * fs), slot_vecs(sn), tid);
-      const int pn = min(sn * fpb + g, Pf - 1);
-      if (plain) rpre = rhs[(size_t)kl * Pf + pn];
     }
     if (plain) {
+      // d_p replaces its right-hand side in the run buffer (p - f0 < slots_per_wg * fpb)
+      cx<T>* xr = rb + (size_t)(p - f0) * K;
       if constexpr (CT) {
-        const cx<T>* const xs[1] = {xv};
-        cx<T>* const ys[1] = {yv};
-        herm_matvec_ct<T, KT, 256 / FPB, 1>(R, xs, ys, part, lt);
+        const cx<T>* const xs[1] = {xr};
+        cx<T>* const ys[1] = {xr};
+        herm_matvec_ct<T, KT, 256 / FPB, 1>(R, xs, ys, rpart, lt);
       } else {
-        herm_matvec<T>(R, K, ld, xv, yv, part, lt, tpg, ns);
+        herm_matvec<T>(R, K, ld, xr, xr, rpart, lt, tpg, ns);
       }
     } else if (nfold == 1) {
       // one sample: v = C u and g = C G_new in one pass; d = g - beta v (v^H G_new)
@@ -734,10 +780,11 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       __syncthreads();
       if (dout) herm_matvec<T>(R, K, ld, xv, yv, part, lt, tpg, ns);
     }
-    if (!dout) continue;
+    if (!dout || plain) continue;
     __syncthreads();
     if (ok && lt < K) dout[(size_t)lt * Pf + p] = yv[lt];
   }
+  if (plain && s_begin < s_end) run_store<T>(rb, dout, f0, nrun, K, Pf, tid);   // the last matvec ended with a barrier
 }
 
 // Packed [Pf][K][K] <-> the per-frequency layout of pitch ld = K + 1 and stride fs.

@@ -43,7 +43,7 @@ struct ocsc_ctx {
   int fpb = 1;     // frequencies solved side by side by one D-step workgroup
   int fs = 0;      // reals per frequency of C (K rows of pitch K+1, 16-byte multiple)
   int sweep_wgs = 0, slots_per_wg = 0;
-  size_t sweep_smem = 0, vapply_smem = 0;
+  size_t sweep_smem = 0, plain_smem = 0, vapply_smem = 0;   // LDS of fold sweeps and of plain sweeps
   bool vstep_fused = false;   // one workgroup per filter (filters up to 16 x 16)
   bool keep_hist = false;     // OCSC_FLAG_KEEP_HISTORY
   bool warm = false;          // OCSC_FLAG_WARM_START
@@ -67,7 +67,6 @@ struct ocsc_ctx {
   int pending_B = 0;    // coded samples not yet accumulated
   int fold_B = 0;       // accumulated samples whose fold is still deferred
   unsigned sweep_count = 0;
-  bool serpentine = true;
   std::string err;
   // profiling
   unsigned prof_mask = 0;
@@ -148,7 +147,9 @@ struct ProfScope {
 };
 
 // ---------------------------------------------------------------- dispatch
-constexpr int plane_threads(int ph, int pw) { return ph * pw >= 128 * 128 ? 512 : 256; }
+// 128 x 128 planes: 16 waves per workgroup, so that one CU has enough waves
+// to overlap the LDS and global latencies of the transform passes.
+constexpr int plane_threads(int ph, int pw) { return ph * pw >= 128 * 128 ? 1024 : 256; }
 
 #define OCSC_SIZE_CASES(X) \
   X(32, 32) X(32, 64) X(32, 128) X(64, 32) X(64, 64) X(64, 128) X(128, 32) X(128, 64) X(128, 128)
@@ -269,10 +270,13 @@ int sweep_nvm_for(int K, int fpb, size_t sr) {
 template <typename T>
 int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dout, int cls) {
   ProfScope ps(c, cls);
-  const int reverse = c->serpentine ? (int)(c->sweep_count & 1u) : 0;
+  // successive sweeps alternate direction, so the tail of one sweep is still
+  // in the Infinity Cache at the head of the next
+  const int reverse = (int)(c->sweep_count & 1u);
   c->sweep_count++;
+  const size_t smem = (dout && nfold == 0) ? c->plain_smem : c->sweep_smem;
 #define OCSC_SWEEP(KT, FPB)                                                                                  \
-  hipLaunchKernelGGL((k_dict_sweep<T, KT, FPB>), dim3(c->sweep_wgs), dim3(256), c->sweep_smem, c->stream,     \
+  hipLaunchKernelGGL((k_dict_sweep<T, KT, FPB>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,               \
                      (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh,     \
                      nfold, (cx<T>*)rfold, (cx<T>*)dout, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg, \
                      reverse)
@@ -651,7 +655,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   auto sweep_bytes = [&](int f) { return sweep_lds_bytes(K, f, fs, (int)sr, sweep_nvm_for(K, f, sr)); };
   const size_t max_lds = 160 * 1024 - 1024;
   const size_t max_slot = (size_t)256 * SWEEP_MAXV * 16;
-  if (sweep_bytes(1) > max_lds || (size_t)fs * sr > max_slot)
+  if (sweep_bytes(1) > max_lds || (size_t)fs * sr > max_slot ||
+      sweep_plain_lds_bytes(K, 1, fs, (int)sr, sweep_nvm_for(K, 1, sr), 1) > max_lds)
     return fail(nullptr, OCSC_E_UNSUPPORTED, "K too large for the LDS-resident D-step of this precision");
   while (fpb > 1 && (sweep_bytes(fpb) > 64 * 1024 || (size_t)fpb * fs * sr > max_slot)) fpb /= 2;
 
@@ -669,16 +674,24 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   c->fs = fs;
   c->sweep_smem = sweep_bytes(fpb);
   {
-    // one round of workgroups over the chip; each walks a run of slots
+    // One round of workgroups over the chip; each walks a run of slots.  A
+    // plain sweep also holds the run's right-hand sides in LDS, so the run
+    // length is capped by what fits at the chosen occupancy.
     const int nslots = (c->Pf + fpb - 1) / fpb;
-    int occ = (int)((160 * 1024) / (c->sweep_smem + 64));   // + the kernel's static LDS
+    const int nvm = sweep_nvm_for(K, fpb, sr);
+    const size_t plain0 = sweep_plain_lds_bytes(K, fpb, fs, (int)sr, nvm, 0);
+    const size_t per_slot = (size_t)fpb * K * 2 * sr;
+    int occ = (int)((160 * 1024) / (std::max(c->sweep_smem, plain0 + per_slot) + 64));   // + static LDS
     occ = occ < 1 ? 1 : (occ > 8 ? 8 : occ);
-    const int target = 256 * occ;
-    c->slots_per_wg = (nslots + target - 1) / target;
-    c->sweep_wgs = (nslots + c->slots_per_wg - 1) / c->slots_per_wg;
+    const size_t budget = (size_t)(160 * 1024) / occ - 64;
+    int spw = (nslots + 256 * occ - 1) / (256 * occ);
+    const int spw_max = (int)((budget - plain0) / per_slot);
+    if (spw > spw_max) spw = spw_max;
+    c->slots_per_wg = spw;
+    c->sweep_wgs = (nslots + spw - 1) / spw;
+    c->plain_smem = plain0 + (size_t)spw * per_slot;
   }
   c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * vb * 2 * sr;
-  if (const char* s = std::getenv("OCSC_SERPENTINE")) c->serpentine = std::atoi(s) != 0;
   c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0;
   c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
   c->vstep_fused = sr == 8 ? vstep_fused_ok<double>(pad_h, pad_w, filt_h, filt_w)
@@ -700,14 +713,15 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     c->own_stream = true;
   }
-  if (c->sweep_smem > 64 * 1024) {
+  if (std::max(c->sweep_smem, c->plain_smem) > 64 * 1024) {
     const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>
 #define X(T, KT, FPB) , (const void*)k_dict_sweep<T, KT, FPB>
                          OCSC_SWEEP_SPECS(X)
 #undef X
     };
     for (const void* fn : fns) {
-      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->sweep_smem);
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)std::max(c->sweep_smem, c->plain_smem));
       if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     }
   }
