@@ -28,13 +28,17 @@ sys.path.insert(0, ROOT)
 METRIC = "images/s coded+dict-updated (K=100, 128²) plain vs BF16/served; p99 latency"
 WORKLOAD = "ocsc_128x128_k100_f32"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1706_06972_amd", "csrc", "kernels.hpp")
+# the D-step sweep's source: common helpers and the sweep itself
+KERNEL_SRC = [os.path.join(ROOT, "paper_1706_06972_amd", "csrc", f) for f in ("common.hpp", "dstep.hpp")]
 HBM_SUMMARY = os.path.join(ROOT, "profiles", f"{WORKLOAD}_hbm_bytes.md")
 
 
 def kernel_source_sha256() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def recorded_traffic():
@@ -49,10 +53,10 @@ def recorded_traffic():
     vals = {}
     with open(HBM_SUMMARY) as fh:
         for line in fh:
-            if ":" in line and line.split(":", 1)[0].strip() in ("dstep_traffic_bytes_per_launch", "kernels_hpp_sha256"):
+            if ":" in line and line.split(":", 1)[0].strip() in ("dstep_traffic_bytes_per_launch", "dstep_source_sha256"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernels_hpp_sha256") != kernel_source_sha256():
+    if vals.get("dstep_source_sha256") != kernel_source_sha256():
         return None
     try:
         return int(float(vals["dstep_traffic_bytes_per_launch"]))

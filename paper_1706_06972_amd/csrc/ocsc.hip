@@ -248,7 +248,7 @@ int launch_zstep(ocsc_ctx* c, int B, int first) {
 template <typename T>
 int launch_gamma(ocsc_ctx* c) {
   ProfScope ps(c, OCSC_KC_OTHER);
-  hipLaunchKernelGGL((k_gamma<T>), dim3((c->Pf + 255) / 256), dim3(256), 0, c->stream, (const cx<T>*)c->Dh,
+  hipLaunchKernelGGL((k_gamma<T>), dim3((c->Pf + 63) / 64), dim3(256), 0, c->stream, (const cx<T>*)c->Dh,
                      (T*)c->gam, (T)c->rho, c->K, c->Pf);
   LAUNCHED(c);
   return OCSC_OK;
