@@ -8,6 +8,7 @@
 #pragma once
 #include "common.hpp"
 #include "dstep.hpp"
+#include "vstep.hpp"
 
 namespace ocsc {
 
@@ -276,314 +277,6 @@ __global__ __launch_bounds__(256) void k_gamma(const cx<T>* __restrict__ Dh, T* 
   part[sl][f] = acc;
   __syncthreads();
   if (sl == 0 && p < Pf) gam[p] = (T)1 / (rho + ((part[0][f] + part[1][f]) + (part[2][f] + part[3][f])));
-}
-
-// ---------------------------------------------------------------------------
-// V-step (Proposition 2) by separable pruned DFTs, in two kernels over
-// (column block vb of VB spectrum columns, filter k).
-//
-// k_vstep_alpha: partial sums over the block's columns of
-//   alpha_k[m][n] = (1/P) Re sum_{u, v} c_v X[u][v] e^{+2 pi i (u m/PH + v n/PW)},
-//   X = d_k + Theta_k,  c_v = 1 at v = 0, PW/2 and 2 otherwise,
-// i.e. the crop of the real inverse DFT of a Hermitian spectrum.
-// ---------------------------------------------------------------------------
-// Columns per block: one 128-byte line of complex values (16 FP32, 8 FP64).
-template <typename T> __host__ __device__ constexpr int vblock() { return 128 / (int)(2 * sizeof(T)); }
-constexpr int MAXF = 128;   // filter extent bound (filt <= pad <= 128)
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_vstep_alpha(const cx<T>* __restrict__ d,
-                                                     const cx<T>* __restrict__ Th, T* __restrict__ apart,
-                                                     const cx<T>* __restrict__ twH,
-                                                     const cx<T>* __restrict__ twW, int PH, int PW,
-                                                     int Mh, int Mw, int first) {
-  constexpr int VB = vblock<T>();
-  __shared__ cx<T> X[MAXF * VB];
-  __shared__ cx<T> t[2 * MAXF * VB];
-  __shared__ cx<T> sH[MAXF], sW[MAXF];
-  const int WC = PW / 2 + 1, Pf = PH * WC;
-  const int vb = blockIdx.x, k = blockIdx.y, nvb = gridDim.x;
-  const int v0 = vb * VB, nv = min(VB, WC - v0);
-  const int tid = threadIdx.x;
-  for (int i = tid; i < PH; i += 256) sH[i] = twH[i];
-  for (int i = tid; i < PW; i += 256) sW[i] = twW[i];
-  const cx<T>* dk = d + (size_t)k * Pf;
-  const cx<T>* tk = Th + (size_t)k * Pf;
-  constexpr int NQ = MAXF * VB / 256;
-  cx<T> xd[NQ], xt[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {   // all loads issued before any use
-    const int e = tid + q * 256, u = e / VB, c = e % VB;
-    xd[q] = mk<T>(0, 0);
-    xt[q] = mk<T>(0, 0);
-    if (e < PH * VB && c < nv) {
-      xd[q] = dk[u * WC + v0 + c];
-      if (!first) xt[q] = tk[u * WC + v0 + c];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int e = tid + q * 256;
-    if (e < PH * VB) X[e] = cadd<T>(xd[q], xt[q]);
-  }
-  __syncthreads();
-  // t[m][c] = sum_u X[u][c] e^{+2 pi i u m / PH}, the u-sum split over two threads
-  const int HU = PH / 2;
-  for (int e = tid; e < 2 * Mh * VB; e += 256) {
-    const int hh = e / (Mh * VB), mc = e % (Mh * VB);
-    const int m = mc / VB, c = mc % VB;
-    T ar = 0, ai = 0;
-    for (int u = hh * HU; u < (hh + 1) * HU; ++u) {
-      const cx<T> w = sH[(u * m) & (PH - 1)];   // e^{-2 pi i um/PH}; use its conjugate
-      const cx<T> x = X[u * VB + c];
-      ar += x.x * w.x + x.y * w.y;
-      ai += x.y * w.x - x.x * w.y;
-    }
-    t[e] = mk<T>(ar, ai);
-  }
-  __syncthreads();
-  for (int e = tid; e < Mh * VB; e += 256) t[e] = cadd<T>(t[e], t[Mh * VB + e]);
-  __syncthreads();
-  const T invP = (T)1 / (T)(PH * PW);
-  T* out = apart + ((size_t)k * nvb + vb) * Mh * Mw;
-  for (int e = tid; e < Mh * Mw; e += 256) {
-    const int m = e / Mw, n = e % Mw;
-    T acc = 0;
-    for (int c = 0; c < nv; ++c) {
-      const int v = v0 + c;
-      const T cv = (v == 0 || 2 * v == PW) ? (T)1 : (T)2;
-      const cx<T> w = sW[(v * n) & (PW - 1)];
-      const cx<T> tv = t[m * VB + c];
-      acc += cv * (tv.x * w.x + tv.y * w.y);   // Re(t * conj(w))
-    }
-    out[e] = acc * invP;
-  }
-}
-
-// k_vstep_apply: alpha_k = sum of the partials; V_k = alpha_k / max(||alpha_k||, 1);
-// for the block's columns Vh = F(zero-pad V_k) by separable pruned DFTs, then
-//   Theta <- Theta + d - Vh  (Theta = 0 on entry when first),
-//   rhs   <- G + rho_d (Vh - Theta)   (right-hand side of the next D-step).
-template <typename T>
-__global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d, cx<T>* __restrict__ Th,
-                                                     const cx<T>* __restrict__ G, cx<T>* __restrict__ rhs,
-                                                     const T* __restrict__ apart, T* __restrict__ V,
-                                                     const cx<T>* __restrict__ twH,
-                                                     const cx<T>* __restrict__ twW, int PH, int PW,
-                                                     int Mh, int Mw, T rho_d, int first) {
-  constexpr int VB = vblock<T>();
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* alpha = reinterpret_cast<T*>(smem_raw);                        // [Mh*Mw]
-  cx<T>* rr = reinterpret_cast<cx<T>*>(smem_raw + (((size_t)Mh * Mw * sizeof(T) + 15) & ~(size_t)15));
-  __shared__ T red[256];
-  __shared__ cx<T> sH[MAXF], sW[MAXF];
-  const int WC = PW / 2 + 1, Pf = PH * WC;
-  const int vb = blockIdx.x, k = blockIdx.y, nvb = gridDim.x;
-  const int v0 = vb * VB, nv = min(VB, WC - v0);
-  const int tid = threadIdx.x;
-  const int MM = Mh * Mw;
-  for (int i = tid; i < PH; i += 256) sH[i] = twH[i];
-  for (int i = tid; i < PW; i += 256) sW[i] = twW[i];
-  const T* ap = apart + (size_t)k * nvb * MM;
-  T ss = 0;
-  for (int e = tid; e < MM; e += 256) {
-    T a = 0;
-#pragma unroll 8
-    for (int j = 0; j < nvb; ++j) a += ap[(size_t)j * MM + e];
-    alpha[e] = a;
-    ss += a * a;
-  }
-  red[tid] = ss;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const T nrm = sqrt(red[0]);
-  const T scale = (T)1 / (nrm > (T)1 ? nrm : (T)1);
-  for (int e = tid; e < MM; e += 256) {
-    const T vval = alpha[e] * scale;
-    alpha[e] = vval;
-    if (vb == 0) V[(size_t)k * MM + e] = vval;
-  }
-  __syncthreads();
-  // rr[m][c] = sum_n V[m][n] e^{-2 pi i v n / PW}
-  for (int e = tid; e < Mh * VB; e += 256) {
-    const int m = e / VB, c = e % VB;
-    T ar = 0, ai = 0;
-    if (c < nv) {
-      const int v = v0 + c;
-      for (int n = 0; n < Mw; ++n) {
-        const cx<T> w = sW[(v * n) & (PW - 1)];
-        const T x = alpha[m * Mw + n];
-        ar += x * w.x;
-        ai += x * w.y;
-      }
-    }
-    rr[e] = mk<T>(ar, ai);
-  }
-  __syncthreads();
-  const size_t base = (size_t)k * Pf;
-  constexpr int NQ = MAXF * VB / 256;
-  cx<T> dq[NQ], tq[NQ], gq[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {   // all loads issued before any use
-    const int e = tid + q * 256, u = e / VB, c = e % VB;
-    dq[q] = tq[q] = gq[q] = mk<T>(0, 0);
-    if (e < PH * VB && c < nv) {
-      const size_t idx = base + (size_t)u * WC + v0 + c;
-      dq[q] = d[idx];
-      if (!first) tq[q] = Th[idx];
-      gq[q] = G[idx];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int e = tid + q * 256, u = e / VB, c = e % VB;
-    if (e >= PH * VB || c >= nv) continue;
-    T ar = 0, ai = 0;
-    for (int m = 0; m < Mh; ++m) {
-      const cx<T> w = sH[(u * m) & (PH - 1)];
-      const cx<T> x = rr[m * VB + c];
-      ar += x.x * w.x - x.y * w.y;
-      ai += x.x * w.y + x.y * w.x;
-    }
-    const size_t idx = base + (size_t)u * WC + v0 + c;
-    const cx<T> th = mk<T>(tq[q].x + dq[q].x - ar, tq[q].y + dq[q].y - ai);
-    Th[idx] = th;
-    rhs[idx] = mk<T>(gq[q].x + rho_d * (ar - th.x), gq[q].y + rho_d * (ai - th.y));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Fused V-step (Proposition 2), one workgroup per filter k, for filters of at
-// most VF x VF taps.  With X = d_k + Theta_k held in LDS:
-//   t[m][v]  = sum_u X[u][v] e^{+2 pi i u m / PH}                   (m < M_h)
-//   alpha    = (1/P) Re sum_v c_v t[m][v] e^{+2 pi i v n / PW}        (the crop of
-//              the real inverse DFT; c_v = 1 at v = 0, PW/2 and 2 otherwise)
-//   V_k      = alpha / max(||alpha||, 1)
-//   r[m][v]  = sum_n V_k[m][n] e^{-2 pi i v n / PW};  F(V)[u][v] = sum_m r[m][v] e^{-2 pi i u m / PH}
-//   Theta   <- X - F(V)  (= Theta + d - F(V));  rhs <- G + rho_d (F(V) - Theta)
-// No other workgroup is involved, so the whole step is one launch.
-// ---------------------------------------------------------------------------
-constexpr int VF = 16;
-
-template <typename T, int PH, int PW, int NT, int NQ>
-__global__ __launch_bounds__(NT) void k_vstep_filter(const cx<T>* __restrict__ d, cx<T>* __restrict__ Th,
-                                                     const cx<T>* __restrict__ G, cx<T>* __restrict__ rhs,
-                                                     T* __restrict__ V, const cx<T>* __restrict__ twH,
-                                                     const cx<T>* __restrict__ twW, int Mh, int Mw, T rho_d,
-                                                     int first) {
-  using Gm = PlaneGeom<PH, PW>;
-  constexpr int WC = Gm::WC, PF = Gm::PF;
-  constexpr int FPT = (PF + NT - 1) / NT;   // frequencies per thread in the update
-  __shared__ __align__(16) cx<T> X[PF];
-  __shared__ cx<T> tq[NQ * VF * WC];       // partial t over u-quarters; later r
-  __shared__ cx<T> sH[PH], sW[PW];
-  __shared__ T al[VF * VF];
-  __shared__ T red[NT / 64];
-  const int k = blockIdx.x, tid = threadIdx.x;
-  const size_t base = (size_t)k * PF;
-  // G of this thread's frequencies is fetched now and used at the end
-  cx<T> gq[FPT];
-#pragma unroll
-  for (int j = 0; j < FPT; ++j) {
-    const int e = min(tid + j * NT, PF - 1);
-    gq[j] = G[base + e];
-  }
-  load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
-  {
-    cx<T> dq[FPT], tqv[FPT];
-#pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      const int e = min(tid + j * NT, PF - 1);
-      dq[j] = d[base + e];
-      tqv[j] = first ? mk<T>(0, 0) : Th[base + e];
-    }
-#pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      const int e = tid + j * NT;
-      if (PF % NT == 0 || e < PF) X[e] = cadd<T>(dq[j], tqv[j]);
-    }
-  }
-  __syncthreads();
-  // t over NQ slices of u
-  constexpr int US = PH / NQ;
-  for (int task = tid; task < NQ * Mh * WC; task += NT) {
-    const int q = task / (Mh * WC), r = task - q * (Mh * WC);
-    const int m = r / WC, v = r - m * WC;
-    T ar = 0, ai = 0;
-#pragma unroll 8
-    for (int u = q * US; u < (q + 1) * US; ++u) {
-      const cx<T> w = sH[(u * m) & (PH - 1)];   // e^{-2 pi i um/PH}; its conjugate is used
-      const cx<T> x = X[u * WC + v];
-      ar += x.x * w.x + x.y * w.y;
-      ai += x.y * w.x - x.x * w.y;
-    }
-    tq[(q * VF + m) * WC + v] = mk<T>(ar, ai);
-  }
-  __syncthreads();
-  const T invP = (T)1 / (T)(PH * PW);
-  T ss = 0;
-  for (int task = tid; task < Mh * Mw; task += NT) {
-    const int m = task / Mw, n = task - m * Mw;
-    T acc = 0;
-    for (int v = 0; v < WC; ++v) {
-      cx<T> tv = tq[m * WC + v];
-#pragma unroll
-      for (int q = 1; q < NQ; ++q) tv = cadd<T>(tv, tq[(q * VF + m) * WC + v]);
-      const cx<T> w = sW[(v * n) & (PW - 1)];
-      const T cv = (v == 0 || 2 * v == PW) ? (T)1 : (T)2;
-      acc += cv * (tv.x * w.x + tv.y * w.y);   // Re(t * conj(w))
-    }
-    acc *= invP;
-    al[task] = acc;
-    ss += acc * acc;
-  }
-  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
-  if ((tid & 63) == 0) red[tid >> 6] = ss;
-  __syncthreads();
-  T nrm2 = 0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) nrm2 += red[w];
-  const T nrm = sqrt(nrm2);
-  const T scale = (T)1 / (nrm > (T)1 ? nrm : (T)1);
-  for (int task = tid; task < Mh * Mw; task += NT) {
-    const T vv = al[task] * scale;
-    al[task] = vv;
-    V[(size_t)k * Mh * Mw + task] = vv;
-  }
-  __syncthreads();
-  // r[m][v] = sum_n V[m][n] e^{-2 pi i v n / PW}   (into tq)
-  for (int task = tid; task < Mh * WC; task += NT) {
-    const int m = task / WC, v = task - m * WC;
-    T ar = 0, ai = 0;
-    for (int n = 0; n < Mw; ++n) {
-      const cx<T> w = sW[(v * n) & (PW - 1)];
-      const T x = al[m * Mw + n];
-      ar += x * w.x;
-      ai += x * w.y;
-    }
-    tq[m * WC + v] = mk<T>(ar, ai);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < FPT; ++j) {
-    const int e = tid + j * NT;
-    if (PF % NT != 0 && e >= PF) continue;
-    const int u = e / WC, v = e - u * WC;
-    T ar = 0, ai = 0;
-    for (int m = 0; m < Mh; ++m) {
-      const cx<T> w = sH[(u * m) & (PH - 1)];
-      const cx<T> x = tq[m * WC + v];
-      ar += x.x * w.x - x.y * w.y;
-      ai += x.x * w.y + x.y * w.x;
-    }
-    const cx<T> xv = X[e];
-    const cx<T> th = mk<T>(xv.x - ar, xv.y - ai);
-    Th[base + e] = th;
-    rhs[base + e] = mk<T>(gq[j].x + rho_d * (ar - th.x), gq[j].y + rho_d * (ai - th.y));
-  }
 }
 
 // ---------------------------------------------------------------------------

@@ -321,6 +321,23 @@ bool vstep_fused_ok(int ph, int pw, int mh, int mw) {
 template <typename T>
 int launch_vstep(ocsc_ctx* c, int first) {
   ProfScope ps(c, OCSC_KC_VSTEP);
+  if (c->vstep_fused && sizeof(T) == 4) {
+    // FP32: the pruned DFTs on the matrix cores
+    switch (c->Ph * 1000 + c->Pw) {
+#define X(A, B)                                                                                                \
+  case A * 1000 + B:                                                                                           \
+    hipLaunchKernelGGL((k_vstep_mfma<A, B>), dim3(c->K), dim3(1024), 0, c->stream, (const float2*)c->d,        \
+                       (float2*)c->Th, (const float2*)c->G, (float2*)c->rhs, (float*)c->V,                     \
+                       (const float2*)c->twH, (const float2*)c->twW, c->Mh, c->Mw, (float)c->rho_d, first);    \
+    break;
+      OCSC_SIZE_CASES(X)
+#undef X
+      default:
+        return fail(c, OCSC_E_UNSUPPORTED, "no V-step kernel for this grid");
+    }
+    LAUNCHED(c);
+    return OCSC_OK;
+  }
   if (c->vstep_fused) {
     const cx<T>* tH = (const cx<T>*)c->twH;
     const cx<T>* tW = (const cx<T>*)c->twW;
