@@ -96,6 +96,46 @@ def oracle_baseline(wl, n_steps: int):
             "seconds": dt, "host_cpus": os.cpu_count()}
 
 
+def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2) -> dict:
+    """Minibatch form: B samples coded against one dictionary, folded in index
+    order, one DictOCSC per minibatch (same kernels, same precision)."""
+    import torch
+    import synth
+    from paper_1706_06972_amd import ocsc as L
+    n_img = xs.shape[0]
+    reps = (B + n_img - 1) // n_img
+    pool = torch.cat([xs] * reps, 0)[:B].contiguous()
+    g = L.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
+               iters_dict=wl.iters_dict, max_batch=B, precision="f32", device=dev)
+    g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
+
+    def step():
+        L.ocsc_code_update(g.ctx, pool, B, None)
+        L.ocsc_history_accumulate(g.ctx)
+        L.ocsc_dict_update(g.ctx)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # untimed breakdown: milliseconds per step of each kernel class
+    classes = ("dstep", "history", "zstep", "codeplane", "vstep", "fft")
+    L.ocsc_profile_enable(g.ctx, list(classes))
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    kern = {c: L.ocsc_profile_read(g.ctx, c)[0] / 2 for c in classes}
+    L.ocsc_profile_enable(g.ctx, [])
+    del g
+    torch.cuda.synchronize()
+    return {"batch": B, "value": B * steps / dt, "unit": "images/s", "ms_per_step": 1000.0 * dt / steps,
+            "steps": steps, "warmup": warmup, "form": "minibatch Sherman-Morrison, FP32",
+            "kernel_ms_per_step": kern}
+
+
 def copy_calibration(mib: int) -> None:
     """Device-to-device copies of a known size, to scale the HBM byte counters."""
     import torch
@@ -116,6 +156,8 @@ def main():
     ap.add_argument("--pool", type=int, default=64, help="distinct images resident on the device")
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps timed for cpu_baseline (0: skip)")
     ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per D-step launch")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="also time minibatch steps of this many samples (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -205,6 +247,7 @@ def main():
     }
     del g
     torch.cuda.synchronize()
+    out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
     if args.cpu_steps > 0:
         out["cpu_baseline"] = oracle_baseline(wl, args.cpu_steps)
     else:

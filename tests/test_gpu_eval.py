@@ -203,3 +203,55 @@ def test_flag_gated_calls():
             g.state(item)
         assert e.value.status == L.OCSC_E_INVALID_ARG
     g.close()
+
+
+def test_evaluation_layer_matches_oracle():
+    """Test-set objective (codes re-solved), PSNR, the code-ADMM study and the
+    relative-change stopping rule, FP64 against the oracle."""
+    say("case evaluation layer f64")
+    from paper_1706_06972_amd import evaluate as E
+    from paper_1706_06972_amd.ocsc import OCSC
+    xs = images(8)
+    train, test = xs[:5], xs[5:]
+    g, o = pair("f64", max_batch=2)
+    for x in train:
+        g.step(x)
+        o.step(x[None])
+    # test objective: mean over the test set with codes re-solved, nothing folded
+    t_gpu = E.test_objective(g, test)
+    t_or = float(np.mean([o.objective(x[None], o.code_update(x[None]))[0] for x in test]))
+    assert abs(t_gpu - t_or) / t_or < 1e-10
+    assert g.count == 5
+    p_gpu = E.psnr(g, test)
+    p_or = []
+    for x in test:
+        U = o.code_update(x[None])[0]
+        rec = O.idft2_real(np.sum(o.Dh * O.dft2(U), axis=0), (PH, PW))
+        p_or.append(O.psnr(x, rec))
+    assert abs(p_gpu - float(np.mean(p_or))) < 1e-8
+    # code-ADMM objective after J iterations
+    D0 = synth.initial_dictionary(K, FH, FW, 0)
+    study = E.code_admm_study(lambda J: OCSC(K, FH, FW, PH, PW, 0.5, 1.0, iters_code=J), D0, test, [1, 5, 20])
+    for rec in study:
+        m = O.OCSC(K, FH, FW, PH, PW, 0.5, 1.0, iters_code=rec["iters"])
+        m.set_dictionary(D0)
+        ref = float(np.mean([m.objective(x[None], m.code_update(x[None]))[0] for x in test]))
+        assert abs(rec["objective"] - ref) / ref < 1e-10
+    assert study[-1]["objective"] < study[0]["objective"]
+    g.close()
+
+
+def test_learn_stops_on_relative_change():
+    say("case learn with stopping rule")
+    from paper_1706_06972_amd import evaluate as E
+    xs = images(3)[:, :32, :32].copy()
+    from paper_1706_06972_amd.ocsc import OCSC
+    g = OCSC(4, 5, 5, 32, 32, 0.1, 1.0)
+    g.set_dictionary(synth.initial_dictionary(4, 5, 5))
+    hist = E.learn(g, xs, passes=40, tol=1e-2, test_xs=xs[:1])
+    assert hist[0]["rel_change_Z"] is None and hist[0]["rel_change_D"] > 0
+    last = hist[-1]
+    stopped = last["rel_change_Z"] is not None and last["rel_change_Z"] < 1e-2 and last["rel_change_D"] < 1e-2
+    assert stopped or len(hist) == 40
+    assert all(np.isfinite(h["test_objective"]) for h in hist)
+    g.close()
