@@ -89,9 +89,10 @@ void ocsc_default_opts(ocsc_opts* opts);
  * C_p = I / rho_d at every frequency, t = 0, dictionary spectrum zero until
  * ocsc_set_dictionary.
  *   K >= 1; 1 <= filt_h <= pad_h; 1 <= filt_w <= pad_w; pad_h, pad_w powers of
- *   two in [32, 128]; lambda >= 0 (the l1 weight beta of eq. csc); rho > 0 (the
- *   code-ADMM penalty).  opts may be NULL (defaults).  The device is the current
- *   HIP device at the time of the call.
+ *   two, both in [32, 128] (planes transformed in LDS) or both in {256, 512}
+ *   (two-pass transforms; then max_batch * K <= 65535); lambda >= 0 (the l1
+ *   weight beta of eq. csc); rho > 0 (the code-ADMM penalty).  opts may be NULL
+ *   (defaults).  The device is the current HIP device at the time of the call.
  * Errors: OCSC_E_INVALID_ARG (nothing allocated, *out untouched),
  *   OCSC_E_UNSUPPORTED (size/precision without a kernel), OCSC_E_OOM, OCSC_E_HIP.
  */

@@ -87,12 +87,14 @@ __device__ __forceinline__ void dft_reg(cx<T>* x) {
   }
 }
 
-// Two-stage radix plans for the 1-D lengths used by the plane kernels.
+// Radix plans (two or three stages) for the 1-D lengths of the plane kernels.
 template <int N> struct Plan;
-template <> struct Plan<16> { static constexpr int R1 = 4, R2 = 4; };
-template <> struct Plan<32> { static constexpr int R1 = 8, R2 = 4; };
-template <> struct Plan<64> { static constexpr int R1 = 8, R2 = 8; };
-template <> struct Plan<128> { static constexpr int R1 = 16, R2 = 8; };
+template <> struct Plan<16> { static constexpr int R1 = 4, R2 = 4, R3 = 1; };
+template <> struct Plan<32> { static constexpr int R1 = 8, R2 = 4, R3 = 1; };
+template <> struct Plan<64> { static constexpr int R1 = 8, R2 = 8, R3 = 1; };
+template <> struct Plan<128> { static constexpr int R1 = 16, R2 = 8, R3 = 1; };
+template <> struct Plan<256> { static constexpr int R1 = 16, R2 = 16, R3 = 1; };
+template <> struct Plan<512> { static constexpr int R1 = 8, R2 = 8, R3 = 8; };
 
 // One Stockham stage of radix R on NLINES lines of length N in LDS.
 // Element n of line l is buf[l * LSTR + n * ESTR].  L is the product of the
@@ -147,9 +149,10 @@ __device__ __forceinline__ void stockham_stage(cx<T>* buf, const cx<T>* tab, int
 
 template <int N, int NLINES, int LSTR, int ESTR, int TS, bool LINE_FAST, bool INV, int NT, typename T>
 __device__ __forceinline__ void fft_lines(cx<T>* buf, const cx<T>* tab, int tid) {
-  constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2, R3 = Plan<N>::R3;
   stockham_stage<R1, N, 1, NLINES, LSTR, ESTR, TS, LINE_FAST, INV, NT, T>(buf, tab, tid);
   stockham_stage<R2, N, R1, NLINES, LSTR, ESTR, TS, LINE_FAST, INV, NT, T>(buf, tab, tid);
+  if constexpr (R3 > 1) stockham_stage<R3, N, R1 * R2, NLINES, LSTR, ESTR, TS, LINE_FAST, INV, NT, T>(buf, tab, tid);
 }
 
 // Geometry of a PH x PW real plane held as a half spectrum in LDS.
@@ -164,14 +167,16 @@ template <int PH, int PW> struct PlaneGeom {
 // Forward R2C: buf rows hold (x[2n], x[2n+1]) in slots 0..M-1 on entry and the
 // half spectrum in slots 0..M on exit.  twH[e] = e^{-2 pi i e/PH} (e < PH),
 // twW[e] = e^{-2 pi i e/PW} (e < PW), both in LDS.
-template <int PH, int PW, int NT, typename T>
-__device__ void rfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
-  using G = PlaneGeom<PH, PW>;
-  constexpr int M = G::M, LDW = G::LDW;
-  fft_lines<M, PH, LDW, 1, 2, true, false, NT, T>(buf, twW, tid);
+// Forward R2C of NROWS real rows of length PW: rows of pitch PW/2 + 1 hold
+// (x[2n], x[2n+1]) in slots 0..PW/2-1 on entry and the row's half spectrum
+// in slots 0..PW/2 on exit.  twW[e] = e^{-2 pi i e/PW} in LDS.
+template <int NROWS, int PW, int NT, typename T>
+__device__ void rows_r2c_lds(cx<T>* buf, const cx<T>* twW, int tid) {
+  constexpr int M = PW / 2, LDW = M + 1;
+  fft_lines<M, NROWS, LDW, 1, 2, true, false, NT, T>(buf, twW, tid);
   // split the packed spectrum of each row into the spectrum of the real row
   constexpr int HALF = M / 2 + 1;
-  for (int task = tid; task < PH * HALF; task += NT) {
+  for (int task = tid; task < NROWS * HALF; task += NT) {
     const int r = task / HALF, k = task % HALF;
     cx<T>* row = buf + r * LDW;
     if (k == 0) {
@@ -190,18 +195,15 @@ __device__ void rfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int ti
     }
   }
   __syncthreads();
-  fft_lines<PH, G::WC, 1, LDW, 1, true, false, NT, T>(buf, twH, tid);
 }
 
-// Unnormalised inverse C2R: half spectrum in, P * (x[2n], x[2n+1]) out.
-// The imaginary parts of columns 0 and PW/2 are ignored after the column pass.
-template <int PH, int PW, int NT, typename T>
-__device__ void irfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
-  using G = PlaneGeom<PH, PW>;
-  constexpr int M = G::M, LDW = G::LDW;
-  fft_lines<PH, G::WC, 1, LDW, 1, true, true, NT, T>(buf, twH, tid);
+// Unnormalised inverse C2R of NROWS rows: half spectra in, PW * (x[2n], x[2n+1]) out.
+// The imaginary parts of columns 0 and PW/2 are ignored.
+template <int NROWS, int PW, int NT, typename T>
+__device__ void rows_c2r_lds(cx<T>* buf, const cx<T>* twW, int tid) {
+  constexpr int M = PW / 2, LDW = M + 1;
   constexpr int HALF = M / 2 + 1;
-  for (int task = tid; task < PH * HALF; task += NT) {
+  for (int task = tid; task < NROWS * HALF; task += NT) {
     const int r = task / HALF, k = task % HALF;
     cx<T>* row = buf + r * LDW;
     if (k == 0) {
@@ -216,7 +218,23 @@ __device__ void irfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int t
     }
   }
   __syncthreads();
-  fft_lines<M, PH, LDW, 1, 2, true, true, NT, T>(buf, twW, tid);
+  fft_lines<M, NROWS, LDW, 1, 2, true, true, NT, T>(buf, twW, tid);
+}
+
+template <int PH, int PW, int NT, typename T>
+__device__ void rfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
+  using G = PlaneGeom<PH, PW>;
+  rows_r2c_lds<PH, PW, NT, T>(buf, twW, tid);
+  fft_lines<PH, G::WC, 1, G::LDW, 1, true, false, NT, T>(buf, twH, tid);
+}
+
+// Unnormalised inverse C2R: half spectrum in, P * (x[2n], x[2n+1]) out.
+// The imaginary parts of columns 0 and PW/2 are ignored after the column pass.
+template <int PH, int PW, int NT, typename T>
+__device__ void irfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
+  using G = PlaneGeom<PH, PW>;
+  fft_lines<PH, G::WC, 1, G::LDW, 1, true, true, NT, T>(buf, twH, tid);
+  rows_c2r_lds<PH, PW, NT, T>(buf, twW, tid);
 }
 
 }  // namespace ocsc

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/ocsc.h"
+#include "bigplane.hpp"
 #include "diag.hpp"
 #include "kernels.hpp"
 
@@ -45,6 +46,7 @@ struct ocsc_ctx {
   int sweep_wgs = 0, slots_per_wg = 0;
   size_t sweep_smem = 0, plain_smem = 0, vapply_smem = 0;   // LDS of fold sweeps and of plain sweeps
   bool vstep_fused = false;   // one workgroup per filter (filters up to 16 x 16)
+  bool big = false;           // two-pass plane transforms (a side above 128)
   bool keep_hist = false;     // OCSC_FLAG_KEEP_HISTORY
   bool warm = false;          // OCSC_FLAG_WARM_START
   // runtime
@@ -61,6 +63,7 @@ struct ocsc_ctx {
   // none, per-sample partial sums of the pending codes, running sums, the
   // spectrum of given filters, exported filters, reduction partials, results
   void *Hm = nullptr, *Ubuf = nullptr, *Dv = nullptr, *Dexp = nullptr;
+  void* Yb = nullptr;   // inverse column pass of the code spectra (two-pass grids)
   double *pend = nullptr, *hacc = nullptr, *dpart = nullptr, *dres = nullptr;
   // host-side bookkeeping
   int64_t t = 0;
@@ -153,12 +156,43 @@ constexpr int plane_threads(int ph, int pw) { return ph * pw >= 128 * 128 ? 1024
 
 #define OCSC_SIZE_CASES(X) \
   X(32, 32) X(32, 64) X(32, 128) X(64, 32) X(64, 64) X(64, 128) X(128, 32) X(128, 64) X(128, 128)
+// grids whose planes do not fit in LDS: two-pass transforms (bigplane.hpp)
+#define OCSC_BIG_CASES(X) X(256, 256) X(256, 512) X(512, 256) X(512, 512)
+
+bool big_grid(int ph, int pw) { return ph > 128 || pw > 128; }
+
+// Two-pass forward R2C of nplanes planes into spectra of stride Pf (row pass
+// into dst, column pass in place).
+template <typename T>
+int launch_big_rfft2(ocsc_ctx* c, const T* src, int sh, int sw, long sstride, cx<T>* dst, int nplanes) {
+  const cx<T>* tH = (const cx<T>*)c->twH;
+  const cx<T>* tW = (const cx<T>*)c->twW;
+  const dim3 rows(c->Ph / BIG_RB, nplanes), cols((c->Wc + big_cb<T>() - 1) / big_cb<T>(), nplanes);
+  switch (c->Ph * 1000 + c->Pw) {
+#define X(A, B)                                                                                          \
+  case A * 1000 + B:                                                                                     \
+    hipLaunchKernelGGL((k_big_rows_fwd<T, A, B>), rows, dim3(256), 0, c->stream, src, sh, sw, sstride, dst, \
+                       (long)c->Pf, tW);                                                                 \
+    hipLaunchKernelGGL((k_big_cols<T, A, B, false>), cols, dim3(256), 0, c->stream, dst, dst, tH);       \
+    break;
+    OCSC_BIG_CASES(X)
+#undef X
+    default:
+      return fail(c, OCSC_E_UNSUPPORTED, "no transform kernel for this grid");
+  }
+  LAUNCHED(c);
+  return OCSC_OK;
+}
 
 template <typename T>
 int launch_rfft2(ocsc_ctx* c, const T* src, int sh, int sw, long sstride, cx<T>* dst, long dstride,
                  int nplanes) {
   if (nplanes <= 0) return OCSC_OK;
   ProfScope ps(c, OCSC_KC_FFT);
+  if (c->big) {
+    if (dstride != c->Pf) return fail(c, OCSC_E_INVALID_ARG, "internal: spectrum stride");
+    return launch_big_rfft2<T>(c, src, sh, sw, sstride, dst, nplanes);
+  }
   const cx<T>* tH = (const cx<T>*)c->twH;
   const cx<T>* tW = (const cx<T>*)c->twW;
   switch (c->Ph * 1000 + c->Pw) {
@@ -182,6 +216,26 @@ int launch_irfft2_crop(ocsc_ctx* c, const cx<T>* src, long sstride, T* dst, int 
   ProfScope ps(c, OCSC_KC_FFT);
   const cx<T>* tH = (const cx<T>*)c->twH;
   const cx<T>* tW = (const cx<T>*)c->twW;
+  if (c->big) {
+    // column pass into the code workspace S (free between calls; nplanes <= K), then rows
+    if (sstride != c->Pf || nplanes > c->maxB * c->K) return fail(c, OCSC_E_INVALID_ARG, "internal: spectrum stride");
+    cx<T>* tmp = (cx<T>*)c->S;
+    const dim3 rows((oh + BIG_RB - 1) / BIG_RB, nplanes), cols((c->Wc + big_cb<T>() - 1) / big_cb<T>(), nplanes);
+    switch (c->Ph * 1000 + c->Pw) {
+#define X(A, B)                                                                                           \
+  case A * 1000 + B:                                                                                      \
+    hipLaunchKernelGGL((k_big_cols<T, A, B, true>), cols, dim3(256), 0, c->stream, src, tmp, tH);         \
+    hipLaunchKernelGGL((k_big_rows_inv_crop<T, A, B>), rows, dim3(256), 0, c->stream, (const cx<T>*)tmp,  \
+                       (long)c->Pf, dst, oh, ow, dstride, tW);                                            \
+    break;
+      OCSC_BIG_CASES(X)
+#undef X
+      default:
+        return fail(c, OCSC_E_UNSUPPORTED, "no transform kernel for this grid");
+    }
+    LAUNCHED(c);
+    return OCSC_OK;
+  }
   switch (c->Ph * 1000 + c->Pw) {
 #define X(A, B)                                                                                         \
   case A * 1000 + B:                                                                                    \
@@ -203,6 +257,28 @@ int launch_code_plane(ocsc_ctx* c, int nplanes, T* Uout, int first, int last) {
   const cx<T>* tH = (const cx<T>*)c->twH;
   const cx<T>* tW = (const cx<T>*)c->twW;
   const T kappa = (T)(c->lam / c->rho);
+  if (c->big) {
+    // column inverse of Zh into Y, row pass (U-step, dual, rows of F(U - W)) into S, column pass on S
+    const dim3 rows(c->Ph / BIG_RB, nplanes), cols((c->Wc + big_cb<T>() - 1) / big_cb<T>(), nplanes);
+    switch (c->Ph * 1000 + c->Pw) {
+#define X(A, B)                                                                                             \
+  case A * 1000 + B:                                                                                        \
+    hipLaunchKernelGGL((k_big_cols<T, A, B, true>), cols, dim3(256), 0, c->stream, (const cx<T>*)c->Zh,     \
+                       (cx<T>*)c->Yb, tH);                                                                  \
+    hipLaunchKernelGGL((k_big_code_rows<T, A, B>), rows, dim3(256), 0, c->stream, (const cx<T>*)c->Yb,      \
+                       (T*)c->W, (cx<T>*)c->S, Uout, tW, kappa, first, last);                               \
+    if (!last)                                                                                              \
+      hipLaunchKernelGGL((k_big_cols<T, A, B, false>), cols, dim3(256), 0, c->stream, (const cx<T>*)c->S,   \
+                         (cx<T>*)c->S, tH);                                                                 \
+    break;
+      OCSC_BIG_CASES(X)
+#undef X
+      default:
+        return fail(c, OCSC_E_UNSUPPORTED, "no code-plane kernel for this grid");
+    }
+    LAUNCHED(c);
+    return OCSC_OK;
+  }
   switch (c->Ph * 1000 + c->Pw) {
 #define X(A, B)                                                                                        \
   case A * 1000 + B:                                                                                   \
@@ -360,14 +436,19 @@ int launch_vstep(ocsc_ctx* c, int first) {
     return OCSC_OK;
   }
   dim3 grid(c->nvb, c->K);
-  hipLaunchKernelGGL((k_vstep_alpha<T>), grid, dim3(256), 0, c->stream, (const cx<T>*)c->d,
-                     (const cx<T>*)c->Th, (T*)c->apart, (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph,
-                     c->Pw, c->Mh, c->Mw, first);
-  LAUNCHED(c);
-  hipLaunchKernelGGL((k_vstep_apply<T>), grid, dim3(256), c->vapply_smem, c->stream, (const cx<T>*)c->d,
-                     (cx<T>*)c->Th, (const cx<T>*)c->G, (cx<T>*)c->rhs, (const T*)c->apart, (T*)c->V,
-                     (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph, c->Pw, c->Mh, c->Mw, (T)c->rho_d,
-                     first);
+#define OCSC_VSTEP_COLS(MAXP)                                                                                    \
+  hipLaunchKernelGGL((k_vstep_alpha<T, MAXP>), grid, dim3(256), 0, c->stream, (const cx<T>*)c->d,                \
+                     (const cx<T>*)c->Th, (T*)c->apart, (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph,        \
+                     c->Pw, c->Mh, c->Mw, first);                                                                \
+  hipLaunchKernelGGL((k_vstep_apply<T, MAXP>), grid, dim3(256), c->vapply_smem, c->stream, (const cx<T>*)c->d,   \
+                     (cx<T>*)c->Th, (const cx<T>*)c->G, (cx<T>*)c->rhs, (const T*)c->apart, (T*)c->V,             \
+                     (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph, c->Pw, c->Mh, c->Mw, (T)c->rho_d, first)
+  if (c->big) {
+    OCSC_VSTEP_COLS(512);
+  } else {
+    OCSC_VSTEP_COLS(128);
+  }
+#undef OCSC_VSTEP_COLS
   LAUNCHED(c);
   return OCSC_OK;
 }
@@ -557,7 +638,7 @@ void free_all(ocsc_ctx* c) {
   void** bufs[] = {&c->xh, &c->Dh, &c->gam, &c->S,    &c->Zh,   &c->W,      &c->G,
                    &c->Cm, &c->d,  &c->Th,  &c->rhs,  &c->V,    &c->apart, &c->twH, &c->twW,
                    &c->xh_obj, &c->Hm, &c->Ubuf, &c->Dv, &c->Dexp, (void**)&c->pend, (void**)&c->hacc,
-                   (void**)&c->dpart, (void**)&c->dres};
+                   (void**)&c->dpart, (void**)&c->dres, &c->Yb};
   for (void** b : bufs)
     if (*b) {
       (void)hipFree(*b);
@@ -660,8 +741,11 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   if (o.flags & ~(OCSC_FLAG_OWN_STREAM | OCSC_FLAG_KEEP_HISTORY | OCSC_FLAG_WARM_START))
     return fail(nullptr, OCSC_E_INVALID_ARG, "unknown bits in opts->flags");
   if (!std::isfinite(o.rho_dict)) return fail(nullptr, OCSC_E_INVALID_ARG, "rho_dict must be finite");
-  if (pad_h > 128 || pad_w > 128)
-    return fail(nullptr, OCSC_E_UNSUPPORTED, "this build has plane kernels for grids up to 128 x 128");
+  if (big_grid(pad_h, pad_w) && !((pad_h == 256 || pad_h == 512) && (pad_w == 256 || pad_w == 512)))
+    return fail(nullptr, OCSC_E_UNSUPPORTED,
+                "this build has plane kernels for grids with both sides <= 128 or both sides in {256, 512}");
+  if (big_grid(pad_h, pad_w) && (size_t)o.max_batch * K > 65535)
+    return fail(nullptr, OCSC_E_UNSUPPORTED, "max_batch * K must be <= 65535 on grids above 128");
   const size_t sr = o.precision == OCSC_FP64 ? 8 : 4;
   // D-step sweep: C_p (K rows of pitch K+1) must fit in LDS; a slot of fpb
   // frequencies must fit the prefetch registers (256 threads x SWEEP_MAXV x 16 B)
@@ -709,6 +793,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     c->plain_smem = plain0 + (size_t)spw * per_slot;
   }
   c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * vb * 2 * sr;
+  c->big = big_grid(pad_h, pad_w);
   c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0;
   c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
   c->vstep_fused = sr == 8 ? vstep_fused_ok<double>(pad_h, pad_w, filt_h, filt_w)
@@ -762,7 +847,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
       {(void**)&c->hacc, 2 * sizeof(double)},
       {&c->Hm, c->keep_hist ? Pf * (size_t)c->fs * sr : 0},
       {&c->Ubuf, c->keep_hist ? B * K_ * c->P * sr : 0},
-      {(void**)&c->pend, c->keep_hist ? 2 * B * 64 * sizeof(double) : 0}};
+      {(void**)&c->pend, c->keep_hist ? 2 * B * 64 * sizeof(double) : 0},
+      {&c->Yb, c->big ? B * K_ * Pf * sc : 0}};
   for (auto& a : allocs) {
     if (a.n == 0) continue;
     e = hipMalloc(a.p, a.n);

@@ -16,18 +16,20 @@ namespace ocsc {
 // ---------------------------------------------------------------------------
 // Columns per block: one 128-byte line of complex values (16 FP32, 8 FP64).
 template <typename T> __host__ __device__ constexpr int vblock() { return 128 / (int)(2 * sizeof(T)); }
-constexpr int MAXF = 128;   // filter extent bound (filt <= pad <= 128)
+constexpr int MAXF = 128;   // filter extent bound of these kernels
+constexpr int VCH = 8;      // loads per thread issued together
 
-template <typename T>
+// MAXP: bound on PH and PW (128, or 512 for the two-pass grids).
+template <typename T, int MAXP>
 __global__ __launch_bounds__(256) void k_vstep_alpha(const cx<T>* __restrict__ d,
                                                      const cx<T>* __restrict__ Th, T* __restrict__ apart,
                                                      const cx<T>* __restrict__ twH,
                                                      const cx<T>* __restrict__ twW, int PH, int PW,
                                                      int Mh, int Mw, int first) {
   constexpr int VB = vblock<T>();
-  __shared__ cx<T> X[MAXF * VB];
+  __shared__ cx<T> X[MAXP * VB];
   __shared__ cx<T> t[2 * MAXF * VB];
-  __shared__ cx<T> sH[MAXF], sW[MAXF];
+  __shared__ cx<T> sH[MAXP], sW[MAXP];
   const int WC = PW / 2 + 1, Pf = PH * WC;
   const int vb = blockIdx.x, k = blockIdx.y, nvb = gridDim.x;
   const int v0 = vb * VB, nv = min(VB, WC - v0);
@@ -36,22 +38,23 @@ __global__ __launch_bounds__(256) void k_vstep_alpha(const cx<T>* __restrict__ d
   for (int i = tid; i < PW; i += 256) sW[i] = twW[i];
   const cx<T>* dk = d + (size_t)k * Pf;
   const cx<T>* tk = Th + (size_t)k * Pf;
-  constexpr int NQ = MAXF * VB / 256;
-  cx<T> xd[NQ], xt[NQ];
+  for (int e0 = 0; e0 < PH * VB; e0 += VCH * 256) {
+    cx<T> xd[VCH], xt[VCH];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {   // all loads issued before any use
-    const int e = tid + q * 256, u = e / VB, c = e % VB;
-    xd[q] = mk<T>(0, 0);
-    xt[q] = mk<T>(0, 0);
-    if (e < PH * VB && c < nv) {
-      xd[q] = dk[u * WC + v0 + c];
-      if (!first) xt[q] = tk[u * WC + v0 + c];
+    for (int q = 0; q < VCH; ++q) {   // a chunk's loads are issued before any use
+      const int e = e0 + tid + q * 256, u = e / VB, c = e % VB;
+      xd[q] = mk<T>(0, 0);
+      xt[q] = mk<T>(0, 0);
+      if (e < PH * VB && c < nv) {
+        xd[q] = dk[u * WC + v0 + c];
+        if (!first) xt[q] = tk[u * WC + v0 + c];
+      }
     }
-  }
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int e = tid + q * 256;
-    if (e < PH * VB) X[e] = cadd<T>(xd[q], xt[q]);
+    for (int q = 0; q < VCH; ++q) {
+      const int e = e0 + tid + q * 256;
+      if (e < PH * VB) X[e] = cadd<T>(xd[q], xt[q]);
+    }
   }
   __syncthreads();
   // t[m][c] = sum_u X[u][c] e^{+2 pi i u m / PH}, the u-sum split over two threads
@@ -91,7 +94,7 @@ __global__ __launch_bounds__(256) void k_vstep_alpha(const cx<T>* __restrict__ d
 // for the block's columns Vh = F(zero-pad V_k) by separable pruned DFTs, then
 //   Theta <- Theta + d - Vh  (Theta = 0 on entry when first),
 //   rhs   <- G + rho_d (Vh - Theta)   (right-hand side of the next D-step).
-template <typename T>
+template <typename T, int MAXP>
 __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d, cx<T>* __restrict__ Th,
                                                      const cx<T>* __restrict__ G, cx<T>* __restrict__ rhs,
                                                      const T* __restrict__ apart, T* __restrict__ V,
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d
   T* alpha = reinterpret_cast<T*>(smem_raw);                        // [Mh*Mw]
   cx<T>* rr = reinterpret_cast<cx<T>*>(smem_raw + (((size_t)Mh * Mw * sizeof(T) + 15) & ~(size_t)15));
   __shared__ T red[256];
-  __shared__ cx<T> sH[MAXF], sW[MAXF];
+  __shared__ cx<T> sH[MAXP], sW[MAXP];
   const int WC = PW / 2 + 1, Pf = PH * WC;
   const int vb = blockIdx.x, k = blockIdx.y, nvb = gridDim.x;
   const int v0 = vb * VB, nv = min(VB, WC - v0);
@@ -151,34 +154,35 @@ __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d
   }
   __syncthreads();
   const size_t base = (size_t)k * Pf;
-  constexpr int NQ = MAXF * VB / 256;
-  cx<T> dq[NQ], tq[NQ], gq[NQ];
+  for (int e0 = 0; e0 < PH * VB; e0 += VCH * 256) {
+    cx<T> dq[VCH], tq[VCH], gq[VCH];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {   // all loads issued before any use
-    const int e = tid + q * 256, u = e / VB, c = e % VB;
-    dq[q] = tq[q] = gq[q] = mk<T>(0, 0);
-    if (e < PH * VB && c < nv) {
+    for (int q = 0; q < VCH; ++q) {   // a chunk's loads are issued before any use
+      const int e = e0 + tid + q * 256, u = e / VB, c = e % VB;
+      dq[q] = tq[q] = gq[q] = mk<T>(0, 0);
+      if (e < PH * VB && c < nv) {
+        const size_t idx = base + (size_t)u * WC + v0 + c;
+        dq[q] = d[idx];
+        if (!first) tq[q] = Th[idx];
+        gq[q] = G[idx];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < VCH; ++q) {
+      const int e = e0 + tid + q * 256, u = e / VB, c = e % VB;
+      if (e >= PH * VB || c >= nv) continue;
+      T ar = 0, ai = 0;
+      for (int m = 0; m < Mh; ++m) {
+        const cx<T> w = sH[(u * m) & (PH - 1)];
+        const cx<T> x = rr[m * VB + c];
+        ar += x.x * w.x - x.y * w.y;
+        ai += x.x * w.y + x.y * w.x;
+      }
       const size_t idx = base + (size_t)u * WC + v0 + c;
-      dq[q] = d[idx];
-      if (!first) tq[q] = Th[idx];
-      gq[q] = G[idx];
+      const cx<T> th = mk<T>(tq[q].x + dq[q].x - ar, tq[q].y + dq[q].y - ai);
+      Th[idx] = th;
+      rhs[idx] = mk<T>(gq[q].x + rho_d * (ar - th.x), gq[q].y + rho_d * (ai - th.y));
     }
-  }
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int e = tid + q * 256, u = e / VB, c = e % VB;
-    if (e >= PH * VB || c >= nv) continue;
-    T ar = 0, ai = 0;
-    for (int m = 0; m < Mh; ++m) {
-      const cx<T> w = sH[(u * m) & (PH - 1)];
-      const cx<T> x = rr[m * VB + c];
-      ar += x.x * w.x - x.y * w.y;
-      ai += x.x * w.y + x.y * w.x;
-    }
-    const size_t idx = base + (size_t)u * WC + v0 + c;
-    const cx<T> th = mk<T>(tq[q].x + dq[q].x - ar, tq[q].y + dq[q].y - ai);
-    Th[idx] = th;
-    rhs[idx] = mk<T>(gq[q].x + rho_d * (ar - th.x), gq[q].y + rho_d * (ai - th.y));
   }
 }
 

@@ -65,8 +65,9 @@ def test_init_rejects_bad_opts():
 
 
 def test_unsupported_sizes_are_reported():
-    rc, _, msg = init_rc(ph=256, pw=256)
-    assert rc == B.OCSC_E_UNSUPPORTED and "128" in msg
+    for ph, pw in ((1024, 1024), (128, 256), (512, 64)):
+        rc, _, msg = init_rc(ph=ph, pw=pw)
+        assert rc == B.OCSC_E_UNSUPPORTED and "256, 512" in msg, (ph, pw)
     o = B.ocsc_default_opts()
     o.precision = B.OCSC_FP64
     rc, _, msg = init_rc(K=200, opts=ctypes.byref(o))
