@@ -136,6 +136,56 @@ def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2) -> dict:
             "kernel_ms_per_step": kern}
 
 
+CODING_GRIDS = ((64, 64), (128, 32), (256, 8), (512, 2))   # (grid side, samples per launch)
+
+
+def code_bytes_per_image(K: int, n: int, iters: int, real_bytes: int) -> int:
+    """Algorithmic HBM bytes of coding one n x n sample of a batch: per
+    iteration the Z and F(U - W) hand-offs written and read and the dual read
+    and written (the dictionary spectrum read is shared by the batch); the
+    codes written once."""
+    Pf, P = n * (n // 2 + 1), n * n
+    return iters * (4 * K * Pf * 2 * real_bytes + 2 * K * P * real_bytes) + K * P * real_bytes
+
+
+def coding_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
+    """Coding only (no history, no dictionary update) against one fixed
+    dictionary on 64, 128, 256 and 512 grids, samples of content n/2 x n/2,
+    one context per grid, a batch of samples per launch."""
+    import torch
+    import synth
+    from paper_1706_06972_amd import ocsc as L
+    D0 = synth.initial_dictionary(K, 11, 11, 0)
+    out, inv_sum, bytes_sum = {}, 0.0, 0
+    for n, B in CODING_GRIDS:
+        wl = synth.Workload(name=f"code{n}", pad_h=n, pad_w=n, content_h=n // 2, content_w=n // 2, k_true=K,
+                            density=0.005, sigma_z=10.0, noise=0.01, K=K, filt_h=11, filt_w=11, lam=1.0, rho=1.0,
+                            iters_code=iters, iters_dict=10, batch=B, n_images=B, passes=1, precision="f32", seed=n)
+        xs = torch.as_tensor(synth.images(wl, range(B)), dtype=torch.float32, device=dev).contiguous()
+        g = L.OCSC(K, 11, 11, n, n, 1.0, 1.0, iters_code=iters, max_batch=B, precision="f32", device=dev)
+        g.set_dictionary(D0)
+        codes = torch.empty((B, K, n, n), dtype=torch.float32, device=dev)
+        L.ocsc_code_update(g.ctx, xs, B, codes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            L.ocsc_code_update(g.ctx, xs, B, codes)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        del g, codes
+        torch.cuda.synchronize()
+        rate = B / dt
+        nb = code_bytes_per_image(K, n, iters, 4)
+        out[str(n)] = {"batch": B, "images_per_s": rate, "ms_per_launch": 1000.0 * dt,
+                       "bytes_per_image": nb, "achieved_GBs": nb * rate / 1e9}
+        inv_sum += 1.0 / rate
+        bytes_sum += nb
+    mix = len(CODING_GRIDS) / inv_sum
+    return {"grids": out, "mix_images_per_s": mix,
+            "mix_achieved_GBs": bytes_sum / len(CODING_GRIDS) * mix / 1e9,
+            "note": "equal shares of the four grids; FP32; K=100, 11x11 filters, J_z=10"}
+
+
 def copy_calibration(mib: int) -> None:
     """Device-to-device copies of a known size, to scale the HBM byte counters."""
     import torch
@@ -158,6 +208,7 @@ def main():
     ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per D-step launch")
     ap.add_argument("--batch", type=int, default=64,
                     help="also time minibatch steps of this many samples (0: skip)")
+    ap.add_argument("--coding", type=int, default=1, help="also time coding on 64..512 grids (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -248,6 +299,7 @@ def main():
     del g
     torch.cuda.synchronize()
     out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
+    out["coding"] = coding_run(dev) if args.coding else None
     if args.cpu_steps > 0:
         out["cpu_baseline"] = oracle_baseline(wl, args.cpu_steps)
     else:
