@@ -186,6 +186,26 @@ def coding_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
             "note": "equal shares of the four grids; FP32; K=100, 11x11 filters, J_z=10"}
 
 
+def copy_ceiling(dev, nbytes: int = 346112000, reps: int = 20) -> dict:
+    """Measured device-to-device copy rate of a buffer the size of one D-step
+    sweep's algorithmic bytes (read + write counted), for context beside the
+    8 TB/s peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    s = a.elapsed_time(b) / 1000.0 / reps
+    del src, dst
+    return {"GBs": 2 * nbytes / s / 1e9, "bytes_moved": 2 * nbytes, "kernel": "torch copy_"}
+
+
 def copy_calibration(mib: int) -> None:
     """Device-to-device copies of a known size, to scale the HBM byte counters."""
     import torch
@@ -300,6 +320,7 @@ def main():
     torch.cuda.synchronize()
     out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
     out["coding"] = coding_run(dev) if args.coding else None
+    out["copy_ceiling"] = copy_ceiling(dev)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = oracle_baseline(wl, args.cpu_steps)
     else:
