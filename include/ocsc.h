@@ -128,6 +128,16 @@ int ocsc_get_dictionary(ocsc_ctx* ctx, void* D_dev_out);
 int ocsc_code_update(ocsc_ctx* ctx, const void* x_dev, int B, void* codes_dev_out);
 
 /*
+ * Like ocsc_code_update, but the B samples join the samples already pending
+ * (coded since the last ocsc_history_accumulate) instead of replacing them,
+ * in the next pending slots; the next ocsc_history_accumulate folds them all
+ * in slot order.  This lets a request loop code requests as they arrive and
+ * fold them once.  OCSC_E_INVALID_ARG if the pending samples would exceed
+ * max_batch.
+ */
+int ocsc_code_append(ocsc_ctx* ctx, const void* x_dev, int B, void* codes_dev_out);
+
+/*
  * Fold the spectra kept by the last ocsc_code_update into the history, in
  * sample order (eqs. B_update and C_update, unnormalised):
  *   G_p += conj(z_p) x_p;  C_p <- C_p - (C_p u)(C_p u)^H / (1 + u^H C_p u), u = conj(z_p),
@@ -148,6 +158,24 @@ int ocsc_history_accumulate(ocsc_ctx* ctx);
  * The last d becomes the dictionary spectrum.  OCSC_E_STATE if t = 0.
  */
 int ocsc_dict_update(ocsc_ctx* ctx);
+
+/*
+ * DictOCSC for n contexts on different grids that share one dictionary (a
+ * generalisation of Algorithm 2; the paper uses one grid).  Each context
+ * keeps its own history and runs its own D-step (eq. sub_d_sol); one
+ * consensus V-step (Proposition 2 applied to the weighted mean)
+ *   V = proj( sum_s P_s alpha_s / sum_s P_s ),  alpha_s = crop(Re F_s^-1(d_s + Theta_s)),
+ * gives every context the same V; then Theta_s += d_s - F_s(V).  The weights
+ * P_s make the fixed point minimise the sum of all samples' losses.  Each
+ * context's last d_s becomes its dictionary spectrum.  Cold start only.
+ *   ctxs: n (1..8) distinct contexts with equal K, filter size, precision,
+ *   iters_dict and device, each with t >= 1 (else OCSC_E_STATE); a context
+ *   created with OCSC_FLAG_WARM_START: OCSC_E_UNSUPPORTED.
+ * The work is enqueued on the first context's stream after every member's
+ * earlier work; later work on each member's stream waits for it.  Pending
+ * codes of the members are discarded; deferred folds are applied.
+ */
+int ocsc_dict_update_group(ocsc_ctx* const* ctxs, int n);
 
 /*
  * Objective of eq. csc per sample against the current dictionary:

@@ -206,6 +206,38 @@ def dict_update(G: np.ndarray, C: np.ndarray, rho_d: float, iters: int, filt, sh
     return d, V, Th
 
 
+def dict_update_group(members: list, iters: int, filt, half: bool = True):
+    """DictOCSC over several grid sizes that share one dictionary.
+
+    ``members`` is a list of (G, C, rho_d, shape), one per grid size, each with
+    its own history.  Every iteration runs each size's D-step, then one
+    consensus V-step
+        V = proj_ball( sum_s P_s alpha_s / sum_s P_s ),
+        alpha_s = crop(Re F_s^-1(d_s + Theta_s)),
+    and each size's dual step Theta_s += d_s - F_s(zero-pad V).  The P_s
+    weights follow from rho_d = rho P per size: in the spatial domain each
+    size's penalty is rho/2 ||zero-pad V - F_s^-1(d_s + Theta_s)||^2 times P_s.
+    With one member this is ``dict_update``.  Returns ([d_s], V, [Theta_s]).
+    """
+    K = members[0][0].shape[0]
+    V = np.zeros((K,) + tuple(filt))
+    Ths = [np.zeros_like(G) for G, _, _, _ in members]
+    ds = [None] * len(members)
+    wsum = float(sum(sh[0] * sh[1] for _, _, _, sh in members))
+    for _ in range(iters):
+        acc = np.zeros_like(V)
+        for i, (G, C, rho_d, shape) in enumerate(members):
+            Vh = dft2(zero_pad(V, shape), half)
+            ds[i] = dict_dstep(C, G, Vh, Ths[i], rho_d)
+            acc += shape[0] * shape[1] * crop(idft2_real(ds[i] + Ths[i], shape, half), *filt)
+        alpha = acc / wsum
+        nrm = np.sqrt(np.sum(alpha * alpha, axis=(-2, -1)))
+        V = alpha / np.maximum(nrm, 1.0)[:, None, None]
+        for i, (G, C, rho_d, shape) in enumerate(members):
+            Ths[i] = Ths[i] + ds[i] - dft2(zero_pad(V, shape), half)
+    return ds, V, Ths
+
+
 # --------------------------------------------------------------------------
 # Objective (eq. csc) and online surrogate (Proposition 1)
 # --------------------------------------------------------------------------
@@ -353,6 +385,16 @@ class OCSC:
         if xs.ndim == 2:
             xs, Us = xs[None], Us[None]
         return np.array([objective(x, U, self.Dh, self.lam, self.half) for x, U in zip(xs, Us)])
+
+    @staticmethod
+    def dict_update_group(models: list) -> None:
+        """Consensus DictOCSC over learners on different grids (``dict_update_group``);
+        each learner's dictionary becomes its last D-step iterate."""
+        m0 = models[0]
+        members = [(m.G, m.C, m.rho_d, m.shape) for m in models]
+        ds, V, Ths = dict_update_group(members, m0.iters_dict, m0.filt, m0.half)
+        for m, d, Th in zip(models, ds, Ths):
+            m.Dh, m.V, m.Th = d, V.copy(), Th
 
     def objective_terms(self, xs: np.ndarray, Us: np.ndarray) -> list:
         xs = np.asarray(xs, np.float64)

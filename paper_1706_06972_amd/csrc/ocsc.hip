@@ -252,7 +252,12 @@ int launch_irfft2_crop(ocsc_ctx* c, const cx<T>* src, long sstride, T* dst, int 
 }
 
 template <typename T>
-int launch_code_plane(ocsc_ctx* c, int nplanes, T* Uout, int first, int last) {
+int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int last) {
+  // samples [off, off + nplanes / K) of the code workspace
+  cx<T>* const Zh = (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf;
+  cx<T>* const S = (cx<T>*)c->S + (size_t)off * c->K * c->Pf;
+  cx<T>* const Yb = c->big ? (cx<T>*)c->Yb + (size_t)off * c->K * c->Pf : nullptr;
+  T* const W = (T*)c->W + (size_t)off * c->K * c->P;
   ProfScope ps(c, OCSC_KC_CODEPLANE);
   const cx<T>* tH = (const cx<T>*)c->twH;
   const cx<T>* tW = (const cx<T>*)c->twW;
@@ -263,13 +268,13 @@ int launch_code_plane(ocsc_ctx* c, int nplanes, T* Uout, int first, int last) {
     switch (c->Ph * 1000 + c->Pw) {
 #define X(A, B)                                                                                             \
   case A * 1000 + B:                                                                                        \
-    hipLaunchKernelGGL((k_big_cols<T, A, B, true>), cols, dim3(256), 0, c->stream, (const cx<T>*)c->Zh,     \
-                       (cx<T>*)c->Yb, tH);                                                                  \
-    hipLaunchKernelGGL((k_big_code_rows<T, A, B>), rows, dim3(256), 0, c->stream, (const cx<T>*)c->Yb,      \
-                       (T*)c->W, (cx<T>*)c->S, Uout, tW, kappa, first, last);                               \
+    hipLaunchKernelGGL((k_big_cols<T, A, B, true>), cols, dim3(256), 0, c->stream, (const cx<T>*)Zh, Yb,   \
+                       tH);                                                                                 \
+    hipLaunchKernelGGL((k_big_code_rows<T, A, B>), rows, dim3(256), 0, c->stream, (const cx<T>*)Yb, W, S,   \
+                       Uout, tW, kappa, first, last);                                                       \
     if (!last)                                                                                              \
-      hipLaunchKernelGGL((k_big_cols<T, A, B, false>), cols, dim3(256), 0, c->stream, (const cx<T>*)c->S,   \
-                         (cx<T>*)c->S, tH);                                                                 \
+      hipLaunchKernelGGL((k_big_cols<T, A, B, false>), cols, dim3(256), 0, c->stream, (const cx<T>*)S, S,  \
+                         tH);                                                                               \
     break;
       OCSC_BIG_CASES(X)
 #undef X
@@ -283,7 +288,7 @@ int launch_code_plane(ocsc_ctx* c, int nplanes, T* Uout, int first, int last) {
 #define X(A, B)                                                                                        \
   case A * 1000 + B:                                                                                   \
     hipLaunchKernelGGL((k_code_plane<T, A, B, plane_threads(A, B)>), dim3(nplanes), dim3(plane_threads(A, B)), 0, \
-                       c->stream, (const cx<T>*)c->Zh, (T*)c->W, (cx<T>*)c->S, Uout, tH, tW, kappa,  \
+                       c->stream, (const cx<T>*)Zh, W, S, Uout, tH, tW, kappa,                       \
                        first, last);                                                                   \
     break;
     OCSC_SIZE_CASES(X)
@@ -296,14 +301,14 @@ int launch_code_plane(ocsc_ctx* c, int nplanes, T* Uout, int first, int last) {
 }
 
 template <typename T>
-int launch_zstep(ocsc_ctx* c, int B, int first) {
+int launch_zstep(ocsc_ctx* c, int off, int B, int first) {
   ProfScope ps(c, OCSC_KC_ZSTEP);
   dim3 grid((c->Pf + ZF - 1) / ZF, B);
   const cx<T>* Dh = (const cx<T>*)c->Dh;
   const T* gam = (const T*)c->gam;
-  const cx<T>* xh = (const cx<T>*)c->xh;
-  const cx<T>* S = (const cx<T>*)c->S;
-  cx<T>* Zh = (cx<T>*)c->Zh;
+  const cx<T>* xh = (const cx<T>*)c->xh + (size_t)off * c->Pf;
+  const cx<T>* S = (const cx<T>*)c->S + (size_t)off * c->K * c->Pf;
+  cx<T>* Zh = (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf;
   const int K = c->K, Pf = c->Pf;
   if (K <= 16)
     hipLaunchKernelGGL((k_code_zstep<T, 1>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
@@ -464,31 +469,35 @@ int flush_fold(ocsc_ctx* c) {
 }
 
 // ---------------------------------------------------------------- calls by type
+// Code B samples into the pending slots [off, off + B) (off = 0: a new
+// minibatch; off = pending_B: appended to the pending ones).
 template <typename T>
-int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes) {
+int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes, int off) {
   int rc = flush_fold<T>(c);
   if (rc) return rc;
-  rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh, c->Pf, B);
+  rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh + (size_t)off * c->Pf, c->Pf, B);
   if (rc) return rc;
-  T* Uout = codes ? (T*)codes : (T*)c->Ubuf;   // Ubuf is null unless the history is kept
+  // Ubuf (null unless the history is kept) holds codes the caller does not keep
+  T* Uout = codes ? (T*)codes : (c->Ubuf ? (T*)c->Ubuf + (size_t)off * c->K * c->P : nullptr);
   for (int j = 0; j < c->Jz; ++j) {
-    rc = launch_zstep<T>(c, B, j == 0);
+    rc = launch_zstep<T>(c, off, B, j == 0);
     if (rc) return rc;
-    rc = launch_code_plane<T>(c, B * c->K, Uout, j == 0, j == c->Jz - 1);
+    rc = launch_code_plane<T>(c, off, B * c->K, Uout, j == 0, j == c->Jz - 1);
     if (rc) return rc;
   }
   if (c->keep_hist) {
     // per-sample partial sums of ||x_b||^2 (Parseval) and ||U_b||_1, added to
     // the running sums when the samples are accumulated
     ProfScope ps(c, OCSC_KC_OTHER);
-    hipLaunchKernelGGL((k_wsq<T>), dim3(64, B), dim3(256), 0, c->stream, (const cx<T>*)c->xh,
-                       (const cx<T>*)nullptr, c->pend, 1, c->Pf, c->Pw);
+    hipLaunchKernelGGL((k_wsq<T>), dim3(64, B), dim3(256), 0, c->stream,
+                       (const cx<T>*)c->xh + (size_t)off * c->Pf, (const cx<T>*)nullptr, c->pend + (size_t)off * 64,
+                       1, c->Pf, c->Pw);
     LAUNCHED(c);
     hipLaunchKernelGGL((k_abs_sum<T>), dim3(64, B), dim3(256), 0, c->stream, (const T*)Uout,
-                       c->pend + (size_t)c->maxB * 64, (long)c->K * c->P);
+                       c->pend + (size_t)(c->maxB + off) * 64, (long)c->K * c->P);
     LAUNCHED(c);
   }
-  c->pending_B = B;
+  c->pending_B = off + B;
   return OCSC_OK;
 }
 
@@ -514,6 +523,77 @@ int dict_update_t(ocsc_ctx* c) {
   // (the same kernel as after ocsc_set_dictionary, so a restored learner
   // continues bit for bit)
   return launch_gamma<T>(c);
+}
+
+// One DictOCSC over several contexts (grids) sharing one dictionary: each
+// context's D-step, the column-block alpha partials of every context, one
+// consensus V-step (k_vstep_group_v, weights P_s), then each context's Theta
+// and right-hand side from the common V.  Everything is enqueued on the first
+// context's stream.
+template <typename T>
+int dict_update_group_t(ocsc_ctx* const* cs, int n) {
+  GroupArgs<T> ga{};
+  ga.n = n;
+  for (int s = 0; s < n; ++s) {
+    ga.apart[s] = (const T*)cs[s]->apart;
+    ga.V[s] = (T*)cs[s]->V;
+    ga.nvb[s] = cs[s]->nvb;
+    ga.w[s] = (T)cs[s]->P;
+  }
+  const int K = cs[0]->K, MM = cs[0]->Mh * cs[0]->Mw;
+  for (int tau = 0; tau < cs[0]->Jd; ++tau) {
+    for (int s = 0; s < n; ++s) {
+      ocsc_ctx* c = cs[s];
+      int rc;
+      if (tau == 0 && c->fold_B) {
+        rc = launch_sweep<T>(c, c->fold_B, nullptr, nullptr, c->d, OCSC_KC_HISTORY);
+        c->fold_B = 0;
+      } else {
+        rc = launch_sweep<T>(c, 0, tau == 0 ? c->G : c->rhs, nullptr, c->d, OCSC_KC_DSTEP);
+      }
+      if (rc) return rc;
+    }
+    ProfScope ps(cs[0], OCSC_KC_VSTEP);
+    for (int s = 0; s < n; ++s) {
+      ocsc_ctx* c = cs[s];
+      const dim3 grid(c->nvb, K);
+#define OCSC_GROUP_ALPHA(MAXP)                                                                                  \
+  hipLaunchKernelGGL((k_vstep_alpha<T, MAXP>), grid, dim3(256), 0, c->stream, (const cx<T>*)c->d,               \
+                     (const cx<T>*)c->Th, (T*)c->apart, (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph,       \
+                     c->Pw, c->Mh, c->Mw, tau == 0)
+      if (c->big) {
+        OCSC_GROUP_ALPHA(512);
+      } else {
+        OCSC_GROUP_ALPHA(128);
+      }
+#undef OCSC_GROUP_ALPHA
+      LAUNCHED(c);
+    }
+    hipLaunchKernelGGL((k_vstep_group_v<T>), dim3(K), dim3(256), MM * sizeof(T), cs[0]->stream, ga, MM);
+    LAUNCHED(cs[0]);
+    for (int s = 0; s < n; ++s) {
+      ocsc_ctx* c = cs[s];
+      const dim3 grid(c->nvb, K);
+#define OCSC_GROUP_APPLY(MAXP)                                                                                  \
+  hipLaunchKernelGGL((k_vstep_apply<T, MAXP>), grid, dim3(256), c->vapply_smem, c->stream, (const cx<T>*)c->d,  \
+                     (cx<T>*)c->Th, (const cx<T>*)c->G, (cx<T>*)c->rhs, (const T*)nullptr, (T*)c->V,             \
+                     (const cx<T>*)c->twH, (const cx<T>*)c->twW, c->Ph, c->Pw, c->Mh, c->Mw, (T)c->rho_d,        \
+                     tau == 0)
+      if (c->big) {
+        OCSC_GROUP_APPLY(512);
+      } else {
+        OCSC_GROUP_APPLY(128);
+      }
+#undef OCSC_GROUP_APPLY
+      LAUNCHED(c);
+    }
+  }
+  for (int s = 0; s < n; ++s) {
+    std::swap(cs[s]->Dh, cs[s]->d);
+    int rc = launch_gamma<T>(cs[s]);
+    if (rc) return rc;
+  }
+  return OCSC_OK;
 }
 
 template <typename T>
@@ -915,7 +995,17 @@ int ocsc_code_update(ocsc_ctx* c, const void* x, int B, void* codes) {
   if (!x) return fail(c, OCSC_E_INVALID_ARG, "x_dev is NULL");
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
   if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
-  return c->sr == 8 ? code_update_t<double>(c, x, B, codes) : code_update_t<float>(c, x, B, codes);
+  return c->sr == 8 ? code_update_t<double>(c, x, B, codes, 0) : code_update_t<float>(c, x, B, codes, 0);
+}
+
+int ocsc_code_append(ocsc_ctx* c, const void* x, int B, void* codes) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!x) return fail(c, OCSC_E_INVALID_ARG, "x_dev is NULL");
+  if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  if (B < 1 || c->pending_B + B > c->maxB)
+    return fail(c, OCSC_E_INVALID_ARG, "B must be >= 1 and the pending samples must fit max_batch");
+  const int off = c->pending_B;
+  return c->sr == 8 ? code_update_t<double>(c, x, B, codes, off) : code_update_t<float>(c, x, B, codes, off);
 }
 
 int ocsc_history_accumulate(ocsc_ctx* c) {
@@ -935,6 +1025,69 @@ int ocsc_dict_update(ocsc_ctx* c) {
   if (!c) return OCSC_E_INVALID_ARG;
   if (c->t == 0) return fail(c, OCSC_E_STATE, "dict_update needs at least one accumulated sample");
   return c->sr == 8 ? dict_update_t<double>(c) : dict_update_t<float>(c);
+}
+
+int ocsc_dict_update_group(ocsc_ctx* const* ctxs, int n) {
+  if (!ctxs || n < 1 || n > GROUP_MAX) return fail(nullptr, OCSC_E_INVALID_ARG, "need 1 <= n <= 8 contexts");
+  ocsc_ctx* c0 = ctxs[0];
+  if (!c0) return fail(nullptr, OCSC_E_INVALID_ARG, "NULL context");
+  for (int s = 0; s < n; ++s) {
+    ocsc_ctx* c = ctxs[s];
+    if (!c) return fail(c0, OCSC_E_INVALID_ARG, "NULL context");
+    for (int r = 0; r < s; ++r)
+      if (ctxs[r] == c) return fail(c0, OCSC_E_INVALID_ARG, "a context is listed twice");
+    if (c->K != c0->K || c->Mh != c0->Mh || c->Mw != c0->Mw || c->sr != c0->sr || c->Jd != c0->Jd ||
+        c->device != c0->device)
+      return fail(c0, OCSC_E_INVALID_ARG, "contexts differ in K, filter size, precision, iters_dict or device");
+  }
+  for (int s = 0; s < n; ++s) {
+    if (ctxs[s]->warm) return fail(c0, OCSC_E_UNSUPPORTED, "the shared dictionary update starts cold");
+    if (ctxs[s]->t == 0) return fail(c0, OCSC_E_STATE, "every context needs at least one accumulated sample");
+  }
+  // run on the first context's stream, after every member's earlier work
+  hipStream_t ls = c0->stream;
+  std::vector<hipStream_t> saved(n);
+  std::vector<hipEvent_t> evs;
+  auto cleanup = [&]() {
+    for (int s = 0; s < n; ++s) ctxs[s]->stream = saved[s];
+    for (auto e : evs) (void)hipEventDestroy(e);
+  };
+  for (int s = 0; s < n; ++s) saved[s] = ctxs[s]->stream;
+  for (int s = 1; s < n; ++s) {
+    if (saved[s] == ls) continue;
+    hipEvent_t e = nullptr;
+    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (err == hipSuccess) {
+      evs.push_back(e);
+      err = hipEventRecord(e, saved[s]);
+    }
+    if (err == hipSuccess) err = hipStreamWaitEvent(ls, e, 0);
+    if (err != hipSuccess) {
+      cleanup();
+      return fail(c0, OCSC_E_HIP, std::string("stream ordering: ") + hipGetErrorString(err));
+    }
+  }
+  for (int s = 0; s < n; ++s) {
+    ctxs[s]->stream = ls;
+    ctxs[s]->pending_B = 0;
+  }
+  const int rc = c0->sr == 8 ? dict_update_group_t<double>(ctxs, n) : dict_update_group_t<float>(ctxs, n);
+  // later work on every member's stream waits for the update
+  hipError_t err = hipSuccess;
+  for (int s = 1; s < n && rc == OCSC_OK && err == hipSuccess; ++s) {
+    if (saved[s] == ls) continue;
+    hipEvent_t e = nullptr;
+    err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (err == hipSuccess) {
+      evs.push_back(e);
+      err = hipEventRecord(e, ls);
+    }
+    if (err == hipSuccess) err = hipStreamWaitEvent(saved[s], e, 0);
+  }
+  cleanup();
+  if (rc) return rc;
+  if (err != hipSuccess) return fail(c0, OCSC_E_HIP, std::string("stream ordering: ") + hipGetErrorString(err));
+  return OCSC_OK;
 }
 
 int ocsc_objective(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {

@@ -94,6 +94,8 @@ __global__ __launch_bounds__(256) void k_vstep_alpha(const cx<T>* __restrict__ d
 // for the block's columns Vh = F(zero-pad V_k) by separable pruned DFTs, then
 //   Theta <- Theta + d - Vh  (Theta = 0 on entry when first),
 //   rhs   <- G + rho_d (Vh - Theta)   (right-hand side of the next D-step).
+// apart == nullptr: V is given (the consensus V-step of several grids) and
+// only read.
 template <typename T, int MAXP>
 __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d, cx<T>* __restrict__ Th,
                                                      const cx<T>* __restrict__ G, cx<T>* __restrict__ rhs,
@@ -114,27 +116,31 @@ __global__ __launch_bounds__(256) void k_vstep_apply(const cx<T>* __restrict__ d
   const int MM = Mh * Mw;
   for (int i = tid; i < PH; i += 256) sH[i] = twH[i];
   for (int i = tid; i < PW; i += 256) sW[i] = twW[i];
-  const T* ap = apart + (size_t)k * nvb * MM;
-  T ss = 0;
-  for (int e = tid; e < MM; e += 256) {
-    T a = 0;
+  if (apart) {
+    const T* ap = apart + (size_t)k * nvb * MM;
+    T ss = 0;
+    for (int e = tid; e < MM; e += 256) {
+      T a = 0;
 #pragma unroll 8
-    for (int j = 0; j < nvb; ++j) a += ap[(size_t)j * MM + e];
-    alpha[e] = a;
-    ss += a * a;
-  }
-  red[tid] = ss;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+      for (int j = 0; j < nvb; ++j) a += ap[(size_t)j * MM + e];
+      alpha[e] = a;
+      ss += a * a;
+    }
+    red[tid] = ss;
     __syncthreads();
-  }
-  const T nrm = sqrt(red[0]);
-  const T scale = (T)1 / (nrm > (T)1 ? nrm : (T)1);
-  for (int e = tid; e < MM; e += 256) {
-    const T vval = alpha[e] * scale;
-    alpha[e] = vval;
-    if (vb == 0) V[(size_t)k * MM + e] = vval;
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const T nrm = sqrt(red[0]);
+    const T scale = (T)1 / (nrm > (T)1 ? nrm : (T)1);
+    for (int e = tid; e < MM; e += 256) {
+      const T vval = alpha[e] * scale;
+      alpha[e] = vval;
+      if (vb == 0) V[(size_t)k * MM + e] = vval;
+    }
+  } else {
+    for (int e = tid; e < MM; e += 256) alpha[e] = V[(size_t)k * MM + e];
   }
   __syncthreads();
   // rr[m][c] = sum_n V[m][n] e^{-2 pi i v n / PW}
@@ -544,6 +550,58 @@ __global__ __launch_bounds__(1024) void k_vstep_mfma(const float2* __restrict__ 
     const float2 th = make_float2(xv.x - ar, xv.y - ai);
     Th[base + e] = th;
     rhs[base + e] = make_float2(gny.x + rho_d * (ar - th.x), gny.y + rho_d * (ai - th.y));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Consensus V-step of several grids sharing one dictionary (one workgroup per
+// filter k): alpha = sum_s w_s alpha_s / sum_s w_s with alpha_s the sum of the
+// column-block partials of grid s (k_vstep_alpha) and w_s = P_s; then
+// V_k = alpha / max(||alpha||, 1), written to every grid's V.
+// ---------------------------------------------------------------------------
+constexpr int GROUP_MAX = 8;
+
+template <typename T>
+struct GroupArgs {
+  const T* apart[GROUP_MAX];
+  T* V[GROUP_MAX];
+  int nvb[GROUP_MAX];
+  T w[GROUP_MAX];
+  int n;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vstep_group_v(GroupArgs<T> a, int MM) {
+  __shared__ T red[256];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* alpha = reinterpret_cast<T*>(smem_raw);   // [MM]
+  const int k = blockIdx.x, tid = threadIdx.x;
+  T wsum = 0;
+  for (int s = 0; s < a.n; ++s) wsum += a.w[s];
+  T ss = 0;
+  for (int e = tid; e < MM; e += 256) {
+    T acc = 0;
+    for (int s = 0; s < a.n; ++s) {
+      const T* ap = a.apart[s] + (size_t)k * a.nvb[s] * MM;
+      T part = 0;
+      for (int j = 0; j < a.nvb[s]; ++j) part += ap[(size_t)j * MM + e];
+      acc += a.w[s] * part;
+    }
+    acc /= wsum;
+    alpha[e] = acc;
+    ss += acc * acc;
+  }
+  red[tid] = ss;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const T nrm = sqrt(red[0]);
+  const T scale = (T)1 / (nrm > (T)1 ? nrm : (T)1);
+  for (int e = tid; e < MM; e += 256) {
+    const T v = alpha[e] * scale;
+    for (int s = 0; s < a.n; ++s) a.V[s][(size_t)k * MM + e] = v;
   }
 }
 

@@ -35,7 +35,8 @@ KERNEL_CLASS = {"fft": 0, "zstep": 1, "codeplane": 2, "history": 3, "dstep": 4, 
 
 EXPORTS = [
     "ocsc_default_opts", "ocsc_init", "ocsc_destroy", "ocsc_set_dictionary", "ocsc_get_dictionary",
-    "ocsc_code_update", "ocsc_history_accumulate", "ocsc_dict_update", "ocsc_objective",
+    "ocsc_code_update", "ocsc_code_append", "ocsc_history_accumulate", "ocsc_dict_update",
+    "ocsc_dict_update_group", "ocsc_objective",
     "ocsc_objective_terms", "ocsc_surrogate", "ocsc_diagnostics", "ocsc_sync",
     "ocsc_last_error", "ocsc_state_bytes", "ocsc_get_state", "ocsc_set_state", "ocsc_get_count",
     "ocsc_set_count", "ocsc_profile_enable", "ocsc_profile_read",
@@ -84,6 +85,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ocsc_set_dictionary": (i32, [vp, vp]),
         "ocsc_get_dictionary": (i32, [vp, vp]),
         "ocsc_code_update": (i32, [vp, vp, i32, vp]),
+        "ocsc_code_append": (i32, [vp, vp, i32, vp]),
+        "ocsc_dict_update_group": (i32, [ctypes.POINTER(vp), i32]),
         "ocsc_history_accumulate": (i32, [vp]),
         "ocsc_dict_update": (i32, [vp]),
         "ocsc_objective": (i32, [vp, vp, vp, i32, ctypes.POINTER(dbl)]),
@@ -165,6 +168,15 @@ def ocsc_get_dictionary(ctx, D_out) -> None:
 
 def ocsc_code_update(ctx, x, B, codes_out=None) -> None:
     _check(ctx, load().ocsc_code_update(ctx, _ptr(x), int(B), _ptr(codes_out)))
+
+
+def ocsc_code_append(ctx, x, B, codes_out=None) -> None:
+    _check(ctx, load().ocsc_code_append(ctx, _ptr(x), int(B), _ptr(codes_out)))
+
+
+def ocsc_dict_update_group(ctxs) -> None:
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    _check(ctxs[0], load().ocsc_dict_update_group(arr, len(ctxs)))
 
 
 def ocsc_history_accumulate(ctx) -> None:
@@ -311,11 +323,29 @@ class OCSC:
         self._x_keep = x
         return codes
 
+    def code_append(self, x, codes=None, want_codes=True):
+        """Code samples into the next pending slots (see ocsc_code_append)."""
+        x = self._dev(x)
+        if x.dim() == 2:
+            x = x[None]
+        B = x.shape[0]
+        if tuple(x.shape[1:]) != self.shape:
+            raise ValueError("samples must have shape (B, pad_h, pad_w)")
+        if codes is None and want_codes:
+            codes = self.torch.empty((B, self.K) + self.shape, dtype=self.dtype, device=self.device)
+        ocsc_code_append(self.ctx, x, B, codes)
+        return codes
+
     def history_accumulate(self):
         ocsc_history_accumulate(self.ctx)
 
     def dict_update(self):
         ocsc_dict_update(self.ctx)
+
+    @staticmethod
+    def dict_update_group(models):
+        """Shared-dictionary DictOCSC over learners on different grids."""
+        ocsc_dict_update_group([m.ctx for m in models])
 
     def step(self, x, codes=None, want_codes=True):
         c = self.code_update(x, codes, want_codes)

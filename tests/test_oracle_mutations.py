@@ -80,3 +80,35 @@ def test_vstep_without_real_part_or_ball_is_caught():
     alpha = O.crop(O.idft2_real(d, shape), *filt)
     assert np.max(np.sqrt(np.sum(alpha ** 2, axis=(1, 2)))) > 1.0
     assert np.max(np.sqrt(np.sum(V ** 2, axis=(1, 2)))) <= 1.0 + 1e-15
+
+
+def test_group_closed_form_catches_equal_weights():
+    """The shared-dictionary pin fails when the consensus V-step averages the
+    grid sizes with equal weights instead of P_s."""
+    import tests.test_oracle_pins_eval as T
+    rng = np.random.default_rng(22)
+    filt, groups, crops = (3, 3), [], []
+    for shape, n in (((8, 8), 3), ((16, 16), 5)):
+        xs = [rng.standard_normal(shape) * 0.05 for _ in range(n)]
+        crops += [x[:3, :3] for x in xs]
+        G, C = T._delta_history(xs, shape, float(shape[0] * shape[1]))
+        groups.append((G, C, float(shape[0] * shape[1]), shape))
+    mean = np.mean(crops, axis=0)
+    expect = mean / max(np.linalg.norm(mean), 1.0)
+
+    def equal_weights(members, iters, filt):
+        V = np.zeros((1,) + filt)
+        Ths = [np.zeros_like(G) for G, _, _, _ in members]
+        ds = [None] * len(members)
+        for _ in range(iters):
+            acc = np.zeros_like(V)
+            for i, (G, C, rho_d, shape) in enumerate(members):
+                ds[i] = O.dict_dstep(C, G, O.dft2(O.zero_pad(V, shape)), Ths[i], rho_d)
+                acc += O.crop(O.idft2_real(ds[i] + Ths[i], shape), *filt)
+            alpha = acc / len(members)
+            V = alpha / np.maximum(np.sqrt(np.sum(alpha * alpha, axis=(-2, -1))), 1.0)[:, None, None]
+            for i, (G, C, rho_d, shape) in enumerate(members):
+                Ths[i] = Ths[i] + ds[i] - O.dft2(O.zero_pad(V, shape))
+        return V
+    assert np.linalg.norm(O.dict_update_group(groups, 3000, filt)[1][0] - expect) < 1e-8
+    assert np.linalg.norm(equal_weights(groups, 3000, filt)[0] - expect) > 1e-2

@@ -137,3 +137,49 @@ def test_p22_psnr_of_a_constant_error():
     for c in (1.0, 2.5, 255.0):
         assert abs(O.psnr(x, x + c) - 20.0 * np.log10(255.0 / c)) < 1e-12
     assert abs(O.psnr(x, x + 0.5, peak=1.0) - 20.0 * np.log10(2.0)) < 1e-12
+
+
+# ------------------------------------- P23: DictOCSC shared across grid sizes
+
+def _delta_history(xs, shape, rho_d):
+    """History of delta codes (every code spectrum = 1) for K = 1 on one grid."""
+    fshape = O.dft2(np.zeros(shape)).shape
+    G = np.zeros((1,) + fshape, complex)
+    C = np.broadcast_to(np.eye(1) / rho_d, fshape + (1, 1)).astype(complex)
+    for x in xs:
+        O.history_fold(G, C, np.ones((1,) + fshape, complex), O.dft2(x))
+    return G, C
+
+
+def test_p23_group_with_one_member_is_dict_update():
+    rng = np.random.default_rng(21)
+    shape, filt, K = (8, 8), (3, 3), 3
+    fshape = (8, 5)
+    G = np.zeros((K,) + fshape, complex)
+    C = np.broadcast_to(np.eye(K) / 64.0, fshape + (K, K)).astype(complex)
+    for _ in range(4):
+        O.history_fold(G, C, O.dft2(rng.standard_normal((K,) + shape)), O.dft2(rng.standard_normal(shape)))
+    d1, V1, T1 = O.dict_update(G, C, 64.0, 7, filt, shape)
+    ds, V, Ts = O.dict_update_group([(G, C, 64.0, shape)], 7, filt)
+    assert np.array_equal(d1, ds[0]) and np.array_equal(V1, V) and np.array_equal(T1, Ts[0])
+
+
+@pytest.mark.parametrize("scale", [0.05, 3.0])
+def test_p23_group_closed_form_delta_codes(scale):
+    """K = 1, every code a delta, samples on an 8x8 and a 16x16 grid: the
+    shared filter minimises the sum of all samples' spatial losses over the
+    unit ball, i.e. it is the projection of the mean crop of all samples."""
+    rng = np.random.default_rng(22)
+    filt = (3, 3)
+    groups = []
+    crops = []
+    for shape, n in (((8, 8), 3), ((16, 16), 5)):
+        xs = [rng.standard_normal(shape) * scale for _ in range(n)]
+        crops += [x[:3, :3] for x in xs]
+        rho_d = 1.0 * shape[0] * shape[1]
+        G, C = _delta_history(xs, shape, rho_d)
+        groups.append((G, C, rho_d, shape))
+    mean = np.mean(crops, axis=0)
+    expect = mean / max(np.linalg.norm(mean), 1.0)
+    ds, V, Ts = O.dict_update_group(groups, 3000, filt)
+    assert np.linalg.norm(V[0] - expect) < 1e-8 * max(np.linalg.norm(expect), 1e-3)
