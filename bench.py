@@ -186,6 +186,36 @@ def coding_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
             "note": "equal shares of the four grids; FP32; K=100, 11x11 filters, J_z=10"}
 
 
+def served_run(dev, K: int = 100) -> dict:
+    """Serving form (continuous batching, resident dictionary updated every
+    256 requests, FP32): Poisson arrivals on a mix of 64/128/256/512 grids
+    (shares 8:4:2:1, a 64 GB HBM budget) at a sustainable and at the
+    configured 5,000/s offered rate, and a 128x128-only stream (the shape of
+    the B=1 workload above).  The first tenth of each run is excluded."""
+    import synth
+    from paper_1706_06972_amd.serve import Server, poisson_requests, summarize
+    D0 = synth.initial_dictionary(K, 11, 11, 0)
+    out = {}
+    grids, shares = (64, 128, 256, 512), (8, 4, 2, 1)
+    srv = Server(K, 11, D0, grids=grids, shares=shares, update_every=256, budget=64e9)
+    for rate, n in ((1000.0, 2000), (5000.0, 3000)):
+        reqs = poisson_requests(n, rate, grids, shares, seed=int(rate))
+        m = srv.run(reqs)
+        out[f"mix_{int(rate)}"] = summarize(reqs, m["wall_s"], m["dictionary_updates"], warmup=n // 10)
+    out["mix_slots"] = srv.slots
+    srv.close()
+    srv = Server(K, 11, D0, grids=(128,), shares=(1,), update_every=256, budget=64e9,
+                 max_launch={128: 64})
+    for rate, n in ((4000.0, 6000), (20000.0, 6000)):
+        reqs = poisson_requests(n, rate, (128,), (1,), seed=7)
+        m = srv.run(reqs)
+        out[f"grid128_{int(rate)}"] = summarize(reqs, m["wall_s"], m["dictionary_updates"], warmup=n // 10)
+    srv.close()
+    out["note"] = ("latency = completion event - arrival; inputs copied from pinned host memory inside the "
+                   "latency; dictionary updated every 256 requests (shared across grids)")
+    return out
+
+
 def copy_ceiling(dev, nbytes: int = 346112000, reps: int = 20) -> dict:
     """Measured device-to-device copy rate of a buffer the size of one D-step
     sweep's algorithmic bytes (read + write counted), for context beside the
@@ -229,6 +259,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64,
                     help="also time minibatch steps of this many samples (0: skip)")
     ap.add_argument("--coding", type=int, default=1, help="also time coding on 64..512 grids (0: skip)")
+    ap.add_argument("--served", type=int, default=1, help="also run the serving form (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -321,6 +352,7 @@ def main():
     out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
     out["coding"] = coding_run(dev) if args.coding else None
     out["copy_ceiling"] = copy_ceiling(dev)
+    out["served"] = served_run(dev) if args.served else None
     if args.cpu_steps > 0:
         out["cpu_baseline"] = oracle_baseline(wl, args.cpu_steps)
     else:
