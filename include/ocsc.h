@@ -80,6 +80,13 @@ typedef struct {
 /* opts.flags: warm-start DictOCSC: each ocsc_dict_update continues from the
  * V and Theta of the previous one instead of V = Theta = 0. */
 #define OCSC_FLAG_WARM_START 4
+/* opts.flags: precision form of the history (FP32 contexts, K <= 128, cold
+ * start).  ocsc_history_accumulate adds the minibatch to H and G with the
+ * product conj(Z)^T Z on the BF16 matrix cores (FP32 accumulation, z split
+ * into two BF16 parts, the products hi*hi + hi*lo + lo*hi), then recomputes
+ * C_p = (H_p + rho_d I)^-1 for every frequency from an FP64 Cholesky factor,
+ * instead of the Sherman-Morrison recursion.  Implies OCSC_FLAG_KEEP_HISTORY. */
+#define OCSC_FLAG_CHOLESKY 8
 
 /* Fill *opts with the defaults listed above. */
 void ocsc_default_opts(ocsc_opts* opts);

@@ -220,7 +220,8 @@ __global__ __launch_bounds__(256) void k_code_zstep(const cx<T>* __restrict__ Dh
                                                    const cx<T>* __restrict__ xh,
                                                    const cx<T>* __restrict__ S,
                                                    cx<T>* __restrict__ Zh, int K, int Pf,
-                                                   int first) {
+                                                   int first, cx<T>* __restrict__ Zt, int ldt, int bt0) {
+  // Zt (optional): the same values frequency-major, Zt[(p * ldt + bt0 + b) * K + k]
   __shared__ cx<T> red[16][ZF + 1];
   const int f = threadIdx.x % ZF, kq = threadIdx.x / ZF;
   const int b = blockIdx.y;
@@ -254,7 +255,11 @@ __global__ __launch_bounds__(256) void k_code_zstep(const cx<T>* __restrict__ Dh
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
     const int k = kq + j * 16;
-    if (ok && k < K) Zh[((size_t)b * K + k) * Pf + p] = cadd<T>(s[j], cmulc<T>(qv, a[j]));
+    if (ok && k < K) {
+      const cx<T> z = cadd<T>(s[j], cmulc<T>(qv, a[j]));
+      Zh[((size_t)b * K + k) * Pf + p] = z;
+      if (Zt) Zt[((size_t)p * ldt + bt0 + b) * K + k] = z;
+    }
   }
 }
 

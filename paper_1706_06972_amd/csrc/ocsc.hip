@@ -18,6 +18,7 @@
 
 #include "../../include/ocsc.h"
 #include "bigplane.hpp"
+#include "chol.hpp"
 #include "diag.hpp"
 #include "kernels.hpp"
 
@@ -47,7 +48,8 @@ struct ocsc_ctx {
   size_t sweep_smem = 0, plain_smem = 0, vapply_smem = 0;   // LDS of fold sweeps and of plain sweeps
   bool vstep_fused = false;   // one workgroup per filter (filters up to 16 x 16)
   bool big = false;           // two-pass plane transforms (a side above 128)
-  bool keep_hist = false;     // OCSC_FLAG_KEEP_HISTORY
+  bool keep_hist = false;     // OCSC_FLAG_KEEP_HISTORY (implied by OCSC_FLAG_CHOLESKY)
+  bool chol = false;          // OCSC_FLAG_CHOLESKY: matrix-core history, C from an FP64 Cholesky
   bool warm = false;          // OCSC_FLAG_WARM_START
   // runtime
   int device = 0;
@@ -64,6 +66,7 @@ struct ocsc_ctx {
   // spectrum of given filters, exported filters, reduction partials, results
   void *Hm = nullptr, *Ubuf = nullptr, *Dv = nullptr, *Dexp = nullptr;
   void* Yb = nullptr;   // inverse column pass of the code spectra (two-pass grids)
+  void* Zt = nullptr;   // last code spectra frequency-major [Pf][max_batch][K] (Cholesky form)
   double *pend = nullptr, *hacc = nullptr, *dpart = nullptr, *dres = nullptr;
   // host-side bookkeeping
   int64_t t = 0;
@@ -301,7 +304,7 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
 }
 
 template <typename T>
-int launch_zstep(ocsc_ctx* c, int off, int B, int first) {
+int launch_zstep(ocsc_ctx* c, int off, int B, int first, bool last) {
   ProfScope ps(c, OCSC_KC_ZSTEP);
   dim3 grid((c->Pf + ZF - 1) / ZF, B);
   const cx<T>* Dh = (const cx<T>*)c->Dh;
@@ -310,16 +313,18 @@ int launch_zstep(ocsc_ctx* c, int off, int B, int first) {
   const cx<T>* S = (const cx<T>*)c->S + (size_t)off * c->K * c->Pf;
   cx<T>* Zh = (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf;
   const int K = c->K, Pf = c->Pf;
+  // the last iterate also goes frequency-major to the matrix-core history update
+  cx<T>* Zt = (last && c->chol) ? (cx<T>*)c->Zt : nullptr;
   if (K <= 16)
-    hipLaunchKernelGGL((k_code_zstep<T, 1>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 1>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
   else if (K <= 32)
-    hipLaunchKernelGGL((k_code_zstep<T, 2>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 2>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
   else if (K <= 64)
-    hipLaunchKernelGGL((k_code_zstep<T, 4>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 4>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
   else if (K <= 128)
-    hipLaunchKernelGGL((k_code_zstep<T, 8>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 8>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
   else if (K <= 256)
-    hipLaunchKernelGGL((k_code_zstep<T, 16>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first);
+    hipLaunchKernelGGL((k_code_zstep<T, 16>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
   else
     return fail(c, OCSC_E_UNSUPPORTED, "code Z-step supports K <= 256");
   LAUNCHED(c);
@@ -480,7 +485,7 @@ int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes, int off) {
   // Ubuf (null unless the history is kept) holds codes the caller does not keep
   T* Uout = codes ? (T*)codes : (c->Ubuf ? (T*)c->Ubuf + (size_t)off * c->K * c->P : nullptr);
   for (int j = 0; j < c->Jz; ++j) {
-    rc = launch_zstep<T>(c, off, B, j == 0);
+    rc = launch_zstep<T>(c, off, B, j == 0, j == c->Jz - 1);
     if (rc) return rc;
     rc = launch_code_plane<T>(c, off, B * c->K, Uout, j == 0, j == c->Jz - 1);
     if (rc) return rc;
@@ -625,12 +630,40 @@ int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* ou
 
 // Kept history: H_p += sum_b conj(z_bp) z_bp^T and the running sums, at
 // accumulation time (the fold of G and C may still be deferred).
+size_t chol_lds(int K) { return ((size_t)K * (K + 1) / 2 + K) * 16; }
+
+// Precision form: H += conj(Z)^T Z and G += conj(Z)^T x on the matrix cores
+// (BF16 split, FP32 accumulation), then C = (H + rho_d I)^-1 by an FP64
+// Cholesky per frequency.
+int chol_history(ocsc_ctx* c, int B) {
+  ProfScope ps(c, OCSC_KC_HISTORY);
+  const int KP = (c->K + 15) / 16 * 16;
+  switch (KP) {
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL((k_herk_bf16<N>), dim3(c->Pf), dim3(256), 0, c->stream, (const float2*)c->Zt, c->maxB, B, \
+                       (const float2*)c->xh, c->Pf, (float*)c->Hm, c->fs, (float2*)c->G, c->K);               \
+    break;
+    X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128)
+#undef X
+    default:
+      return fail(c, OCSC_E_UNSUPPORTED, "the Cholesky form needs K <= 128");
+  }
+  LAUNCHED(c);
+  hipLaunchKernelGGL(k_chol_inv, dim3(c->Pf), dim3(256), chol_lds(c->K), c->stream, (const float*)c->Hm,
+                     (float*)c->Cm, c->K, c->fs, c->rho_d);
+  LAUNCHED(c);
+  return OCSC_OK;
+}
+
 template <typename T>
 int keep_history_t(ocsc_ctx* c, int B) {
   ProfScope ps(c, OCSC_KC_OTHER);
-  hipLaunchKernelGGL((k_hist_herk<T>), dim3(c->Pf), dim3(256), sizeof(cx<T>) * 8 * c->K, c->stream, (T*)c->Hm,
-                     (const cx<T>*)c->Zh, B, c->K, c->Pf, c->fs);
-  LAUNCHED(c);
+  if (!c->chol) {
+    hipLaunchKernelGGL((k_hist_herk<T>), dim3(c->Pf), dim3(256), sizeof(cx<T>) * 8 * c->K, c->stream, (T*)c->Hm,
+                       (const cx<T>*)c->Zh, B, c->K, c->Pf, c->fs);
+    LAUNCHED(c);
+  }
   hipLaunchKernelGGL(k_hist_sums, dim3(1), dim3(256), 0, c->stream, c->pend, B * 64,
                      c->pend + (size_t)c->maxB * 64, B * 64, c->hacc, 1.0 / c->P);
   LAUNCHED(c);
@@ -718,7 +751,7 @@ void free_all(ocsc_ctx* c) {
   void** bufs[] = {&c->xh, &c->Dh, &c->gam, &c->S,    &c->Zh,   &c->W,      &c->G,
                    &c->Cm, &c->d,  &c->Th,  &c->rhs,  &c->V,    &c->apart, &c->twH, &c->twW,
                    &c->xh_obj, &c->Hm, &c->Ubuf, &c->Dv, &c->Dexp, (void**)&c->pend, (void**)&c->hacc,
-                   (void**)&c->dpart, (void**)&c->dres, &c->Yb};
+                   (void**)&c->dpart, (void**)&c->dres, &c->Yb, &c->Zt};
   for (void** b : bufs)
     if (*b) {
       (void)hipFree(*b);
@@ -818,8 +851,11 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   if (o.max_batch < 1 || o.max_batch > 65535) return fail(nullptr, OCSC_E_INVALID_ARG, "max_batch must be in [1, 65535]");
   if (o.precision != OCSC_FP64 && o.precision != OCSC_FP32)
     return fail(nullptr, OCSC_E_INVALID_ARG, "unknown precision");
-  if (o.flags & ~(OCSC_FLAG_OWN_STREAM | OCSC_FLAG_KEEP_HISTORY | OCSC_FLAG_WARM_START))
+  if (o.flags & ~(OCSC_FLAG_OWN_STREAM | OCSC_FLAG_KEEP_HISTORY | OCSC_FLAG_WARM_START | OCSC_FLAG_CHOLESKY))
     return fail(nullptr, OCSC_E_INVALID_ARG, "unknown bits in opts->flags");
+  if ((o.flags & OCSC_FLAG_CHOLESKY) &&
+      (o.precision != OCSC_FP32 || K > 128 || (o.flags & OCSC_FLAG_WARM_START)))
+    return fail(nullptr, OCSC_E_UNSUPPORTED, "the Cholesky form needs an FP32 context, K <= 128 and a cold start");
   if (!std::isfinite(o.rho_dict)) return fail(nullptr, OCSC_E_INVALID_ARG, "rho_dict must be finite");
   if (big_grid(pad_h, pad_w) && !((pad_h == 256 || pad_h == 512) && (pad_w == 256 || pad_w == 512)))
     return fail(nullptr, OCSC_E_UNSUPPORTED,
@@ -874,7 +910,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   }
   c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * vb * 2 * sr;
   c->big = big_grid(pad_h, pad_w);
-  c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0;
+  c->chol = (o.flags & OCSC_FLAG_CHOLESKY) != 0;
+  c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0 || c->chol;
   c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
   c->vstep_fused = sr == 8 ? vstep_fused_ok<double>(pad_h, pad_w, filt_h, filt_w)
                            : vstep_fused_ok<float>(pad_h, pad_w, filt_h, filt_w);
@@ -894,6 +931,10 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     c->own_stream = true;
+  }
+  if (c->chol && chol_lds(K) > 64 * 1024) {
+    e = hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds(K));
+    if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
   if (std::max(c->sweep_smem, c->plain_smem) > 64 * 1024) {
     const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>
@@ -928,7 +969,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
       {&c->Hm, c->keep_hist ? Pf * (size_t)c->fs * sr : 0},
       {&c->Ubuf, c->keep_hist ? B * K_ * c->P * sr : 0},
       {(void**)&c->pend, c->keep_hist ? 2 * B * 64 * sizeof(double) : 0},
-      {&c->Yb, c->big ? B * K_ * Pf * sc : 0}};
+      {&c->Yb, c->big ? B * K_ * Pf * sc : 0},
+      {&c->Zt, c->chol ? Pf * B * K_ * sc : 0}};
   for (auto& a : allocs) {
     if (a.n == 0) continue;
     e = hipMalloc(a.p, a.n);
@@ -1015,7 +1057,14 @@ int ocsc_history_accumulate(ocsc_ctx* c) {
     int rc = c->sr == 8 ? keep_history_t<double>(c, c->pending_B) : keep_history_t<float>(c, c->pending_B);
     if (rc) return rc;
   }
-  c->fold_B = c->pending_B;
+  if (c->chol) {
+    // G, H and C are updated now; there is no Sherman-Morrison fold to defer
+    int rc = chol_history(c, c->pending_B);
+    if (rc) return rc;
+    c->fold_B = 0;
+  } else {
+    c->fold_B = c->pending_B;
+  }
   c->t += c->pending_B;
   c->pending_B = 0;
   return OCSC_OK;

@@ -28,6 +28,7 @@ OCSC_FP32 = 1
 OCSC_FLAG_OWN_STREAM = 1
 OCSC_FLAG_KEEP_HISTORY = 2
 OCSC_FLAG_WARM_START = 4
+OCSC_FLAG_CHOLESKY = 8
 
 STATE = {"dict_hat": 0, "G": 1, "cinv": 2, "V": 3, "theta": 4, "zhat": 5, "xhat": 6, "H": 7, "sums": 8,
          "rhs": 9}
@@ -269,7 +270,7 @@ class OCSC:
 
     def __init__(self, K, filt_h, filt_w, pad_h, pad_w, lam, rho, *, iters_code=10, iters_dict=10,
                  max_batch=1, precision="f64", rho_dict=0.0, keep_history=False, warm_start=False,
-                 device="cuda"):
+                 cholesky=False, device="cuda"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -277,7 +278,8 @@ class OCSC:
         self.max_batch = max_batch
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         with torch.cuda.device(self.device):
-            flags = (OCSC_FLAG_KEEP_HISTORY if keep_history else 0) | (OCSC_FLAG_WARM_START if warm_start else 0)
+            flags = ((OCSC_FLAG_KEEP_HISTORY if keep_history else 0) | (OCSC_FLAG_WARM_START if warm_start else 0)
+                     | (OCSC_FLAG_CHOLESKY if cholesky else 0))
             self.ctx = ocsc_init(K, filt_h, filt_w, pad_h, pad_w, lam, rho, iters_code=iters_code,
                                  iters_dict=iters_dict, max_batch=max_batch, precision=precision,
                                  rho_dict=rho_dict, flags=flags)

@@ -64,6 +64,14 @@ def test_init_rejects_bad_opts():
         assert init_rc(opts=ctypes.byref(o))[0] == B.OCSC_E_INVALID_ARG, field
 
 
+def test_cholesky_form_limits():
+    for prec, K, extra in ((B.OCSC_FP64, 16, 0), (B.OCSC_FP32, 200, 0), (B.OCSC_FP32, 16, B.OCSC_FLAG_WARM_START)):
+        o = B.ocsc_default_opts()
+        o.precision, o.flags = prec, B.OCSC_FLAG_CHOLESKY | extra
+        rc, _, msg = init_rc(K=K, opts=ctypes.byref(o))
+        assert rc == B.OCSC_E_UNSUPPORTED and "Cholesky" in msg
+
+
 def test_unsupported_sizes_are_reported():
     for ph, pw in ((1024, 1024), (128, 256), (512, 64)):
         rc, _, msg = init_rc(ph=ph, pw=pw)

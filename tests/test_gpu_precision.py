@@ -1,0 +1,63 @@
+"""Precision form (OCSC_FLAG_CHOLESKY): the minibatch history on the BF16
+matrix cores with a split-precision correction, C recomputed from an FP64
+Cholesky per frequency; FP32 code ADMM.  Against the FP64 oracle every
+quantity must be within 1e-3 (norm-wise relative); the errors are printed.
+"""
+import numpy as np
+import pytest
+
+import oracle.ocsc_oracle as O
+import synth
+from tests.gpu_util import rel, say, spectra, to_np, unpack_cinv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def images(n, ph, K_true, seed):
+    wl = synth.Workload(name="t", pad_h=ph, pad_w=ph, content_h=ph - 10, content_w=ph - 10, k_true=K_true,
+                        density=0.01, sigma_z=10.0, noise=0.01, K=K_true, filt_h=11, filt_w=11, lam=1.0, rho=1.0,
+                        iters_code=10, iters_dict=10, batch=1, n_images=n, passes=1, precision="f64", seed=seed)
+    return synth.images(wl, range(n))
+
+
+@pytest.mark.parametrize("K,B,batches", [(16, 8, 2), (100, 6, 2), (40, 70, 1)])
+def test_cholesky_form_matches_oracle(K, B, batches):
+    say(f"case precision form K={K} B={B}")
+    from paper_1706_06972_amd.ocsc import OCSC
+    n = 64
+    xs = images(B * batches, n, 16, 11)
+    g = OCSC(K, 11, 11, n, n, 1.0, 1.0, precision="f32", max_batch=B, cholesky=True)
+    o = O.OCSC(K, 11, 11, n, n, 1.0, 1.0, keep_history=True)
+    D0 = synth.initial_dictionary(K, 11, 11, 0)
+    g.set_dictionary(D0)
+    o.set_dictionary(D0)
+    errs = {}
+    for bi in range(batches):
+        x = xs[bi * B:(bi + 1) * B]
+        U = to_np(g.code_update(x))
+        Uo = o.code_update(x)
+        errs["codes"] = max(errs.get("codes", 0), rel(U, Uo))
+        g.history_accumulate()
+        o.history_accumulate()
+        H = unpack_cinv(to_np(g.state("H")), K, n, n)
+        C = unpack_cinv(to_np(g.state("cinv")), K, n, n)
+        errs["H"] = max(errs.get("H", 0), rel(H, o.H))
+        errs["G"] = max(errs.get("G", 0), rel(spectra(to_np(g.state("G")), (K,), n, n), o.G))
+        errs["C"] = max(errs.get("C", 0), rel(C, o.C))
+        # solve residual of the recomputed inverse against the device's own H
+        A = H + o.rho_d * np.eye(K)
+        res = np.linalg.norm(A @ C - np.eye(K), axis=(-2, -1)) / np.sqrt(K)
+        errs["solve_residual"] = max(errs.get("solve_residual", 0), float(res.max()))
+        g.dict_update()
+        o.dict_update()
+        errs["dict"] = max(errs.get("dict", 0), rel(to_np(g.get_dictionary()), o.get_dictionary()))
+        errs["V"] = max(errs.get("V", 0), rel(to_np(g.state("V")).reshape(K, 11, 11), o.V))
+        f = g.objective(x, torch.as_tensor(U, device="cuda"))
+        fo = o.objective(x, Uo)
+        errs["objective"] = max(errs.get("objective", 0), float(np.max(np.abs(np.array(f) - fo) / np.abs(fo))))
+    say("errors vs FP64 oracle", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v < 1e-3, (k, v)
+    assert g.count == B * batches
+    g.close()
