@@ -58,7 +58,7 @@ def test_init_rejects_bad_opts():
     o.struct_size = 8
     assert init_rc(opts=ctypes.byref(o))[0] == B.OCSC_E_INVALID_ARG
     for field, val in (("iters_code", 0), ("iters_dict", 0), ("max_batch", 0), ("precision", 7),
-                       ("flags", 8), ("flags", B.OCSC_FLAG_KEEP_HISTORY | 16)):
+                       ("flags", 16), ("flags", B.OCSC_FLAG_KEEP_HISTORY | 32)):
         o = B.ocsc_default_opts()
         setattr(o, field, val)
         assert init_rc(opts=ctypes.byref(o))[0] == B.OCSC_E_INVALID_ARG, field
