@@ -96,9 +96,11 @@ def oracle_baseline(wl, n_steps: int):
             "seconds": dt, "host_cpus": os.cpu_count()}
 
 
-def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2) -> dict:
+def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2, cholesky: bool = False) -> dict:
     """Minibatch form: B samples coded against one dictionary, folded in index
-    order, one DictOCSC per minibatch (same kernels, same precision)."""
+    order, one DictOCSC per minibatch (same kernels, same precision).  With
+    cholesky: the precision form (history on the BF16 matrix cores, C from an
+    FP64 Cholesky per frequency)."""
     import torch
     import synth
     from paper_1706_06972_amd import ocsc as L
@@ -106,7 +108,7 @@ def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2) -> dict:
     reps = (B + n_img - 1) // n_img
     pool = torch.cat([xs] * reps, 0)[:B].contiguous()
     g = L.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
-               iters_dict=wl.iters_dict, max_batch=B, precision="f32", device=dev)
+               iters_dict=wl.iters_dict, max_batch=B, precision="f32", cholesky=cholesky, device=dev)
     g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
 
     def step():
@@ -132,7 +134,9 @@ def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2) -> dict:
     del g
     torch.cuda.synchronize()
     return {"batch": B, "value": B * steps / dt, "unit": "images/s", "ms_per_step": 1000.0 * dt / steps,
-            "steps": steps, "warmup": warmup, "form": "minibatch Sherman-Morrison, FP32",
+            "steps": steps, "warmup": warmup,
+            "form": ("precision form: BF16 matrix-core history + FP64 Cholesky inverse, FP32 code"
+                     if cholesky else "minibatch Sherman-Morrison, FP32"),
             "kernel_ms_per_step": kern}
 
 
@@ -350,6 +354,7 @@ def main():
     del g
     torch.cuda.synchronize()
     out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
+    out["precision"] = batched_run(wl, args.batch, xs, dev, cholesky=True) if args.batch > 1 else None
     out["coding"] = coding_run(dev) if args.coding else None
     out["copy_ceiling"] = copy_ceiling(dev)
     out["served"] = served_run(dev) if args.served else None

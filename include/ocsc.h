@@ -234,6 +234,24 @@ int ocsc_diagnostics(ocsc_ctx* ctx, double* out_host);
 /* Wait until all work enqueued on the context stream has finished. */
 int ocsc_sync(ocsc_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Steady-state step as a HIP graph: two bodies of Algorithm 3 (code update,
+ * history accumulate, dictionary update) captured once and replayed, which
+ * removes the per-launch host cost of the ~40 launches of a step.
+ *   x_dev: real [2][B][pad_h][pad_w], read by each launch (the caller refills it);
+ *   codes_dev_out: real [2][B][K][pad_h][pad_w] or NULL.
+ * Capture needs a context on a non-default stream (OCSC_E_UNSUPPORTED) with
+ * no pending codes and no deferred fold (OCSC_E_STATE); capturing does not
+ * run the steps.  Each ocsc_graph_launch runs both steps on the context
+ * stream (t += 2B) with the same results as the eager calls; it needs the
+ * same state (OCSC_E_STATE otherwise).  Eager calls may be interleaved.
+ * ------------------------------------------------------------------------- */
+typedef struct ocsc_graph ocsc_graph;
+int ocsc_graph_create(ocsc_ctx* ctx, const void* x_dev, int B, void* codes_dev_out, ocsc_graph** out);
+int ocsc_graph_launch(ocsc_graph* graph);
+/* Waits for the context stream, then frees the graph.  NULL is accepted. */
+int ocsc_graph_destroy(ocsc_graph* graph);
+
 /* Text of the last failure on this context (or of the last failed ocsc_init
  * when ctx is NULL).  Valid until the next call on the same context. */
 const char* ocsc_last_error(const ocsc_ctx* ctx);

@@ -142,20 +142,23 @@ __global__ __launch_bounds__(256) void k_herk_bf16(const float2* __restrict__ Zt
 //   4. C = X^H X, C_ij = sum_{k >= max(i, j)} conj(X_ki) X_kj, rounded to FP32
 //      in the R-form of C (rows of pitch K + 1 at Cm + p * fs).
 // Dynamic LDS: (K(K+1)/2 + K) complex doubles.  The trailing loops run on a
-// 16 x 16 thread tiling.
+// (CHOL_NT / 16) x 16 thread tiling.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int tri_idx(int i, int j) { return i * (i + 1) / 2 + j; }
 
-__global__ __launch_bounds__(256) void k_chol_inv(const float* __restrict__ Hm, float* __restrict__ Cm, int K,
+constexpr int CHOL_NT = 1024;   // threads per workgroup: 16 waves share each step's work
+
+__global__ __launch_bounds__(CHOL_NT) void k_chol_inv(const float* __restrict__ Hm, float* __restrict__ Cm, int K,
                                                  int fs, double rho_d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double2* L = reinterpret_cast<double2*>(smem_raw);
   double2* col = L + K * (K + 1) / 2;
   const int p = blockIdx.x, tid = threadIdx.x;
+  constexpr int NY = CHOL_NT / 16;
   const int ty = tid >> 4, tx = tid & 15;
   const int ld = K + 1;
   const float* R = Hm + (size_t)p * fs;
-  for (int i = ty; i < K; i += 16)
+  for (int i = ty; i < K; i += NY)
     for (int j = tx; j <= i; j += 16)
       L[tri_idx(i, j)] = (i == j) ? make_double2((double)R[i * ld + i] + rho_d, 0.0)
                                   : make_double2((double)R[j * ld + i], -(double)R[i * ld + j]);
@@ -164,13 +167,13 @@ __global__ __launch_bounds__(256) void k_chol_inv(const float* __restrict__ Hm, 
   for (int j = 0; j < K; ++j) {
     const double d = sqrt(L[tri_idx(j, j)].x);
     const double inv = 1.0 / d;
-    for (int i = j + tid; i < K; i += 256) {
+    for (int i = j + tid; i < K; i += CHOL_NT) {
       const double2 v = L[tri_idx(i, j)];
       col[i] = (i == j) ? make_double2(d, 0.0) : make_double2(v.x * inv, v.y * inv);
     }
     __syncthreads();
-    for (int i = j + tid; i < K; i += 256) L[tri_idx(i, j)] = col[i];
-    for (int i = j + 1 + ty; i < K; i += 16) {
+    for (int i = j + tid; i < K; i += CHOL_NT) L[tri_idx(i, j)] = col[i];
+    for (int i = j + 1 + ty; i < K; i += NY) {
       const double2 a = col[i];
       for (int k = j + 1 + tx; k <= i; k += 16) {   // A_ik -= L_ij conj(L_kj)
         const double2 b = col[k];
@@ -187,13 +190,13 @@ __global__ __launch_bounds__(256) void k_chol_inv(const float* __restrict__ Hm, 
     // X_kk stays in a register until the end of the step: slot (k, k) still
     // holds L_kk for the threads that read it at the start
     const double xkk = 1.0 / L[tri_idx(k, k)].x;
-    for (int i = k + 1 + tid; i < K; i += 256) col[i] = L[tri_idx(i, k)];   // column k of L
-    for (int j = tid; j < k; j += 256) {                                    // row k of X
+    for (int i = k + 1 + tid; i < K; i += CHOL_NT) col[i] = L[tri_idx(i, k)];   // column k of L
+    for (int j = tid; j < k; j += CHOL_NT) {                                    // row k of X
       const double2 bkj = L[tri_idx(k, j)];
       L[tri_idx(k, j)] = make_double2(bkj.x * xkk, bkj.y * xkk);
     }
     __syncthreads();
-    for (int i = k + 1 + ty; i < K; i += 16) {
+    for (int i = k + 1 + ty; i < K; i += NY) {
       const double2 l = col[i];
       for (int j = tx; j <= k; j += 16) {   // B_ij -= L_ik X_kj (B_ik starts at 0)
         const double2 x = (j == k) ? make_double2(xkk, 0.0) : L[tri_idx(k, j)];
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const float* __restrict__ Hm, 
   }
   // 4. C = X^H X (upper triangle and its imaginary parts)
   float* Co = Cm + (size_t)p * fs;
-  for (int i = ty; i < K; i += 16) {
+  for (int i = ty; i < K; i += NY) {
     for (int j = i + tx; j < K; j += 16) {
       double sr = 0.0, si = 0.0;
       for (int k = j; k < K; ++k) {

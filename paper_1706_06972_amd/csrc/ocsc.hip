@@ -650,7 +650,7 @@ int chol_history(ocsc_ctx* c, int B) {
       return fail(c, OCSC_E_UNSUPPORTED, "the Cholesky form needs K <= 128");
   }
   LAUNCHED(c);
-  hipLaunchKernelGGL(k_chol_inv, dim3(c->Pf), dim3(256), chol_lds(c->K), c->stream, (const float*)c->Hm,
+  hipLaunchKernelGGL(k_chol_inv, dim3(c->Pf), dim3(CHOL_NT), chol_lds(c->K), c->stream, (const float*)c->Hm,
                      (float*)c->Cm, c->K, c->fs, c->rho_d);
   LAUNCHED(c);
   return OCSC_OK;
@@ -1167,6 +1167,86 @@ int ocsc_diagnostics(ocsc_ctx* c, double* out) {
   if (!c) return OCSC_E_INVALID_ARG;
   if (!out) return fail(c, OCSC_E_INVALID_ARG, "out_host is NULL");
   return c->sr == 8 ? diagnostics_t<double>(c, out) : diagnostics_t<float>(c, out);
+}
+
+// ---------------------------------------------------------------- graphs
+}  // extern "C"
+
+struct ocsc_graph {
+  ocsc_ctx* c = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int B = 0;
+};
+
+extern "C" {
+
+int ocsc_graph_create(ocsc_ctx* c, const void* x, int B, void* codes, ocsc_graph** out) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!x || !out) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
+  if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
+  if (!c->stream) return fail(c, OCSC_E_UNSUPPORTED, "graph capture needs a context on a non-default stream");
+  if (c->pending_B || c->fold_B) return fail(c, OCSC_E_STATE, "graph capture needs no pending codes and no deferred fold");
+  ocsc_graph* gr = new (std::nothrow) ocsc_graph();
+  if (!gr) return fail(c, OCSC_E_OOM, "host allocation failed");
+  gr->c = c;
+  gr->B = B;
+  // Two steps: each dictionary update swaps the dictionary and D-step buffers,
+  // so after two the buffers (and the sweep directions, J_d sweeps per step)
+  // are where they started and the same graph can be replayed.
+  const unsigned mask = c->prof_mask;
+  const int64_t t0 = c->t;
+  const unsigned sc0 = c->sweep_count;
+  c->prof_mask = 0;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  int rc = e == hipSuccess ? OCSC_OK : fail(c, OCSC_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  const size_t xs = (size_t)B * c->P * c->sr, us = (size_t)B * c->K * c->P * c->sr;
+  for (int s = 0; s < 2 && rc == OCSC_OK; ++s) {
+    rc = ocsc_code_update(c, (const char*)x + s * xs, B, codes ? (char*)codes + s * us : nullptr);
+    if (rc == OCSC_OK) rc = ocsc_history_accumulate(c);
+    if (rc == OCSC_OK) rc = ocsc_dict_update(c);
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->stream, &g);
+  if (rc == OCSC_OK && e != hipSuccess)
+    rc = fail(c, OCSC_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  c->prof_mask = mask;
+  c->t = t0;   // nothing ran yet; each launch counts its 2B samples
+  c->sweep_count = sc0;
+  c->pending_B = c->fold_B = 0;
+  if (rc == OCSC_OK) {
+    gr->graph = g;
+    e = hipGraphInstantiate(&gr->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = fail(c, OCSC_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  } else if (g) {
+    (void)hipGraphDestroy(g);
+  }
+  if (rc != OCSC_OK) {
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return rc;
+  }
+  *out = gr;
+  return OCSC_OK;
+}
+
+int ocsc_graph_launch(ocsc_graph* gr) {
+  if (!gr) return OCSC_E_INVALID_ARG;
+  ocsc_ctx* c = gr->c;
+  if (c->pending_B || c->fold_B) return fail(c, OCSC_E_STATE, "pending codes or a deferred fold");
+  HIPX(c, hipGraphLaunch(gr->exec, c->stream));
+  c->t += 2 * gr->B;
+  return OCSC_OK;
+}
+
+int ocsc_graph_destroy(ocsc_graph* gr) {
+  if (!gr) return OCSC_OK;
+  if (gr->c && gr->c->stream) (void)hipStreamSynchronize(gr->c->stream);
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  delete gr;
+  return OCSC_OK;
 }
 
 int ocsc_sync(ocsc_ctx* c) {

@@ -39,6 +39,7 @@ EXPORTS = [
     "ocsc_code_update", "ocsc_code_append", "ocsc_history_accumulate", "ocsc_dict_update",
     "ocsc_dict_update_group", "ocsc_objective",
     "ocsc_objective_terms", "ocsc_surrogate", "ocsc_diagnostics", "ocsc_sync",
+    "ocsc_graph_create", "ocsc_graph_launch", "ocsc_graph_destroy",
     "ocsc_last_error", "ocsc_state_bytes", "ocsc_get_state", "ocsc_set_state", "ocsc_get_count",
     "ocsc_set_count", "ocsc_profile_enable", "ocsc_profile_read",
 ]
@@ -95,6 +96,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ocsc_surrogate": (i32, [vp, vp, ctypes.POINTER(dbl)]),
         "ocsc_diagnostics": (i32, [vp, ctypes.POINTER(dbl)]),
         "ocsc_sync": (i32, [vp]),
+        "ocsc_graph_create": (i32, [vp, vp, i32, vp, ctypes.POINTER(vp)]),
+        "ocsc_graph_launch": (i32, [vp]),
+        "ocsc_graph_destroy": (i32, [vp]),
         "ocsc_last_error": (ctypes.c_char_p, [vp]),
         "ocsc_state_bytes": (i32, [vp, i32, ctypes.POINTER(i64)]),
         "ocsc_get_state": (i32, [vp, i32, vp]),
@@ -213,6 +217,21 @@ def ocsc_diagnostics(ctx, K):
     _check(ctx, load().ocsc_diagnostics(ctx, out))
     v = list(out)
     return {"primal_residual": v[0], "dict_norm": v[1], "V_norms": v[2:2 + K], "D_norms": v[2 + K:2 + 2 * K]}
+
+
+def ocsc_graph_create(ctx, x, B, codes_out=None):
+    """Returns an opaque graph handle (c_void_p) for two captured steps."""
+    h = ctypes.c_void_p()
+    _check(ctx, load().ocsc_graph_create(ctx, _ptr(x), int(B), _ptr(codes_out), ctypes.byref(h)))
+    return h
+
+
+def ocsc_graph_launch(ctx, h) -> None:
+    _check(ctx, load().ocsc_graph_launch(h))
+
+
+def ocsc_graph_destroy(h) -> None:
+    _check(None, load().ocsc_graph_destroy(h))
 
 
 def ocsc_sync(ctx) -> None:
