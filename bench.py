@@ -190,6 +190,36 @@ def coding_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
             "note": "equal shares of the four grids; FP32; K=100, 11x11 filters, J_z=10"}
 
 
+def graph_run(wl, xs, steps: int, warmup: int = 4) -> dict:
+    """The same B=1 step replayed from HIP graphs (two steps per graph, one
+    graph per pair of resident images), on a context with its own stream."""
+    import torch
+    import synth
+    from paper_1706_06972_amd import ocsc as L
+    n_img = xs.shape[0] // 2 * 2
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        g = L.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
+                   iters_dict=wl.iters_dict, max_batch=1, precision="f32")
+    g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
+    codes = torch.empty((2, 1, wl.K, wl.pad_h, wl.pad_w), dtype=torch.float32, device=xs.device)
+    graphs = [L.ocsc_graph_create(g.ctx, xs[i:i + 2].contiguous(), 1, codes) for i in range(0, n_img, 2)]
+    for i in range(warmup):
+        L.ocsc_graph_launch(g.ctx, graphs[i % len(graphs)])
+    st.synchronize()
+    launches = max(1, steps // 2)
+    t0 = time.perf_counter()
+    for i in range(launches):
+        L.ocsc_graph_launch(g.ctx, graphs[i % len(graphs)])
+    st.synchronize()
+    dt = time.perf_counter() - t0
+    for h in graphs:
+        L.ocsc_graph_destroy(h)
+    g.close()
+    return {"value": 2 * launches / dt, "unit": "images/s", "ms_per_step": 1000.0 * dt / (2 * launches),
+            "steps": 2 * launches, "form": "the B=1 step above, replayed from HIP graphs"}
+
+
 def served_run(dev, K: int = 100) -> dict:
     """Serving form (continuous batching, resident dictionary updated every
     256 requests, FP32): Poisson arrivals on a mix of 64/128/256/512 grids
@@ -353,6 +383,7 @@ def main():
     }
     del g
     torch.cuda.synchronize()
+    out["graph"] = graph_run(wl, xs, args.steps)
     out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
     out["precision"] = batched_run(wl, args.batch, xs, dev, cholesky=True) if args.batch > 1 else None
     out["coding"] = coding_run(dev) if args.coding else None
