@@ -110,6 +110,7 @@ def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2, cholesky:
     g = L.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
                iters_dict=wl.iters_dict, max_batch=B, precision="f32", cholesky=cholesky, device=dev)
     g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
+    shape, _ = g.autotune(B)
 
     def step():
         L.ocsc_code_update(g.ctx, pool, B, None)
@@ -134,7 +135,7 @@ def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2, cholesky:
     del g
     torch.cuda.synchronize()
     return {"batch": B, "value": B * steps / dt, "unit": "images/s", "ms_per_step": 1000.0 * dt / steps,
-            "steps": steps, "warmup": warmup,
+            "steps": steps, "warmup": warmup, "launch_shape": shape,
             "form": ("precision form: BF16 matrix-core history + FP64 Cholesky inverse, FP32 code"
                      if cholesky else "minibatch Sherman-Morrison, FP32"),
             "kernel_ms_per_step": kern}
@@ -169,28 +170,40 @@ def coding_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
         g = L.OCSC(K, 11, 11, n, n, 1.0, 1.0, iters_code=iters, max_batch=B, precision="f32", device=dev)
         g.set_dictionary(D0)
         codes = torch.empty((B, K, n, n), dtype=torch.float32, device=dev)
-        L.ocsc_code_update(g.ctx, xs, B, codes)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
+
+        def timed():
             L.ocsc_code_update(g.ctx, xs, B, codes)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                L.ocsc_code_update(g.ctx, xs, B, codes)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+
+        default = g.tuning
+        shape, _ = g.autotune(B)   # before any code update: the workspace holds no pending codes
+        g.set_tuning(**default)
+        dt0 = timed()
+        g.set_tuning(**shape)
+        dt = timed()
+        g.close()
         del g, codes
         torch.cuda.synchronize()
         rate = B / dt
         nb = code_bytes_per_image(K, n, iters, 4)
         out[str(n)] = {"batch": B, "images_per_s": rate, "ms_per_launch": 1000.0 * dt,
-                       "bytes_per_image": nb, "achieved_GBs": nb * rate / 1e9}
+                       "bytes_per_image": nb, "achieved_GBs": nb * rate / 1e9, "tuned_shape": shape,
+                       "default_shape": default, "default_images_per_s": B / dt0}
         inv_sum += 1.0 / rate
         bytes_sum += nb
     mix = len(CODING_GRIDS) / inv_sum
     return {"grids": out, "mix_images_per_s": mix,
             "mix_achieved_GBs": bytes_sum / len(CODING_GRIDS) * mix / 1e9,
-            "note": "equal shares of the four grids; FP32; K=100, 11x11 filters, J_z=10"}
+            "note": "equal shares of the four grids; FP32; K=100, 11x11 filters, J_z=10; launch shapes "
+                    "picked by ocsc_autotune per grid"}
 
 
-def graph_run(wl, xs, steps: int, warmup: int = 4) -> dict:
+def graph_run(wl, xs, steps: int, warmup: int = 4, shape=None) -> dict:
     """The same B=1 step replayed from HIP graphs (two steps per graph, one
     graph per pair of resident images), on a context with its own stream."""
     import torch
@@ -202,6 +215,8 @@ def graph_run(wl, xs, steps: int, warmup: int = 4) -> dict:
         g = L.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
                    iters_dict=wl.iters_dict, max_batch=1, precision="f32")
     g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
+    if shape:
+        g.set_tuning(**shape)
     codes = torch.empty((2, 1, wl.K, wl.pad_h, wl.pad_w), dtype=torch.float32, device=xs.device)
     graphs = [L.ocsc_graph_create(g.ctx, xs[i:i + 2].contiguous(), 1, codes) for i in range(0, n_img, 2)]
     for i in range(warmup):
@@ -323,6 +338,8 @@ def main():
     g = L.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
                iters_dict=wl.iters_dict, max_batch=1, precision="f32", device=dev)
     g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
+    # launch shapes of the code update for single samples (bitwise the same results for every shape)
+    tuned, _ = g.autotune(1)
 
     def step(i):
         x = xs[i % n_img:i % n_img + 1]
@@ -380,10 +397,11 @@ def main():
                      "traffic": traffic, "bytes_per_launch": per_launch,
                      "avg_launch_us": dstep_avg_us},
         "kernels": kern,
+        "launch_shape": tuned,
     }
     del g
     torch.cuda.synchronize()
-    out["graph"] = graph_run(wl, xs, args.steps)
+    out["graph"] = graph_run(wl, xs, args.steps, shape=tuned)
     out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
     out["precision"] = batched_run(wl, args.batch, xs, dev, cholesky=True) if args.batch > 1 else None
     out["coding"] = coding_run(dev) if args.coding else None

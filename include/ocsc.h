@@ -252,6 +252,43 @@ int ocsc_graph_launch(ocsc_graph* graph);
 /* Waits for the context stream, then frees the graph.  NULL is accepted. */
 int ocsc_graph_destroy(ocsc_graph* graph);
 
+/* ---------------------------------------------------------------------------
+ * Launch shapes of the code update (the per-sample ADMM of eq. fcsc_code:
+ * Z-step and plane kernel, 2 launches per code iteration) and their
+ * autotuner.  Every valid shape computes the same values bit for bit (the
+ * per-element arithmetic and the order of every sum are fixed); only the
+ * speed differs, so a tuned context reproduces an untuned one exactly.
+ *   plane_threads: threads per workgroup of the plane kernel, one plane per
+ *                  workgroup: 256, 512 or 1024, at most pad_h * pad_w / 4.
+ *                  Grids with a side above 128 use fixed two-pass kernels
+ *                  and accept only 256.
+ *   zstep_freqs:   frequencies per Z-step workgroup, 16, 32 or 64
+ *                  (16 * zstep_freqs threads).
+ *   zstep_samples: samples per Z-step workgroup, 1, 2 or 4 (the dictionary
+ *                  spectrum is read once for them).
+ * Defaults: plane_threads 1024 for 128 x 128 grids, else 256; 16; 1.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t plane_threads;
+  int32_t zstep_freqs;
+  int32_t zstep_samples;
+  int32_t reserved; /* 0 */
+} ocsc_tuning;
+
+int ocsc_get_tuning(const ocsc_ctx* ctx, ocsc_tuning* out);
+/* OCSC_E_INVALID_ARG for a shape outside the lists above (the context keeps
+ * its shape). */
+int ocsc_set_tuning(ocsc_ctx* ctx, const ocsc_tuning* tuning);
+/* Time every valid shape of both kernels on the context's own code
+ * workspace for batches of B samples (1 <= B <= max_batch) and keep the
+ * fastest of each.  The workspace contents are overwritten, so the call
+ * needs no pending codes (OCSC_E_STATE); a deferred history fold is applied
+ * first.  The learner state (dictionary, history, t) is not changed.  Writes
+ * the chosen shape to out and the summed time of one Z-step and one plane
+ * launch with it to best_ms (both nullable).  Waits for completion; not
+ * allowed during stream capture. */
+int ocsc_autotune(ocsc_ctx* ctx, int B, ocsc_tuning* out, double* best_ms);
+
 /* Text of the last failure on this context (or of the last failed ocsc_init
  * when ctx is NULL).  Valid until the next call on the same context. */
 const char* ocsc_last_error(const ocsc_ctx* ctx);

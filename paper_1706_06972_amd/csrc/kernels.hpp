@@ -207,59 +207,66 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
 // frequency p with a = Dh[:, p], s = S[:, p]:
 //   z = s + conj(a) * gam_p * (x_p - a^T s),   gam_p = 1 / (rho + ||a||^2),
 // which is the Sherman-Morrison solution of (conj(a) a^T + rho I) z =
-// conj(a) x_p + rho s.  A workgroup of 256 threads serves 16 frequencies of
-// one sample: thread (kq, f) holds filters k = kq, kq + 16, ... (at most KPT)
-// of frequency f in registers, so each filter row is read as one 128-byte
-// (FP32) or 256-byte (FP64) segment.  first: s = 0.
+// conj(a) x_p + rho s.  A workgroup of 16 * ZF threads serves ZF frequencies
+// of SB consecutive samples: thread (kq, f) holds filters k = kq, kq + 16, ...
+// (at most KPT) of frequency f in registers, so a wave reads 64 / ZF filter
+// rows per load, each as one run of ZF complex values; the filter values are
+// read once for the SB samples.  The sums over filters are taken in the same
+// order for every ZF and SB (per thread over j, then over the 16 threads of a
+// frequency in kq order), so every launch shape gives the same bits.
+// first: s = 0.
 // ---------------------------------------------------------------------------
-constexpr int ZF = 16;
-
-template <typename T, int KPT>
-__global__ __launch_bounds__(256) void k_code_zstep(const cx<T>* __restrict__ Dh,
-                                                   const T* __restrict__ gam,
-                                                   const cx<T>* __restrict__ xh,
-                                                   const cx<T>* __restrict__ S,
-                                                   cx<T>* __restrict__ Zh, int K, int Pf,
-                                                   int first, cx<T>* __restrict__ Zt, int ldt, int bt0) {
+template <typename T, int KPT, int ZF, int SB>
+__global__ __launch_bounds__(16 * ZF) void k_code_zstep(const cx<T>* __restrict__ Dh,
+                                                        const T* __restrict__ gam,
+                                                        const cx<T>* __restrict__ xh,
+                                                        const cx<T>* __restrict__ S,
+                                                        cx<T>* __restrict__ Zh, int K, int Pf, int B,
+                                                        int first, cx<T>* __restrict__ Zt, int ldt, int bt0) {
   // Zt (optional): the same values frequency-major, Zt[(p * ldt + bt0 + b) * K + k]
   __shared__ cx<T> red[16][ZF + 1];
   const int f = threadIdx.x % ZF, kq = threadIdx.x / ZF;
-  const int b = blockIdx.y;
   const int p = blockIdx.x * ZF + f;
   const bool ok = p < Pf;
-  cx<T> a[KPT], s[KPT];
-  cx<T> acc = mk<T>(0, 0);
+  cx<T> a[KPT];
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
     const int k = kq + j * 16;
-    a[j] = mk<T>(0, 0);
-    s[j] = mk<T>(0, 0);
-    if (ok && k < K) {
-      a[j] = Dh[(size_t)k * Pf + p];
-      if (!first) s[j] = S[((size_t)b * K + k) * Pf + p];
-    }
-    acc = cadd<T>(acc, cmul<T>(a[j], s[j]));
+    a[j] = (ok && k < K) ? Dh[(size_t)k * Pf + p] : mk<T>(0, 0);
   }
-  red[kq][f] = acc;
-  __syncthreads();
-  if (kq == 0) {
-    cx<T> tot = red[0][f];
+  for (int sb = 0; sb < SB; ++sb) {
+    const int b = blockIdx.y * SB + sb;
+    if (b >= B) break;   // the same for the whole workgroup
+    cx<T> s[KPT];
+    cx<T> acc = mk<T>(0, 0);
 #pragma unroll
-    for (int i = 1; i < 16; ++i) tot = cadd<T>(tot, red[i][f]);
-    cx<T> qv = mk<T>(0, 0);
-    if (ok) qv = cscale<T>(csub<T>(xh[(size_t)b * Pf + p], tot), gam[p]);
-    red[0][f] = qv;
-  }
-  __syncthreads();
-  const cx<T> qv = red[0][f];
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const int k = kq + j * 16;
-    if (ok && k < K) {
-      const cx<T> z = cadd<T>(s[j], cmulc<T>(qv, a[j]));
-      Zh[((size_t)b * K + k) * Pf + p] = z;
-      if (Zt) Zt[((size_t)p * ldt + bt0 + b) * K + k] = z;
+    for (int j = 0; j < KPT; ++j) {
+      const int k = kq + j * 16;
+      s[j] = (ok && k < K && !first) ? S[((size_t)b * K + k) * Pf + p] : mk<T>(0, 0);
+      acc = cadd<T>(acc, cmul<T>(a[j], s[j]));
     }
+    red[kq][f] = acc;
+    __syncthreads();
+    if (kq == 0) {
+      cx<T> tot = red[0][f];
+#pragma unroll
+      for (int i = 1; i < 16; ++i) tot = cadd<T>(tot, red[i][f]);
+      cx<T> qv = mk<T>(0, 0);
+      if (ok) qv = cscale<T>(csub<T>(xh[(size_t)b * Pf + p], tot), gam[p]);
+      red[0][f] = qv;
+    }
+    __syncthreads();
+    const cx<T> qv = red[0][f];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const int k = kq + j * 16;
+      if (ok && k < K) {
+        const cx<T> z = cadd<T>(s[j], cmulc<T>(qv, a[j]));
+        Zh[((size_t)b * K + k) * Pf + p] = z;
+        if (Zt) Zt[((size_t)p * ldt + bt0 + b) * K + k] = z;
+      }
+    }
+    if (SB > 1) __syncthreads();   // red is reused by the next sample
   }
 }
 

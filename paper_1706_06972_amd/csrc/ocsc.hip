@@ -51,6 +51,7 @@ struct ocsc_ctx {
   bool keep_hist = false;     // OCSC_FLAG_KEEP_HISTORY (implied by OCSC_FLAG_CHOLESKY)
   bool chol = false;          // OCSC_FLAG_CHOLESKY: matrix-core history, C from an FP64 Cholesky
   bool warm = false;          // OCSC_FLAG_WARM_START
+  ocsc_tuning tune{};         // launch shapes of the code update (ocsc_set_tuning / ocsc_autotune)
   // runtime
   int device = 0;
   hipStream_t stream = nullptr;
@@ -156,6 +157,10 @@ struct ProfScope {
 // 128 x 128 planes: 16 waves per workgroup, so that one CU has enough waves
 // to overlap the LDS and global latencies of the transform passes.
 constexpr int plane_threads(int ph, int pw) { return ph * pw >= 128 * 128 ? 1024 : 256; }
+// plane-kernel workgroup sizes offered to the tuner: at least four reals per thread
+constexpr bool plane_nt_ok(int ph, int pw, int nt) {
+  return (nt == 256 || nt == 512 || nt == 1024) && nt * 4 <= ph * pw;
+}
 
 #define OCSC_SIZE_CASES(X) \
   X(32, 32) X(32, 64) X(32, 128) X(64, 32) X(64, 64) X(64, 128) X(128, 32) X(128, 64) X(128, 128)
@@ -287,46 +292,67 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
     LAUNCHED(c);
     return OCSC_OK;
   }
+  const int nt = c->tune.plane_threads;
+  bool done = false;
   switch (c->Ph * 1000 + c->Pw) {
-#define X(A, B)                                                                                        \
-  case A * 1000 + B:                                                                                   \
-    hipLaunchKernelGGL((k_code_plane<T, A, B, plane_threads(A, B)>), dim3(nplanes), dim3(plane_threads(A, B)), 0, \
-                       c->stream, (const cx<T>*)Zh, W, S, Uout, tH, tW, kappa,                       \
-                       first, last);                                                                   \
+#define OCSC_PLANE_NT(A, B, NT)                                                                          \
+  if constexpr (plane_nt_ok(A, B, NT)) {                                                                 \
+    if (nt == NT) {                                                                                      \
+      hipLaunchKernelGGL((k_code_plane<T, A, B, NT>), dim3(nplanes), dim3(NT), 0, c->stream,             \
+                         (const cx<T>*)Zh, W, S, Uout, tH, tW, kappa, first, last);                      \
+      done = true;                                                                                       \
+    }                                                                                                    \
+  }
+#define X(A, B)              \
+  case A * 1000 + B:         \
+    OCSC_PLANE_NT(A, B, 256)  \
+    OCSC_PLANE_NT(A, B, 512)  \
+    OCSC_PLANE_NT(A, B, 1024) \
     break;
     OCSC_SIZE_CASES(X)
 #undef X
+#undef OCSC_PLANE_NT
     default:
-      return fail(c, OCSC_E_UNSUPPORTED, "no code-plane kernel for this grid");
+      break;
   }
+  if (!done) return fail(c, OCSC_E_UNSUPPORTED, "no code-plane kernel for this grid and workgroup size");
   LAUNCHED(c);
   return OCSC_OK;
+}
+
+template <typename T, int KPT, int ZF, int SB>
+void zstep_kernel(ocsc_ctx* c, int off, int B, int first, cx<T>* Zt) {
+  const dim3 grid((c->Pf + ZF - 1) / ZF, (B + SB - 1) / SB);
+  hipLaunchKernelGGL((k_code_zstep<T, KPT, ZF, SB>), grid, dim3(16 * ZF), 0, c->stream, (const cx<T>*)c->Dh,
+                     (const T*)c->gam, (const cx<T>*)c->xh + (size_t)off * c->Pf,
+                     (const cx<T>*)c->S + (size_t)off * c->K * c->Pf, (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf,
+                     c->K, c->Pf, B, first, Zt, c->maxB, off);
+}
+
+template <typename T, int KPT>
+bool zstep_shape(ocsc_ctx* c, int off, int B, int first, cx<T>* Zt) {
+  const int zf = c->tune.zstep_freqs, sb = c->tune.zstep_samples;
+#define X(ZF, SB) \
+  if (zf == ZF && sb == SB) { zstep_kernel<T, KPT, ZF, SB>(c, off, B, first, Zt); return true; }
+  X(16, 1) X(16, 2) X(16, 4) X(32, 1) X(32, 2) X(32, 4) X(64, 1) X(64, 2) X(64, 4)
+#undef X
+  return false;
 }
 
 template <typename T>
 int launch_zstep(ocsc_ctx* c, int off, int B, int first, bool last) {
   ProfScope ps(c, OCSC_KC_ZSTEP);
-  dim3 grid((c->Pf + ZF - 1) / ZF, B);
-  const cx<T>* Dh = (const cx<T>*)c->Dh;
-  const T* gam = (const T*)c->gam;
-  const cx<T>* xh = (const cx<T>*)c->xh + (size_t)off * c->Pf;
-  const cx<T>* S = (const cx<T>*)c->S + (size_t)off * c->K * c->Pf;
-  cx<T>* Zh = (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf;
-  const int K = c->K, Pf = c->Pf;
   // the last iterate also goes frequency-major to the matrix-core history update
   cx<T>* Zt = (last && c->chol) ? (cx<T>*)c->Zt : nullptr;
-  if (K <= 16)
-    hipLaunchKernelGGL((k_code_zstep<T, 1>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
-  else if (K <= 32)
-    hipLaunchKernelGGL((k_code_zstep<T, 2>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
-  else if (K <= 64)
-    hipLaunchKernelGGL((k_code_zstep<T, 4>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
-  else if (K <= 128)
-    hipLaunchKernelGGL((k_code_zstep<T, 8>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
-  else if (K <= 256)
-    hipLaunchKernelGGL((k_code_zstep<T, 16>), grid, dim3(256), 0, c->stream, Dh, gam, xh, S, Zh, K, Pf, first, Zt, c->maxB, off);
-  else
-    return fail(c, OCSC_E_UNSUPPORTED, "code Z-step supports K <= 256");
+  const int K = c->K;
+  bool ok;
+  if (K <= 16) ok = zstep_shape<T, 1>(c, off, B, first, Zt);
+  else if (K <= 32) ok = zstep_shape<T, 2>(c, off, B, first, Zt);
+  else if (K <= 64) ok = zstep_shape<T, 4>(c, off, B, first, Zt);
+  else if (K <= 128) ok = zstep_shape<T, 8>(c, off, B, first, Zt);
+  else if (K <= 256) ok = zstep_shape<T, 16>(c, off, B, first, Zt);
+  else return fail(c, OCSC_E_UNSUPPORTED, "code Z-step supports K <= 256");
+  if (!ok) return fail(c, OCSC_E_INVALID_ARG, "internal: Z-step shape");
   LAUNCHED(c);
   return OCSC_OK;
 }
@@ -910,6 +936,10 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   }
   c->vapply_smem = (((size_t)filt_h * filt_w * sr + 15) & ~(size_t)15) + (size_t)filt_h * vb * 2 * sr;
   c->big = big_grid(pad_h, pad_w);
+  c->tune.plane_threads = c->big ? 256 : plane_threads(pad_h, pad_w);
+  c->tune.zstep_freqs = 16;
+  c->tune.zstep_samples = 1;
+  c->tune.reserved = 0;
   c->chol = (o.flags & OCSC_FLAG_CHOLESKY) != 0;
   c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0 || c->chol;
   c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
@@ -1172,6 +1202,97 @@ int ocsc_diagnostics(ocsc_ctx* c, double* out) {
 // ---------------------------------------------------------------- graphs
 }  // extern "C"
 
+namespace {
+
+bool tuning_valid(const ocsc_ctx* c, const ocsc_tuning& t) {
+  if (t.reserved != 0) return false;
+  const bool pt = c->big ? t.plane_threads == 256 : plane_nt_ok(c->Ph, c->Pw, t.plane_threads);
+  const bool zf = t.zstep_freqs == 16 || t.zstep_freqs == 32 || t.zstep_freqs == 64;
+  const bool sb = t.zstep_samples == 1 || t.zstep_samples == 2 || t.zstep_samples == 4;
+  return pt && zf && sb;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// Mean duration of `reps` launches after one untimed launch.
+template <typename F>
+int time_launches(ocsc_ctx* c, EventPair& ev, F&& launch, int reps, double* ms_out) {
+  int rc = launch();
+  if (rc) return rc;
+  HIPX(c, hipEventRecord(ev.a, c->stream));
+  for (int r = 0; r < reps; ++r) {
+    rc = launch();
+    if (rc) return rc;
+  }
+  HIPX(c, hipEventRecord(ev.b, c->stream));
+  HIPX(c, hipEventSynchronize(ev.b));
+  float ms = 0;
+  HIPX(c, hipEventElapsedTime(&ms, ev.a, ev.b));
+  *ms_out = ms / reps;
+  return OCSC_OK;
+}
+
+// Try every launch shape of the Z-step and of the plane kernel on the code
+// workspace (samples [0, B)) and keep the fastest of each.  The Z-step runs
+// as a middle iteration (reads S) and the plane kernel as a middle iteration
+// (reads and writes W, writes S); the values in the workspace are irrelevant
+// to the timing.
+template <typename T>
+int autotune_t(ocsc_ctx* c, int B, double* best_ms) {
+  int rc = flush_fold<T>(c);
+  if (rc) return rc;
+  EventPair ev;
+  HIPX(c, hipEventCreate(&ev.a));
+  HIPX(c, hipEventCreate(&ev.b));
+  const unsigned mask = c->prof_mask;
+  c->prof_mask = 0;
+  const ocsc_tuning start = c->tune;
+  ocsc_tuning best = start;
+  double best_z = 1e30, best_p = 1e30;
+  constexpr int REPS = 3;
+  for (int zf : {16, 32, 64}) {
+    for (int sb : {1, 2, 4}) {
+      c->tune.zstep_freqs = zf;
+      c->tune.zstep_samples = sb;
+      double ms = 0;
+      rc = time_launches(c, ev, [&] { return launch_zstep<T>(c, 0, B, 0, false); }, REPS, &ms);
+      if (rc) break;
+      if (ms < best_z) {
+        best_z = ms;
+        best.zstep_freqs = zf;
+        best.zstep_samples = sb;
+      }
+    }
+    if (rc) break;
+  }
+  c->tune = start;
+  for (int nt : {256, 512, 1024}) {
+    if (rc) break;
+    c->tune.plane_threads = nt;
+    if (!tuning_valid(c, c->tune)) continue;
+    double ms = 0;
+    rc = time_launches(c, ev, [&] { return launch_code_plane<T>(c, 0, B * c->K, nullptr, 0, 0); }, REPS, &ms);
+    if (rc) break;
+    if (ms < best_p) {
+      best_p = ms;
+      best.plane_threads = nt;
+    }
+  }
+  c->prof_mask = mask;
+  c->tune = rc ? start : best;
+  if (rc) return rc;
+  *best_ms = best_z + best_p;
+  return OCSC_OK;
+}
+
+}  // namespace
+
 struct ocsc_graph {
   ocsc_ctx* c = nullptr;
   hipGraph_t graph = nullptr;
@@ -1246,6 +1367,38 @@ int ocsc_graph_destroy(ocsc_graph* gr) {
   if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
   if (gr->graph) (void)hipGraphDestroy(gr->graph);
   delete gr;
+  return OCSC_OK;
+}
+
+// ---------------------------------------------------------------- launch shapes
+int ocsc_get_tuning(const ocsc_ctx* c, ocsc_tuning* out) {
+  if (!c || !out) return OCSC_E_INVALID_ARG;
+  *out = c->tune;
+  return OCSC_OK;
+}
+
+int ocsc_set_tuning(ocsc_ctx* c, const ocsc_tuning* t) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!t) return fail(c, OCSC_E_INVALID_ARG, "tuning is NULL");
+  if (!tuning_valid(c, *t)) return fail(c, OCSC_E_INVALID_ARG, "unsupported launch shape");
+  c->tune = *t;
+  return OCSC_OK;
+}
+
+int ocsc_autotune(ocsc_ctx* c, int B, ocsc_tuning* out, double* best_ms) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
+  if (c->pending_B) return fail(c, OCSC_E_STATE, "pending codes occupy the code workspace");
+  if (c->stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    HIPX(c, hipStreamIsCapturing(c->stream, &st));
+    if (st != hipStreamCaptureStatusNone) return fail(c, OCSC_E_STATE, "the context stream is being captured");
+  }
+  double ms = 0;
+  const int rc = c->sr == 8 ? autotune_t<double>(c, B, &ms) : autotune_t<float>(c, B, &ms);
+  if (rc) return rc;
+  if (out) *out = c->tune;
+  if (best_ms) *best_ms = ms;
   return OCSC_OK;
 }
 

@@ -40,6 +40,7 @@ EXPORTS = [
     "ocsc_dict_update_group", "ocsc_objective",
     "ocsc_objective_terms", "ocsc_surrogate", "ocsc_diagnostics", "ocsc_sync",
     "ocsc_graph_create", "ocsc_graph_launch", "ocsc_graph_destroy",
+    "ocsc_get_tuning", "ocsc_set_tuning", "ocsc_autotune",
     "ocsc_last_error", "ocsc_state_bytes", "ocsc_get_state", "ocsc_set_state", "ocsc_get_count",
     "ocsc_set_count", "ocsc_profile_enable", "ocsc_profile_read",
 ]
@@ -55,6 +56,15 @@ class OcscOpts(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("rho_dict", ctypes.c_double),
         ("stream", ctypes.c_void_p),
+    ]
+
+
+class OcscTuning(ctypes.Structure):
+    _fields_ = [
+        ("plane_threads", ctypes.c_int32),
+        ("zstep_freqs", ctypes.c_int32),
+        ("zstep_samples", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -99,6 +109,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ocsc_graph_create": (i32, [vp, vp, i32, vp, ctypes.POINTER(vp)]),
         "ocsc_graph_launch": (i32, [vp]),
         "ocsc_graph_destroy": (i32, [vp]),
+        "ocsc_get_tuning": (i32, [vp, ctypes.POINTER(OcscTuning)]),
+        "ocsc_set_tuning": (i32, [vp, ctypes.POINTER(OcscTuning)]),
+        "ocsc_autotune": (i32, [vp, i32, ctypes.POINTER(OcscTuning), ctypes.POINTER(dbl)]),
         "ocsc_last_error": (ctypes.c_char_p, [vp]),
         "ocsc_state_bytes": (i32, [vp, i32, ctypes.POINTER(i64)]),
         "ocsc_get_state": (i32, [vp, i32, vp]),
@@ -232,6 +245,33 @@ def ocsc_graph_launch(ctx, h) -> None:
 
 def ocsc_graph_destroy(h) -> None:
     _check(None, load().ocsc_graph_destroy(h))
+
+
+TUNING_FIELDS = ("plane_threads", "zstep_freqs", "zstep_samples")
+
+
+def ocsc_get_tuning(ctx) -> dict:
+    t = OcscTuning()
+    _check(ctx, load().ocsc_get_tuning(ctx, ctypes.byref(t)))
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
+def ocsc_set_tuning(ctx, **shape) -> None:
+    """Change some fields of the launch shape (the others stay)."""
+    cur = ocsc_get_tuning(ctx)
+    unknown = set(shape) - set(TUNING_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    cur.update(shape)
+    t = OcscTuning(**cur)
+    _check(ctx, load().ocsc_set_tuning(ctx, ctypes.byref(t)))
+
+
+def ocsc_autotune(ctx, B):
+    """Returns (chosen shape as a dict, ms of one Z-step + one plane launch)."""
+    t, ms = OcscTuning(), ctypes.c_double()
+    _check(ctx, load().ocsc_autotune(ctx, int(B), ctypes.byref(t), ctypes.byref(ms)))
+    return {f: getattr(t, f) for f in TUNING_FIELDS}, ms.value
 
 
 def ocsc_sync(ctx) -> None:
@@ -405,6 +445,18 @@ class OCSC:
 
     def sync(self):
         ocsc_sync(self.ctx)
+
+    @property
+    def tuning(self) -> dict:
+        return ocsc_get_tuning(self.ctx)
+
+    def set_tuning(self, **shape):
+        ocsc_set_tuning(self.ctx, **shape)
+
+    def autotune(self, B=None):
+        """Pick the fastest code-update launch shapes for batches of B samples
+        (default max_batch); returns (shape, ms per code iteration)."""
+        return ocsc_autotune(self.ctx, self.max_batch if B is None else B)
 
     def state(self, which):
         n = ocsc_state_bytes(self.ctx, which)

@@ -16,6 +16,8 @@ Design (host loop over the C calls; every arithmetic step runs in the library):
   recorded after its batch has completed; latency = completion - arrival.
 * The pending slots per grid (the device state a request occupies until its
   history is folded) are sized so that all contexts fit the HBM budget.
+* Each grid's code-update launch shapes are autotuned at start-up for a full
+  launch (``ocsc_autotune``); every shape gives the same bits.
 * Every ``update_every`` completed requests the pending samples of every grid
   are accumulated and one shared dictionary update is enqueued; requests
   coded afterwards carry the next dictionary version.  A grid whose slots are
@@ -95,7 +97,7 @@ class Server:
                  shares: Sequence[float] = (8, 4, 2, 1), lam: float = 1.0, rho: float = 1.0,
                  update_every: int = 256, budget: float = 64e9, max_launch: Optional[Dict[int, int]] = None,
                  iters_code: int = 10, iters_dict: int = 10, keep_codes: bool = False, device: str = "cuda:0",
-                 slots: Optional[Dict[int, int]] = None):
+                 slots: Optional[Dict[int, int]] = None, autotune: bool = True):
         import torch
         from paper_1706_06972_amd.ocsc import OCSC
         self.torch = torch
@@ -110,6 +112,8 @@ class Server:
                 m = OCSC(K, filt, filt, n, n, lam, rho, iters_code=iters_code, iters_dict=iters_dict,
                          max_batch=self.slots[n], precision="f32", device=self.device)
                 m.set_dictionary(D0)
+                if autotune:   # launch shapes for full launches of this grid (same bits for every shape)
+                    m.autotune(min(max_launch[n], self.slots[n]))
             g = _Grid(n, m, st, self.slots[n], max_launch[n])
             g.xbuf = torch.empty((g.max_launch, n, n), dtype=torch.float32, pin_memory=True)
             g.xdev = torch.empty((g.max_launch, n, n), dtype=torch.float32, device=self.device)

@@ -92,6 +92,10 @@ def test_null_context_calls():
     assert L.ocsc_surrogate(None, None, out) == B.OCSC_E_INVALID_ARG
     assert L.ocsc_diagnostics(None, out) == B.OCSC_E_INVALID_ARG
     assert L.ocsc_objective_terms(None, None, None, 1, out) == B.OCSC_E_INVALID_ARG
+    t = B.OcscTuning()
+    assert L.ocsc_get_tuning(None, ctypes.byref(t)) == B.OCSC_E_INVALID_ARG
+    assert L.ocsc_set_tuning(None, ctypes.byref(t)) == B.OCSC_E_INVALID_ARG
+    assert L.ocsc_autotune(None, 1, None, None) == B.OCSC_E_INVALID_ARG
 
 
 def test_no_device_is_a_hip_error_not_a_crash():

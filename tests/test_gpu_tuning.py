@@ -1,0 +1,118 @@
+"""Launch shapes of the code update and their autotuner, through the C ABI.
+
+Every shape must give the codes and code spectra of the default shape bit for
+bit (same arithmetic, same order of every sum), on grids with one-pass and
+two-pass transforms and on batches that do not fill the last Z-step
+workgroup.  The autotuner must pick a valid shape, keep the learner state and
+refuse to run over pending codes.  The default shape itself is checked against
+the FP64 oracle by the parity tests.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle.ocsc_oracle as O
+import synth
+from tests.gpu_util import rel, say, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def images(n, ph, pw, seed):
+    wl = synth.Workload(name="t", pad_h=ph, pad_w=pw, content_h=ph // 2, content_w=pw // 2, k_true=4,
+                        density=0.02, sigma_z=10.0, noise=0.01, K=4, filt_h=5, filt_w=5, lam=1.0, rho=1.0,
+                        iters_code=10, iters_dict=10, batch=1, n_images=n, passes=1, precision="f64", seed=seed)
+    return synth.images(wl, range(n))
+
+
+def shapes(ph, pw):
+    nts = [nt for nt in (256, 512, 1024) if nt * 4 <= ph * pw] if max(ph, pw) <= 128 else [256]
+    return [dict(plane_threads=nt, zstep_freqs=zf, zstep_samples=sb)
+            for nt, zf, sb in itertools.product(nts, (16, 32, 64), (1, 2, 4))]
+
+
+@pytest.mark.parametrize("prec,ph,pw,K", [("f32", 128, 128, 20), ("f64", 64, 64, 16), ("f32", 32, 64, 40),
+                                          ("f32", 256, 256, 6), ("f64", 128, 128, 3)])
+def test_every_shape_gives_the_same_bits(prec, ph, pw, K):
+    say(f"case shapes {prec} {ph}x{pw} K={K}")
+    from paper_1706_06972_amd.ocsc import OCSC
+    B = 3
+    xs = images(B, ph, pw, 7)
+    g = OCSC(K, 5, 5, ph, pw, 0.5, 1.0, precision=prec, max_batch=B)
+    g.set_dictionary(synth.initial_dictionary(K, 5, 5, 1))
+    default = g.tuning
+    U0 = to_np(g.code_update(xs))
+    Z0 = to_np(g.state("zhat"))
+    assert np.count_nonzero(U0) > 0
+    for sh in shapes(ph, pw):
+        g.set_tuning(**sh)
+        assert g.tuning == sh
+        U = to_np(g.code_update(xs))
+        assert np.array_equal(U, U0), sh
+        assert np.array_equal(to_np(g.state("zhat")), Z0), sh
+    g.set_tuning(**default)
+    g.close()
+
+
+def test_invalid_shapes_are_refused():
+    say("case invalid shapes")
+    from paper_1706_06972_amd import ocsc as L
+    from paper_1706_06972_amd.ocsc import OCSC
+    small = OCSC(4, 5, 5, 32, 32, 0.5, 1.0, precision="f32")
+    big = OCSC(4, 5, 5, 256, 256, 0.5, 1.0, precision="f32")
+    for g, bad in ((small, dict(plane_threads=512)), (small, dict(plane_threads=128)), (small, dict(zstep_freqs=8)),
+                   (small, dict(zstep_samples=3)), (big, dict(plane_threads=1024))):
+        before = g.tuning
+        with pytest.raises(L.OcscError) as e:
+            g.set_tuning(**bad)
+        assert e.value.status == L.OCSC_E_INVALID_ARG
+        assert g.tuning == before
+    assert small.tuning == dict(plane_threads=256, zstep_freqs=16, zstep_samples=1)
+    small.close()
+    big.close()
+
+
+@pytest.mark.parametrize("prec,n,K", [("f64", 64, 8), ("f32", 128, 12)])
+def test_autotune_keeps_the_learner(prec, n, K):
+    """Two learners fed the same samples, one autotuned between its history
+    accumulation (deferred fold) and its dictionary update: every result is
+    bitwise the same, and both match the oracle."""
+    say(f"case autotune {prec} {n}")
+    from paper_1706_06972_amd import ocsc as L
+    from paper_1706_06972_amd.ocsc import OCSC
+    B = 2
+    xs = images(2 * B, n, n, 3)
+    D0 = synth.initial_dictionary(K, 5, 5, 2)
+    a = OCSC(K, 5, 5, n, n, 0.5, 1.0, precision=prec, max_batch=B)
+    b = OCSC(K, 5, 5, n, n, 0.5, 1.0, precision=prec, max_batch=B)
+    o = O.OCSC(K, 5, 5, n, n, 0.5, 1.0)
+    for m in (a, b, o):
+        m.set_dictionary(D0)
+    for step in range(2):
+        x = xs[step * B:(step + 1) * B]
+        Ua = to_np(a.code_update(x))
+        Ub = to_np(b.code_update(x))
+        Uo = o.code_update(x)
+        assert np.array_equal(Ua, Ub)
+        assert rel(Ua, Uo) < (1e-10 if prec == "f64" else 1e-3)
+        if step == 0:
+            with pytest.raises(L.OcscError) as e:
+                b.autotune(B)
+            assert e.value.status == L.OCSC_E_STATE
+        for m in (a, b, o):
+            m.history_accumulate()
+        shape, ms = b.autotune(B)
+        assert ms > 0 and b.tuning == shape
+        b.set_tuning(**shape)
+        for m in (a, b, o):
+            m.dict_update()
+        for item in ("dict_hat", "G", "cinv", "V", "theta"):
+            assert np.array_equal(to_np(a.state(item)), to_np(b.state(item))), item
+        assert a.count == b.count == (step + 1) * B
+    with pytest.raises(L.OcscError) as e:
+        b.autotune(B + 1)
+    assert e.value.status == L.OCSC_E_INVALID_ARG
+    a.close()
+    b.close()
