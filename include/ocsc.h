@@ -266,13 +266,26 @@ int ocsc_graph_destroy(ocsc_graph* graph);
  *                  (16 * zstep_freqs threads).
  *   zstep_samples: samples per Z-step workgroup, 1, 2 or 4 (the dictionary
  *                  spectrum is read once for them).
- * Defaults: plane_threads 1024 for 128 x 128 grids, else 256; 16; 1.
+ *   col_bytes:     two-pass grids: bytes of each spectrum row that one
+ *                  column-pass workgroup transforms (its block of columns):
+ *                  128, 256 or 512, with pad_h * col_bytes <= 131072.
+ *   row_block:     two-pass grids: rows per row-pass workgroup, 4, 8 or 16.
+ *                  (col_bytes and row_block are checked but unused on
+ *                  one-pass grids.)
+ *   chunk_samples: 0, or 1, 2, 4, 8 or 16: a batch is coded in groups of
+ *                  this many samples, each group running all its iterations
+ *                  before the next starts (its workspace can then stay in
+ *                  the Infinity Cache); 0 runs the whole batch together.
+ * Defaults: plane_threads 1024 for 128 x 128 grids, else 256; 16; 1; 128; 8; 0.
+ * ocsc_autotune times whole code updates for the group size.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t plane_threads;
   int32_t zstep_freqs;
   int32_t zstep_samples;
-  int32_t reserved; /* 0 */
+  int32_t col_bytes;
+  int32_t row_block;
+  int32_t chunk_samples;
 } ocsc_tuning;
 
 int ocsc_get_tuning(const ocsc_ctx* ctx, ocsc_tuning* out);
@@ -285,7 +298,7 @@ int ocsc_set_tuning(ocsc_ctx* ctx, const ocsc_tuning* tuning);
  * needs no pending codes (OCSC_E_STATE); a deferred history fold is applied
  * first.  The learner state (dictionary, history, t) is not changed.  Writes
  * the chosen shape to out and the summed time of one Z-step and one plane
- * launch with it to best_ms (both nullable).  Waits for completion; not
+ * launch of the whole batch with it to best_ms (both nullable).  Waits for completion; not
  * allowed during stream capture. */
 int ocsc_autotune(ocsc_ctx* ctx, int B, ocsc_tuning* out, double* best_ms);
 

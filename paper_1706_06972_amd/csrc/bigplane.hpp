@@ -5,25 +5,30 @@
 // over (block, plane) workgroups that stage their block in LDS:
 //   row pass:    RB consecutive rows of one plane (real <-> half spectrum)
 //   column pass: a block of CB spectrum columns of one plane, all PH rows
-//                (CB complex = 128 bytes per row segment)
+//                (CB complex = 128, 256 or 512 bytes per row segment)
+// The code-plane step takes CB and RB from the context's launch shape; the
+// per-column and per-row arithmetic does not depend on them.
 // Spectra keep the layout of the small-grid path: cx[plane][PH][PW/2 + 1].
 #pragma once
 #include "common.hpp"
 
 namespace ocsc {
 
-constexpr int BIG_RB = 8;   // rows per row-pass workgroup
+constexpr int BIG_RB = 8;   // rows per row-pass workgroup of the sample and objective transforms
 template <typename T> __host__ __device__ constexpr int big_cb() { return 128 / (int)(2 * sizeof(T)); }
+// threads of a column-pass workgroup: PH / 16 (FP32) or PH / 32 (FP64) values each
+template <typename T, int CB> __host__ __device__ constexpr int big_cols_nt() { return CB * 16 * (int)sizeof(T) / 4; }
 
 // ---------------------------------------------------------------------------
 // Column pass: length-PH DFT (forward or inverse, unnormalised) of columns
 // [c0, c0 + CB) of each plane, src -> dst (may alias).  Columns past PW/2
 // are computed on clamped copies and not stored.
 // ---------------------------------------------------------------------------
-template <typename T, int PH, int PW, bool INV>
-__global__ __launch_bounds__(256) void k_big_cols(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
-                                                  const cx<T>* __restrict__ twH) {
-  constexpr int WC = PW / 2 + 1, CB = big_cb<T>(), NT = 256;
+template <typename T, int PH, int PW, bool INV, int CB = big_cb<T>()>
+__global__ __launch_bounds__((big_cols_nt<T, CB>())) void k_big_cols(const cx<T>* __restrict__ src,
+                                                                  cx<T>* __restrict__ dst,
+                                                                  const cx<T>* __restrict__ twH) {
+  constexpr int WC = PW / 2 + 1, NT = big_cols_nt<T, CB>();
   constexpr int NE = PH * CB, EPT = (NE + NT - 1) / NT;
   __shared__ __align__(16) cx<T> buf[NE];   // buf[u * CB + c]
   __shared__ cx<T> sH[PH];
@@ -123,12 +128,12 @@ __global__ __launch_bounds__(256) void k_big_rows_inv_crop(const cx<T>* __restri
 //   completes S = F(U - W)).  On the last iteration only U is stored.
 // W = 0 on entry when first.
 // ---------------------------------------------------------------------------
-template <typename T, int PH, int PW>
+template <typename T, int PH, int PW, int RB = BIG_RB>
 __global__ __launch_bounds__(256) void k_big_code_rows(const cx<T>* __restrict__ Y, T* __restrict__ W,
                                                        cx<T>* __restrict__ S, T* __restrict__ Uout,
                                                        const cx<T>* __restrict__ twW, T kappa, int first,
                                                        int last) {
-  constexpr int M = PW / 2, WC = M + 1, NT = 256, RB = BIG_RB;
+  constexpr int M = PW / 2, WC = M + 1, NT = 256;
   constexpr int NE = RB * WC, NR = RB * PW;
   __shared__ __align__(16) cx<T> buf[NE];
   __shared__ cx<T> sW[PW];

@@ -259,6 +259,38 @@ int launch_irfft2_crop(ocsc_ctx* c, const cx<T>* src, long sstride, T* dst, int 
   return OCSC_OK;
 }
 
+// Two-pass code-plane step of one grid in the context's launch shape (column
+// block of col_bytes per spectrum row, row_block rows per row workgroup).
+template <typename T, int A, int B, int CB, int RB>
+void big_code_plane_shape(ocsc_ctx* c, const cx<T>* Zh, cx<T>* Yb, T* W, cx<T>* S, T* Uout, int nplanes, T kappa,
+                          int first, int last) {
+  const cx<T>* tH = (const cx<T>*)c->twH;
+  const cx<T>* tW = (const cx<T>*)c->twW;
+  constexpr int NTC = big_cols_nt<T, CB>();
+  const dim3 rows(A / RB, nplanes), cols((c->Wc + CB - 1) / CB, nplanes);
+  hipLaunchKernelGGL((k_big_cols<T, A, B, true, CB>), cols, dim3(NTC), 0, c->stream, Zh, Yb, tH);
+  hipLaunchKernelGGL((k_big_code_rows<T, A, B, RB>), rows, dim3(256), 0, c->stream, (const cx<T>*)Yb, W, S, Uout,
+                     tW, kappa, first, last);
+  if (!last) hipLaunchKernelGGL((k_big_cols<T, A, B, false, CB>), cols, dim3(NTC), 0, c->stream, (const cx<T>*)S, S, tH);
+}
+
+template <typename T, int A, int B>
+bool big_code_plane(ocsc_ctx* c, const cx<T>* Zh, cx<T>* Yb, T* W, cx<T>* S, T* Uout, int nplanes, T kappa,
+                    int first, int last) {
+  const int cbytes = c->tune.col_bytes, rb = c->tune.row_block;
+#define X(CBY, RB)                                                                                        \
+  if constexpr ((long)A * CBY <= 131072) {                                                                \
+    if (cbytes == CBY && rb == RB) {                                                                      \
+      big_code_plane_shape<T, A, B, CBY / (int)sizeof(cx<T>), RB>(c, Zh, Yb, W, S, Uout, nplanes, kappa,  \
+                                                                  first, last);                           \
+      return true;                                                                                        \
+    }                                                                                                     \
+  }
+  X(128, 4) X(128, 8) X(128, 16) X(256, 4) X(256, 8) X(256, 16) X(512, 4) X(512, 8) X(512, 16)
+#undef X
+  return false;
+}
+
 template <typename T>
 int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int last) {
   // samples [off, off + nplanes / K) of the code workspace
@@ -272,23 +304,18 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
   const T kappa = (T)(c->lam / c->rho);
   if (c->big) {
     // column inverse of Zh into Y, row pass (U-step, dual, rows of F(U - W)) into S, column pass on S
-    const dim3 rows(c->Ph / BIG_RB, nplanes), cols((c->Wc + big_cb<T>() - 1) / big_cb<T>(), nplanes);
+    bool done = false;
     switch (c->Ph * 1000 + c->Pw) {
-#define X(A, B)                                                                                             \
-  case A * 1000 + B:                                                                                        \
-    hipLaunchKernelGGL((k_big_cols<T, A, B, true>), cols, dim3(256), 0, c->stream, (const cx<T>*)Zh, Yb,   \
-                       tH);                                                                                 \
-    hipLaunchKernelGGL((k_big_code_rows<T, A, B>), rows, dim3(256), 0, c->stream, (const cx<T>*)Yb, W, S,   \
-                       Uout, tW, kappa, first, last);                                                       \
-    if (!last)                                                                                              \
-      hipLaunchKernelGGL((k_big_cols<T, A, B, false>), cols, dim3(256), 0, c->stream, (const cx<T>*)S, S,  \
-                         tH);                                                                               \
+#define X(A, B)                                              \
+  case A * 1000 + B:                                         \
+    done = big_code_plane<T, A, B>(c, Zh, Yb, W, S, Uout, nplanes, kappa, first, last); \
     break;
       OCSC_BIG_CASES(X)
 #undef X
       default:
-        return fail(c, OCSC_E_UNSUPPORTED, "no code-plane kernel for this grid");
+        break;
     }
+    if (!done) return fail(c, OCSC_E_UNSUPPORTED, "no code-plane kernel for this grid and launch shape");
     LAUNCHED(c);
     return OCSC_OK;
   }
@@ -345,7 +372,7 @@ int launch_zstep(ocsc_ctx* c, int off, int B, int first, bool last) {
   // the last iterate also goes frequency-major to the matrix-core history update
   cx<T>* Zt = (last && c->chol) ? (cx<T>*)c->Zt : nullptr;
   const int K = c->K;
-  bool ok;
+  bool ok = false;
   if (K <= 16) ok = zstep_shape<T, 1>(c, off, B, first, Zt);
   else if (K <= 32) ok = zstep_shape<T, 2>(c, off, B, first, Zt);
   else if (K <= 64) ok = zstep_shape<T, 4>(c, off, B, first, Zt);
@@ -499,6 +526,27 @@ int flush_fold(ocsc_ctx* c) {
   return OCSC_OK;
 }
 
+// The J_z ADMM iterations of samples [off, off + B) (spectra already in xh).
+// With chunk_samples set, groups of that many samples run all their
+// iterations before the next group starts, so that a group's code workspace
+// (spectra, dual, column-pass output) can stay in the Infinity Cache between
+// launches; the samples are independent, so the values are the same.
+template <typename T>
+int code_iterations(ocsc_ctx* c, int off, int B, T* Uout) {
+  const int chunk = c->tune.chunk_samples > 0 ? c->tune.chunk_samples : B;
+  for (int s0 = 0; s0 < B; s0 += chunk) {
+    const int nb = B - s0 < chunk ? B - s0 : chunk;
+    T* U = Uout ? Uout + (size_t)s0 * c->K * c->P : nullptr;
+    for (int j = 0; j < c->Jz; ++j) {
+      int rc = launch_zstep<T>(c, off + s0, nb, j == 0, j == c->Jz - 1);
+      if (rc) return rc;
+      rc = launch_code_plane<T>(c, off + s0, nb * c->K, U, j == 0, j == c->Jz - 1);
+      if (rc) return rc;
+    }
+  }
+  return OCSC_OK;
+}
+
 // ---------------------------------------------------------------- calls by type
 // Code B samples into the pending slots [off, off + B) (off = 0: a new
 // minibatch; off = pending_B: appended to the pending ones).
@@ -510,12 +558,8 @@ int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes, int off) {
   if (rc) return rc;
   // Ubuf (null unless the history is kept) holds codes the caller does not keep
   T* Uout = codes ? (T*)codes : (c->Ubuf ? (T*)c->Ubuf + (size_t)off * c->K * c->P : nullptr);
-  for (int j = 0; j < c->Jz; ++j) {
-    rc = launch_zstep<T>(c, off, B, j == 0, j == c->Jz - 1);
-    if (rc) return rc;
-    rc = launch_code_plane<T>(c, off, B * c->K, Uout, j == 0, j == c->Jz - 1);
-    if (rc) return rc;
-  }
+  rc = code_iterations<T>(c, off, B, Uout);
+  if (rc) return rc;
   if (c->keep_hist) {
     // per-sample partial sums of ||x_b||^2 (Parseval) and ||U_b||_1, added to
     // the running sums when the samples are accumulated
@@ -939,7 +983,9 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   c->tune.plane_threads = c->big ? 256 : plane_threads(pad_h, pad_w);
   c->tune.zstep_freqs = 16;
   c->tune.zstep_samples = 1;
-  c->tune.reserved = 0;
+  c->tune.col_bytes = 128;
+  c->tune.row_block = BIG_RB;
+  c->tune.chunk_samples = 0;
   c->chol = (o.flags & OCSC_FLAG_CHOLESKY) != 0;
   c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0 || c->chol;
   c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
@@ -1205,11 +1251,15 @@ int ocsc_diagnostics(ocsc_ctx* c, double* out) {
 namespace {
 
 bool tuning_valid(const ocsc_ctx* c, const ocsc_tuning& t) {
-  if (t.reserved != 0) return false;
   const bool pt = c->big ? t.plane_threads == 256 : plane_nt_ok(c->Ph, c->Pw, t.plane_threads);
   const bool zf = t.zstep_freqs == 16 || t.zstep_freqs == 32 || t.zstep_freqs == 64;
   const bool sb = t.zstep_samples == 1 || t.zstep_samples == 2 || t.zstep_samples == 4;
-  return pt && zf && sb;
+  const bool cb = (t.col_bytes == 128 || t.col_bytes == 256 || t.col_bytes == 512) &&
+                  (long)c->Ph * t.col_bytes <= 131072;
+  const bool rb = t.row_block == 4 || t.row_block == 8 || t.row_block == 16;
+  const bool ch = t.chunk_samples == 0 || t.chunk_samples == 1 || t.chunk_samples == 2 || t.chunk_samples == 4 ||
+                  t.chunk_samples == 8 || t.chunk_samples == 16;
+  return pt && zf && sb && cb && rb && ch;
 }
 
 struct EventPair {
@@ -1272,16 +1322,41 @@ int autotune_t(ocsc_ctx* c, int B, double* best_ms) {
     if (rc) break;
   }
   c->tune = start;
+  // plane kernel: workgroup size (one-pass grids) or column block x row block (two-pass grids)
   for (int nt : {256, 512, 1024}) {
+    for (int cby : {128, 256, 512}) {
+      for (int rb : {4, 8, 16}) {
+        if (rc) break;
+        if (!c->big && (cby != start.col_bytes || rb != start.row_block)) continue;
+        c->tune.plane_threads = nt;
+        c->tune.col_bytes = cby;
+        c->tune.row_block = rb;
+        if (!tuning_valid(c, c->tune)) continue;
+        double ms = 0;
+        rc = time_launches(c, ev, [&] { return launch_code_plane<T>(c, 0, B * c->K, nullptr, 0, 0); }, REPS, &ms);
+        if (rc) break;
+        if (ms < best_p) {
+          best_p = ms;
+          best.plane_threads = nt;
+          best.col_bytes = cby;
+          best.row_block = rb;
+        }
+      }
+    }
+  }
+  // sample groups: whole code updates (all iterations) with the chosen kernel shapes
+  double best_c = 1e30;
+  c->tune = best;
+  for (int ch : {0, 1, 2, 4, 8, 16}) {
     if (rc) break;
-    c->tune.plane_threads = nt;
-    if (!tuning_valid(c, c->tune)) continue;
+    if (ch >= B) continue;
+    c->tune.chunk_samples = ch;
     double ms = 0;
-    rc = time_launches(c, ev, [&] { return launch_code_plane<T>(c, 0, B * c->K, nullptr, 0, 0); }, REPS, &ms);
+    rc = time_launches(c, ev, [&] { return code_iterations<T>(c, 0, B, (T*)nullptr); }, 2, &ms);
     if (rc) break;
-    if (ms < best_p) {
-      best_p = ms;
-      best.plane_threads = nt;
+    if (ms < best_c * 0.98 || ch == 0) {   // a group size must win by 2% over the whole batch
+      best_c = ms;
+      best.chunk_samples = ch;
     }
   }
   c->prof_mask = mask;

@@ -64,7 +64,9 @@ class OcscTuning(ctypes.Structure):
         ("plane_threads", ctypes.c_int32),
         ("zstep_freqs", ctypes.c_int32),
         ("zstep_samples", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("col_bytes", ctypes.c_int32),
+        ("row_block", ctypes.c_int32),
+        ("chunk_samples", ctypes.c_int32),
     ]
 
 
@@ -247,7 +249,7 @@ def ocsc_graph_destroy(h) -> None:
     _check(None, load().ocsc_graph_destroy(h))
 
 
-TUNING_FIELDS = ("plane_threads", "zstep_freqs", "zstep_samples")
+TUNING_FIELDS = ("plane_threads", "zstep_freqs", "zstep_samples", "col_bytes", "row_block", "chunk_samples")
 
 
 def ocsc_get_tuning(ctx) -> dict:

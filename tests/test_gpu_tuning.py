@@ -28,13 +28,22 @@ def images(n, ph, pw, seed):
 
 
 def shapes(ph, pw):
-    nts = [nt for nt in (256, 512, 1024) if nt * 4 <= ph * pw] if max(ph, pw) <= 128 else [256]
-    return [dict(plane_threads=nt, zstep_freqs=zf, zstep_samples=sb)
-            for nt, zf, sb in itertools.product(nts, (16, 32, 64), (1, 2, 4))]
+    """Every valid shape: Z-step tiles x (workgroup sizes, one-pass grids, or
+    column block x row block, two-pass grids)."""
+    z = list(itertools.product((16, 32, 64), (1, 2, 4)))
+    if max(ph, pw) <= 128:
+        planes = [(nt, 128, 8) for nt in (256, 512, 1024) if nt * 4 <= ph * pw]
+    else:
+        planes = [(256, cb, rb) for cb in (128, 256, 512) for rb in (4, 8, 16) if ph * cb <= 131072]
+    # sample groups of 0 (whole batch), 1 and 2 in turn (the batch has 3 samples)
+    return [dict(plane_threads=nt, zstep_freqs=zf, zstep_samples=sb, col_bytes=cb, row_block=rb,
+                 chunk_samples=(0, 1, 2)[i % 3])
+            for i, ((nt, cb, rb), (zf, sb)) in enumerate(itertools.product(planes, z))]
 
 
 @pytest.mark.parametrize("prec,ph,pw,K", [("f32", 128, 128, 20), ("f64", 64, 64, 16), ("f32", 32, 64, 40),
-                                          ("f32", 256, 256, 6), ("f64", 128, 128, 3)])
+                                          ("f32", 256, 256, 6), ("f64", 128, 128, 3), ("f64", 256, 512, 3),
+                                          ("f32", 512, 512, 2)])
 def test_every_shape_gives_the_same_bits(prec, ph, pw, K):
     say(f"case shapes {prec} {ph}x{pw} K={K}")
     from paper_1706_06972_amd.ocsc import OCSC
@@ -63,13 +72,20 @@ def test_invalid_shapes_are_refused():
     small = OCSC(4, 5, 5, 32, 32, 0.5, 1.0, precision="f32")
     big = OCSC(4, 5, 5, 256, 256, 0.5, 1.0, precision="f32")
     for g, bad in ((small, dict(plane_threads=512)), (small, dict(plane_threads=128)), (small, dict(zstep_freqs=8)),
-                   (small, dict(zstep_samples=3)), (big, dict(plane_threads=1024))):
+                   (small, dict(zstep_samples=3)), (big, dict(plane_threads=1024)), (small, dict(col_bytes=64)),
+                   (small, dict(row_block=2)), (big, dict(row_block=32)), (small, dict(chunk_samples=3))):
         before = g.tuning
         with pytest.raises(L.OcscError) as e:
             g.set_tuning(**bad)
         assert e.value.status == L.OCSC_E_INVALID_ARG
         assert g.tuning == before
-    assert small.tuning == dict(plane_threads=256, zstep_freqs=16, zstep_samples=1)
+    assert small.tuning == dict(plane_threads=256, zstep_freqs=16, zstep_samples=1, col_bytes=128, row_block=8,
+                                chunk_samples=0)
+    big512 = OCSC(2, 5, 5, 512, 512, 0.5, 1.0, precision="f32")
+    with pytest.raises(L.OcscError):
+        big512.set_tuning(col_bytes=512)   # 512 rows x 512 bytes exceed the column workgroup's LDS
+    big512.set_tuning(col_bytes=256, row_block=16)
+    big512.close()
     small.close()
     big.close()
 
