@@ -29,7 +29,7 @@ METRIC = "images/s coded+dict-updated (K=100, 128²) plain vs BF16/served; p99 l
 WORKLOAD = "ocsc_128x128_k100_f32"
 HBM_PEAK_GBS = 8000.0
 # the D-step sweep's source: common helpers and the sweep itself
-KERNEL_SRC = [os.path.join(ROOT, "paper_1706_06972_amd", "csrc", f) for f in ("common.hpp", "dstep.hpp")]
+KERNEL_SRC = [os.path.join(ROOT, "paper_1706_06972_amd", "csrc", f) for f in ("fft_lds.hpp", "common.hpp", "dstep.hpp")]
 HBM_SUMMARY = os.path.join(ROOT, "profiles", f"{WORKLOAD}_hbm_bytes.md")
 
 
@@ -201,6 +201,57 @@ def coding_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
             "mix_achieved_GBs": bytes_sum / len(CODING_GRIDS) * mix / 1e9,
             "note": "equal shares of the four grids; FP32; K=100, 11x11 filters, J_z=10; launch shapes "
                     "picked by ocsc_autotune per grid"}
+
+
+def grouped_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
+    """Uneven sizes: one batch per grid coded (a) by per-grid launches in
+    turn, with autotuned shapes, and (b) by one persistent grouped launch
+    (ocsc_code_update_group); full batches (the samples per launch of the
+    coding run) and single samples per grid."""
+    return {"full": _grouped(dev, CODING_GRIDS, K, iters, reps),
+            "single": _grouped(dev, tuple((n, 1) for n, _ in CODING_GRIDS), K, iters, 4 * reps),
+            "note": ("K=100, FP32, J_z=10; separate: per-grid launch sequences in turn on one stream; grouped: "
+                     "every iteration of every grid in one cooperative launch")}
+
+
+def _grouped(dev, grids, K, iters, reps) -> dict:
+    import torch
+    import synth
+    from paper_1706_06972_amd import ocsc as L
+    D0 = synth.initial_dictionary(K, 11, 11, 0)
+    models, xs = [], []
+    for n, B in grids:
+        wl = synth.Workload(name=f"group{n}", pad_h=n, pad_w=n, content_h=n // 2, content_w=n // 2, k_true=K,
+                            density=0.005, sigma_z=10.0, noise=0.01, K=K, filt_h=11, filt_w=11, lam=1.0, rho=1.0,
+                            iters_code=iters, iters_dict=10, batch=B, n_images=B, passes=1, precision="f32", seed=n)
+        xs.append(torch.as_tensor(synth.images(wl, range(B)), dtype=torch.float32, device=dev).contiguous())
+        g = L.OCSC(K, 11, 11, n, n, 1.0, 1.0, iters_code=iters, max_batch=B, precision="f32", device=dev)
+        g.set_dictionary(D0)
+        g.autotune(B)
+        models.append(g)
+    total = sum(B for _, B in grids)
+
+    def separate():
+        for g, x in zip(models, xs):
+            L.ocsc_code_update(g.ctx, x, x.shape[0], None)
+
+    def grouped():
+        L.ocsc_code_update_group([g.ctx for g in models], xs, [x.shape[0] for x in xs], None)
+
+    out = {}
+    for name, fn in (("separate", separate), ("grouped", grouped)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[name] = {"images_per_s": total / dt, "ms_per_launch": 1000.0 * dt}
+    for g in models:
+        g.close()
+    out["batch"] = {str(n): B for n, B in grids}
+    return out
 
 
 def graph_run(wl, xs, steps: int, warmup: int = 4, shape=None) -> dict:
@@ -405,6 +456,7 @@ def main():
     out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
     out["precision"] = batched_run(wl, args.batch, xs, dev, cholesky=True) if args.batch > 1 else None
     out["coding"] = coding_run(dev) if args.coding else None
+    out["grouped"] = grouped_run(dev) if args.coding else None
     out["copy_ceiling"] = copy_ceiling(dev)
     out["served"] = served_run(dev) if args.served else None
     if args.cpu_steps > 0:

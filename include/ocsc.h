@@ -145,6 +145,27 @@ int ocsc_code_update(ocsc_ctx* ctx, const void* x_dev, int B, void* codes_dev_ou
 int ocsc_code_append(ocsc_ctx* ctx, const void* x_dev, int B, void* codes_dev_out);
 
 /*
+ * Code one batch on each of n contexts -- grids of different sizes -- with
+ * all their code-ADMM iterations (eq. fcsc_code) in one persistent,
+ * cooperative launch: a fixed grid of resident workgroups takes each phase's
+ * work items grouped by grid (FFT size) and meets at a grid-wide barrier
+ * between phases (Z-steps; plane steps or inverse column passes; row passes;
+ * forward column passes).  The sample spectra are computed first by each
+ * context's usual transform.  Each context ends as after
+ * ocsc_code_update(ctxs[s], x_devs[s], Bs[s], codes_devs[s]), with the same
+ * values bit for bit.
+ *   1 <= n <= 8 distinct contexts with the same precision, iters_code and
+ *   device, K <= 128 each (OCSC_E_UNSUPPORTED above); 1 <= Bs[s] <= max_batch;
+ *   x_devs[s]: real [Bs[s]][pad_h][pad_w] of that context;
+ *   codes_devs: NULL, or n entries, each NULL or real [Bs[s]][K][pad_h][pad_w].
+ * Enqueued on the first context's stream after the earlier work of every
+ * member's stream; later work on every member's stream waits for it.
+ * Two-pass grids use the default column and row blocks.
+ */
+int ocsc_code_update_group(ocsc_ctx* const* ctxs, const void* const* x_devs, const int* Bs,
+                           void* const* codes_devs, int n);
+
+/*
  * Fold the spectra kept by the last ocsc_code_update into the history, in
  * sample order (eqs. B_update and C_update, unnormalised):
  *   G_p += conj(z_p) x_p;  C_p <- C_p - (C_p u)(C_p u)^H / (1 + u^H C_p u), u = conj(z_p),

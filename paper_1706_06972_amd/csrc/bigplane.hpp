@@ -12,6 +12,9 @@
 #pragma once
 #include "common.hpp"
 
+// the passes below compute the same bits wherever they are inlined
+#pragma clang fp contract(off)
+
 namespace ocsc {
 
 constexpr int BIG_RB = 8;   // rows per row-pass workgroup of the sample and objective transforms
@@ -24,17 +27,17 @@ template <typename T, int CB> __host__ __device__ constexpr int big_cols_nt() { 
 // [c0, c0 + CB) of each plane, src -> dst (may alias).  Columns past PW/2
 // are computed on clamped copies and not stored.
 // ---------------------------------------------------------------------------
-template <typename T, int PH, int PW, bool INV, int CB = big_cb<T>()>
-__global__ __launch_bounds__((big_cols_nt<T, CB>())) void k_big_cols(const cx<T>* __restrict__ src,
-                                                                  cx<T>* __restrict__ dst,
-                                                                  const cx<T>* __restrict__ twH) {
-  constexpr int WC = PW / 2 + 1, NT = big_cols_nt<T, CB>();
+// The body serves column block bx of plane q with LDS buf (PH * CB complex,
+// buf[u * CB + c]) and table sH.
+template <typename T, int PH, int PW, bool INV, int CB, int NT>
+__device__ __forceinline__ void big_cols_body(cx<T>* buf, cx<T>* sH, int bx, long q, const cx<T>* __restrict__ src,
+                                              cx<T>* __restrict__ dst, const cx<T>* __restrict__ twH) {
+  constexpr int WC = PW / 2 + 1;
   constexpr int NE = PH * CB, EPT = (NE + NT - 1) / NT;
-  __shared__ __align__(16) cx<T> buf[NE];   // buf[u * CB + c]
-  __shared__ cx<T> sH[PH];
+  static_assert(NE % NT == 0, "column block must be a multiple of the workgroup");
   const int tid = threadIdx.x;
-  const int c0 = blockIdx.x * CB;
-  const size_t pb = (size_t)blockIdx.y * PH * WC;
+  const int c0 = bx * CB;
+  const size_t pb = (size_t)q * PH * WC;
   for (int i = tid; i < PH; i += NT) sH[i] = twH[i];
   {
     cx<T> r[EPT];
@@ -55,6 +58,15 @@ __global__ __launch_bounds__((big_cols_nt<T, CB>())) void k_big_cols(const cx<T>
     const int u = e / CB, c = c0 + (e % CB);
     if (c < WC) dst[pb + (size_t)u * WC + c] = buf[e];
   }
+}
+
+template <typename T, int PH, int PW, bool INV, int CB = big_cb<T>()>
+__global__ __launch_bounds__((big_cols_nt<T, CB>())) void k_big_cols(const cx<T>* __restrict__ src,
+                                                                  cx<T>* __restrict__ dst,
+                                                                  const cx<T>* __restrict__ twH) {
+  __shared__ __align__(16) cx<T> buf[PH * CB];
+  __shared__ cx<T> sH[PH];
+  big_cols_body<T, PH, PW, INV, CB, big_cols_nt<T, CB>()>(buf, sH, blockIdx.x, blockIdx.y, src, dst, twH);
 }
 
 // ---------------------------------------------------------------------------
@@ -128,18 +140,17 @@ __global__ __launch_bounds__(256) void k_big_rows_inv_crop(const cx<T>* __restri
 //   completes S = F(U - W)).  On the last iteration only U is stored.
 // W = 0 on entry when first.
 // ---------------------------------------------------------------------------
-template <typename T, int PH, int PW, int RB = BIG_RB>
-__global__ __launch_bounds__(256) void k_big_code_rows(const cx<T>* __restrict__ Y, T* __restrict__ W,
-                                                       cx<T>* __restrict__ S, T* __restrict__ Uout,
-                                                       const cx<T>* __restrict__ twW, T kappa, int first,
-                                                       int last) {
-  constexpr int M = PW / 2, WC = M + 1, NT = 256;
+// The body serves row block bx of plane q with LDS buf (RB * (PW/2 + 1)
+// complex) and table sW.
+template <typename T, int PH, int PW, int RB, int NT>
+__device__ __forceinline__ void big_code_rows_body(cx<T>* buf, cx<T>* sW, int bx, size_t q,
+                                                   const cx<T>* __restrict__ Y, T* __restrict__ W,
+                                                   cx<T>* __restrict__ S, T* __restrict__ Uout,
+                                                   const cx<T>* __restrict__ twW, T kappa, int first, int last) {
+  constexpr int M = PW / 2, WC = M + 1;
   constexpr int NE = RB * WC, NR = RB * PW;
-  __shared__ __align__(16) cx<T> buf[NE];
-  __shared__ cx<T> sW[PW];
   const int tid = threadIdx.x;
-  const int r0 = blockIdx.x * RB;
-  const size_t q = blockIdx.y;
+  const int r0 = bx * RB;
   const size_t so = q * PH * WC + (size_t)r0 * WC;   // spectrum rows
   const size_t ro = q * PH * PW + (size_t)r0 * PW;   // real rows
   for (int i = tid; i < PW; i += NT) sW[i] = twW[i];
@@ -162,8 +173,7 @@ __global__ __launch_bounds__(256) void k_big_code_rows(const cx<T>* __restrict__
     if (NR % NT != 0 && e >= NR) continue;
     const int rr = e / PW, c = e % PW;
     const cx<T> v = buf[rr * WC + (c >> 1)];
-    const T y = ((c & 1) ? v.y : v.x) * scale;
-    const T a = y + wv[j];
+    const T a = fma((c & 1) ? v.y : v.x, scale, wv[j]);   // y + W, y the inverse transform
     const T u = copysign(fmax(fabs(a) - kappa, (T)0), a);
     const T wn = a - u;   // W + y - U
     if (last) {
@@ -188,4 +198,16 @@ __global__ __launch_bounds__(256) void k_big_code_rows(const cx<T>* __restrict__
   for (int e = tid; e < NE; e += NT) S[so + e] = buf[e];
 }
 
+template <typename T, int PH, int PW, int RB = BIG_RB>
+__global__ __launch_bounds__(256) void k_big_code_rows(const cx<T>* __restrict__ Y, T* __restrict__ W,
+                                                       cx<T>* __restrict__ S, T* __restrict__ Uout,
+                                                       const cx<T>* __restrict__ twW, T kappa, int first,
+                                                       int last) {
+  __shared__ __align__(16) cx<T> buf[RB * (PW / 2 + 1)];
+  __shared__ cx<T> sW[PW];
+  big_code_rows_body<T, PH, PW, RB, 256>(buf, sW, blockIdx.x, blockIdx.y, Y, W, S, Uout, twW, kappa, first, last);
+}
+
 }  // namespace ocsc
+
+#pragma clang fp contract(fast)

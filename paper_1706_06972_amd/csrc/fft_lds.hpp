@@ -13,8 +13,15 @@
 // stage twiddles, runs an in-register radix-R DFT and writes the results back
 // to their Stockham positions.  All threads finish reading before any writes
 // (one barrier in between), so a stage works in place.
+//
+// Floating-point contraction is off in this file and in the code-update
+// bodies (kernels.hpp, bigplane.hpp): every fused multiply-add is written
+// out, so a body computes the same bits wherever the compiler inlines it
+// (separate kernels, launch shapes, the grouped persistent launch).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#pragma clang fp contract(off)
 
 namespace ocsc {
 
@@ -27,11 +34,11 @@ template <typename T> __device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r
 template <typename T> __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
 template <typename T> __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
 template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return mk<T>(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 // a * conj(b)
 template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
-  return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  return mk<T>(fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -(a.x * b.y)));
 }
 template <typename T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return mk<T>(a.x, -a.y); }
 template <typename T> __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
@@ -54,7 +61,7 @@ __device__ __forceinline__ cx<T> rot16(cx<T> v, int e) {
   if (e == 4) return INV ? mk<T>(-v.y, v.x) : mk<T>(v.y, -v.x);
   const T c = (T)kCos16[e];
   const T s = INV ? (T)kSin16[e] : -(T)kSin16[e];
-  return mk<T>(v.x * c - v.y * s, v.x * s + v.y * c);
+  return mk<T>(fma(v.x, c, -(v.y * s)), fma(v.x, s, v.y * c));
 }
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
@@ -238,3 +245,5 @@ __device__ void irfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int t
 }
 
 }  // namespace ocsc
+
+#pragma clang fp contract(fast)

@@ -10,6 +10,9 @@
 #include "dstep.hpp"
 #include "vstep.hpp"
 
+// the code-update bodies below compute the same bits wherever they are inlined
+#pragma clang fp contract(off)
+
 namespace ocsc {
 
 // Global <-> LDS traffic of one PH x PW plane in 16-byte vectors.  Every
@@ -141,20 +144,19 @@ __global__ __launch_bounds__(NT) void k_irfft2_crop(const cx<T>* __restrict__ sr
 // Code update, spatial half of one ADMM iteration, one workgroup per plane:
 //   Y = Re F^-1(Zh);  U = S_kappa(Y + W);  W <- Y + W - U;  S = F(U - W).
 // first: W = 0 on entry.  last: write U to Uout (if non-null) and stop.
+// The body serves plane q with the workgroup's LDS buf (PH * LDW complex)
+// and tables sH, sW; the caller separates successive planes by a barrier.
 // ---------------------------------------------------------------------------
 template <typename T, int PH, int PW, int NT>
-__global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh, T* __restrict__ W,
-                                                   cx<T>* __restrict__ S, T* __restrict__ Uout,
-                                                   const cx<T>* __restrict__ twH,
-                                                   const cx<T>* __restrict__ twW, T kappa, int first,
-                                                   int last) {
+__device__ __forceinline__ void code_plane_body(cx<T>* buf, cx<T>* sH, cx<T>* sW, long q,
+                                                const cx<T>* __restrict__ Zh, T* __restrict__ W,
+                                                cx<T>* __restrict__ S, T* __restrict__ Uout,
+                                                const cx<T>* __restrict__ twH, const cx<T>* __restrict__ twW,
+                                                T kappa, int first, int last) {
   using G = PlaneGeom<PH, PW>;
   using IO = PlaneIO<T, PH, PW, NT>;
   constexpr int VR = IO::VR, CR = IO::CR, NRV = IO::NRV;
-  __shared__ __align__(16) cx<T> buf[PH * G::LDW];
-  __shared__ cx<T> sH[PH], sW[PW];
   const int tid = threadIdx.x;
-  const long q = blockIdx.x;
   load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
   IO::spec_in(buf, Zh + q * G::PF, tid);
   // the dual W of this plane is fetched while the inverse transform runs
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
 #pragma unroll
       for (int h = 0; h < VR / 2; ++h) {
         const cx<T> y = o[h];
-        const T v0 = y.x * scale + w[2 * h], v1 = y.y * scale + w[2 * h + 1];
+        const T v0 = fma(y.x, scale, w[2 * h]), v1 = fma(y.y, scale, w[2 * h + 1]);
         const T u0 = copysign(fmax(fabs(v0) - kappa, (T)0), v0);
         const T u1 = copysign(fmax(fabs(v1) - kappa, (T)0), v1);
         u[2 * h] = u0;
@@ -202,6 +204,17 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
   IO::spec_out(S + q * G::PF, buf, tid);
 }
 
+template <typename T, int PH, int PW, int NT>
+__global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh, T* __restrict__ W,
+                                                   cx<T>* __restrict__ S, T* __restrict__ Uout,
+                                                   const cx<T>* __restrict__ twH,
+                                                   const cx<T>* __restrict__ twW, T kappa, int first,
+                                                   int last) {
+  __shared__ __align__(16) cx<T> buf[PH * PlaneGeom<PH, PW>::LDW];
+  __shared__ cx<T> sH[PH], sW[PW];
+  code_plane_body<T, PH, PW, NT>(buf, sH, sW, (long)blockIdx.x, Zh, W, S, Uout, twH, twW, kappa, first, last);
+}
+
 // ---------------------------------------------------------------------------
 // Code update, frequency half of one ADMM iteration (the Z-step).  At each
 // frequency p with a = Dh[:, p], s = S[:, p]:
@@ -216,17 +229,16 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
 // frequency in kq order), so every launch shape gives the same bits.
 // first: s = 0.
 // ---------------------------------------------------------------------------
+// The body serves frequency block bx of sample block by with the LDS
+// reduction buffer red (16 * (ZF + 1) complex).
 template <typename T, int KPT, int ZF, int SB>
-__global__ __launch_bounds__(16 * ZF) void k_code_zstep(const cx<T>* __restrict__ Dh,
-                                                        const T* __restrict__ gam,
-                                                        const cx<T>* __restrict__ xh,
-                                                        const cx<T>* __restrict__ S,
-                                                        cx<T>* __restrict__ Zh, int K, int Pf, int B,
-                                                        int first, cx<T>* __restrict__ Zt, int ldt, int bt0) {
+__device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by, const cx<T>* __restrict__ Dh,
+                                           const T* __restrict__ gam, const cx<T>* __restrict__ xh,
+                                           const cx<T>* __restrict__ S, cx<T>* __restrict__ Zh, int K, int Pf,
+                                           int B, int first, cx<T>* __restrict__ Zt, int ldt, int bt0) {
   // Zt (optional): the same values frequency-major, Zt[(p * ldt + bt0 + b) * K + k]
-  __shared__ cx<T> red[16][ZF + 1];
   const int f = threadIdx.x % ZF, kq = threadIdx.x / ZF;
-  const int p = blockIdx.x * ZF + f;
+  const int p = bx * ZF + f;
   const bool ok = p < Pf;
   cx<T> a[KPT];
 #pragma unroll
@@ -235,7 +247,7 @@ __global__ __launch_bounds__(16 * ZF) void k_code_zstep(const cx<T>* __restrict_
     a[j] = (ok && k < K) ? Dh[(size_t)k * Pf + p] : mk<T>(0, 0);
   }
   for (int sb = 0; sb < SB; ++sb) {
-    const int b = blockIdx.y * SB + sb;
+    const int b = by * SB + sb;
     if (b >= B) break;   // the same for the whole workgroup
     cx<T> s[KPT];
     cx<T> acc = mk<T>(0, 0);
@@ -268,6 +280,17 @@ __global__ __launch_bounds__(16 * ZF) void k_code_zstep(const cx<T>* __restrict_
     }
     if (SB > 1) __syncthreads();   // red is reused by the next sample
   }
+}
+
+template <typename T, int KPT, int ZF, int SB>
+__global__ __launch_bounds__(16 * ZF) void k_code_zstep(const cx<T>* __restrict__ Dh,
+                                                        const T* __restrict__ gam,
+                                                        const cx<T>* __restrict__ xh,
+                                                        const cx<T>* __restrict__ S,
+                                                        cx<T>* __restrict__ Zh, int K, int Pf, int B,
+                                                        int first, cx<T>* __restrict__ Zt, int ldt, int bt0) {
+  __shared__ cx<T> red[16][ZF + 1];
+  zstep_body<T, KPT, ZF, SB>(red, blockIdx.x, blockIdx.y, Dh, gam, xh, S, Zh, K, Pf, B, first, Zt, ldt, bt0);
 }
 
 // gam_p = 1 / (rho + sum_k |Dh[k][p]|^2): 64 frequencies per workgroup, the
@@ -370,3 +393,5 @@ __global__ void k_fill_zero(T* __restrict__ x, size_t n) {
 }
 
 }  // namespace ocsc
+
+#pragma clang fp contract(fast)

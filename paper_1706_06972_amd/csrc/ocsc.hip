@@ -20,6 +20,7 @@
 #include "bigplane.hpp"
 #include "chol.hpp"
 #include "diag.hpp"
+#include "group.hpp"
 #include "kernels.hpp"
 
 using namespace ocsc;
@@ -550,16 +551,25 @@ int code_iterations(ocsc_ctx* c, int off, int B, T* Uout) {
 // ---------------------------------------------------------------- calls by type
 // Code B samples into the pending slots [off, off + B) (off = 0: a new
 // minibatch; off = pending_B: appended to the pending ones).
+// Before the iterations: a deferred fold, then the sample spectra into slots [off, off + B).
 template <typename T>
-int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes, int off) {
+int code_prologue(ocsc_ctx* c, const void* x, int B, int off) {
   int rc = flush_fold<T>(c);
   if (rc) return rc;
-  rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh + (size_t)off * c->Pf, c->Pf, B);
-  if (rc) return rc;
-  // Ubuf (null unless the history is kept) holds codes the caller does not keep
-  T* Uout = codes ? (T*)codes : (c->Ubuf ? (T*)c->Ubuf + (size_t)off * c->K * c->P : nullptr);
-  rc = code_iterations<T>(c, off, B, Uout);
-  if (rc) return rc;
+  return launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh + (size_t)off * c->Pf, c->Pf, B);
+}
+
+// Where the codes of slots [off, ...) go: the caller's buffer, else (history
+// kept) the library's, else nowhere.
+template <typename T>
+T* code_out(ocsc_ctx* c, void* codes, int off) {
+  return codes ? (T*)codes : (c->Ubuf ? (T*)c->Ubuf + (size_t)off * c->K * c->P : nullptr);
+}
+
+// After the iterations: per-sample partial sums for the kept history; the
+// slots become pending.
+template <typename T>
+int code_epilogue(ocsc_ctx* c, const T* Uout, int B, int off) {
   if (c->keep_hist) {
     // per-sample partial sums of ||x_b||^2 (Parseval) and ||U_b||_1, added to
     // the running sums when the samples are accumulated
@@ -568,13 +578,150 @@ int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes, int off) {
                        (const cx<T>*)c->xh + (size_t)off * c->Pf, (const cx<T>*)nullptr, c->pend + (size_t)off * 64,
                        1, c->Pf, c->Pw);
     LAUNCHED(c);
-    hipLaunchKernelGGL((k_abs_sum<T>), dim3(64, B), dim3(256), 0, c->stream, (const T*)Uout,
+    hipLaunchKernelGGL((k_abs_sum<T>), dim3(64, B), dim3(256), 0, c->stream, Uout,
                        c->pend + (size_t)(c->maxB + off) * 64, (long)c->K * c->P);
     LAUNCHED(c);
   }
   c->pending_B = off + B;
   return OCSC_OK;
 }
+
+// Code B samples into the pending slots [off, off + B) (off = 0: a new
+// minibatch; off = pending_B: appended to the pending ones).
+template <typename T>
+int code_update_t(ocsc_ctx* c, const void* x, int B, void* codes, int off) {
+  int rc = code_prologue<T>(c, x, B, off);
+  if (rc) return rc;
+  T* Uout = code_out<T>(c, codes, off);
+  rc = code_iterations<T>(c, off, B, Uout);
+  if (rc) return rc;
+  return code_epilogue<T>(c, Uout, B, off);
+}
+
+// Batches on several contexts (slots from 0), their iterations in one
+// cooperative launch of k_code_group on the first context's stream.
+template <typename T>
+int code_group_t(ocsc_ctx* const* cs, const void* const* xs, const int* Bs, void* const* codes, int n) {
+  ocsc_ctx* c0 = cs[0];
+  CodeGroupArgs<T> g{};
+  g.n = n;
+  g.Jz = c0->Jz;
+  size_t smem = 16 * (CG_ZF + 1) * sizeof(cx<T>);
+  int kmax = 0;
+  T* U[CG_MAX] = {};
+  long z = 0, pl = 0, r = 0, f = 0;
+  for (int s = 0; s < n; ++s) {
+    ocsc_ctx* c = cs[s];
+    int rc = code_prologue<T>(c, xs[s], Bs[s], 0);
+    if (rc) return rc;
+    U[s] = code_out<T>(c, codes ? codes[s] : nullptr, 0);
+    const int B = Bs[s], BK = B * c->K;
+    g.ph[s] = c->Ph;
+    g.pw[s] = c->Pw;
+    g.K[s] = c->K;
+    g.B[s] = B;
+    g.Pf[s] = c->Pf;
+    g.big[s] = c->big;
+    g.ldt[s] = c->maxB;
+    g.Dh[s] = (const cx<T>*)c->Dh;
+    g.gam[s] = (const T*)c->gam;
+    g.xh[s] = (const cx<T>*)c->xh;
+    g.S[s] = (cx<T>*)c->S;
+    g.Zh[s] = (cx<T>*)c->Zh;
+    g.W[s] = (T*)c->W;
+    g.Yb[s] = (cx<T>*)c->Yb;
+    g.U[s] = U[s];
+    g.Zt[s] = c->chol ? (cx<T>*)c->Zt : nullptr;
+    g.twH[s] = (const cx<T>*)c->twH;
+    g.twW[s] = (const cx<T>*)c->twW;
+    g.kappa[s] = (T)(c->lam / c->rho);
+    g.z0[s] = (int)z;
+    g.p0[s] = (int)pl;
+    g.r0[s] = (int)r;
+    g.f0[s] = (int)f;
+    z += (long)((c->Pf + CG_ZF - 1) / CG_ZF) * B;
+    size_t need;
+    if (c->big) {
+      g.any_big = 1;
+      pl += (long)cg_col_blocks<T>(c->Pw) * BK;
+      r += (long)(c->Ph / BIG_RB) * BK;
+      f += (long)cg_col_blocks<T>(c->Pw) * BK;
+      const size_t cols = (size_t)c->Ph * (big_cb<T>() + 1), rows = (size_t)BIG_RB * c->Wc + c->Pw;
+      need = (cols > rows ? cols : rows) * sizeof(cx<T>);
+    } else {
+      pl += BK;
+      need = ((size_t)c->Ph * c->Wc + c->Ph + c->Pw) * sizeof(cx<T>);
+    }
+    if (need > smem) smem = need;
+    if (c->K > kmax) kmax = c->K;
+  }
+  if (z > INT32_MAX || pl > INT32_MAX || r > INT32_MAX || f > INT32_MAX)
+    return fail(c0, OCSC_E_INVALID_ARG, "too many work items for one launch");
+  g.z0[n] = (int)z;
+  g.p0[n] = (int)pl;
+  g.r0[n] = (int)r;
+  g.f0[n] = (int)f;
+  const void* fn = kmax <= 16 ? (const void*)k_code_group<T, 1> : (const void*)k_code_group<T, 8>;
+  HIPX(c0, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  int per_cu = 0, cus = 0;
+  HIPX(c0, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, CG_NT, smem));
+  HIPX(c0, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c0->device));
+  if (per_cu < 1 || cus < 1) return fail(c0, OCSC_E_UNSUPPORTED, "the grouped code kernel does not fit a CU");
+  {
+    ProfScope ps(c0, OCSC_KC_CODEPLANE);
+    void* args[] = {&g};
+    HIPX(c0, hipLaunchCooperativeKernel(fn, dim3(per_cu * cus), dim3(CG_NT), args, (unsigned)smem, c0->stream));
+  }
+  for (int s = 0; s < n; ++s) {
+    int rc = code_epilogue<T>(cs[s], U[s], Bs[s], 0);
+    if (rc) return rc;
+  }
+  return OCSC_OK;
+}
+
+// Runs a call over several contexts on the first context's stream: that
+// stream first waits for the earlier work of every member's stream, each
+// member's stream is the first one's during the call, and afterwards every
+// member's stream waits for the call's work.
+struct StreamJoin {
+  ocsc_ctx* const* cs;
+  int n;
+  hipStream_t ls;
+  std::vector<hipStream_t> saved;
+  std::vector<hipEvent_t> evs;
+  StreamJoin(ocsc_ctx* const* cs_, int n_) : cs(cs_), n(n_), ls(cs_[0]->stream), saved(n_) {
+    for (int s = 0; s < n; ++s) saved[s] = cs[s]->stream;
+  }
+  hipError_t order(hipStream_t from, hipStream_t to) {
+    if (from == to) return hipSuccess;
+    hipEvent_t e = nullptr;
+    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    if (err != hipSuccess) return err;
+    evs.push_back(e);
+    err = hipEventRecord(e, from);
+    return err == hipSuccess ? hipStreamWaitEvent(to, e, 0) : err;
+  }
+  hipError_t enter() {
+    for (int s = 1; s < n; ++s) {
+      hipError_t err = order(saved[s], ls);
+      if (err != hipSuccess) return err;
+    }
+    for (int s = 0; s < n; ++s) cs[s]->stream = ls;
+    return hipSuccess;
+  }
+  hipError_t leave() {
+    for (int s = 0; s < n; ++s) cs[s]->stream = saved[s];
+    for (int s = 1; s < n; ++s) {
+      hipError_t err = order(ls, saved[s]);
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  }
+  ~StreamJoin() {
+    for (int s = 0; s < n; ++s) cs[s]->stream = saved[s];
+    for (auto e : evs) (void)hipEventDestroy(e);
+  }
+};
 
 template <typename T>
 int dict_update_t(ocsc_ctx* c) {
@@ -1114,6 +1261,38 @@ int ocsc_code_update(ocsc_ctx* c, const void* x, int B, void* codes) {
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
   if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
   return c->sr == 8 ? code_update_t<double>(c, x, B, codes, 0) : code_update_t<float>(c, x, B, codes, 0);
+}
+
+int ocsc_code_update_group(ocsc_ctx* const* ctxs, const void* const* xs, const int* Bs, void* const* codes, int n) {
+  if (!ctxs || !xs || !Bs || n < 1 || n > CG_MAX)
+    return fail(nullptr, OCSC_E_INVALID_ARG, "need 1 <= n <= 8 contexts, samples and batch sizes");
+  ocsc_ctx* c0 = ctxs[0];
+  if (!c0) return fail(nullptr, OCSC_E_INVALID_ARG, "NULL context");
+  for (int s = 0; s < n; ++s) {
+    ocsc_ctx* c = ctxs[s];
+    if (!c) return fail(c0, OCSC_E_INVALID_ARG, "NULL context");
+    for (int r = 0; r < s; ++r)
+      if (ctxs[r] == c) return fail(c0, OCSC_E_INVALID_ARG, "a context is listed twice");
+    if (c->sr != c0->sr || c->Jz != c0->Jz || c->device != c0->device)
+      return fail(c0, OCSC_E_INVALID_ARG, "contexts differ in precision, iters_code or device");
+    if (!xs[s]) return fail(c0, OCSC_E_INVALID_ARG, "x_dev is NULL");
+    void* cd = codes ? codes[s] : nullptr;
+    if (((uintptr_t)xs[s] | (uintptr_t)cd) & 15) return fail(c0, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
+    if (Bs[s] < 1 || Bs[s] > c->maxB) return fail(c0, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
+  }
+  for (int s = 0; s < n; ++s)
+    if (ctxs[s]->K > 128) return fail(c0, OCSC_E_UNSUPPORTED, "the grouped code launch supports K <= 128");
+  int coop = 0;
+  HIPX(c0, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c0->device));
+  if (!coop) return fail(c0, OCSC_E_UNSUPPORTED, "the device has no cooperative launch");
+  StreamJoin join(ctxs, n);
+  hipError_t err = join.enter();
+  if (err != hipSuccess) return fail(c0, OCSC_E_HIP, std::string("stream ordering: ") + hipGetErrorString(err));
+  const int rc = c0->sr == 8 ? code_group_t<double>(ctxs, xs, Bs, codes, n) : code_group_t<float>(ctxs, xs, Bs, codes, n);
+  err = join.leave();
+  if (rc) return rc;
+  if (err != hipSuccess) return fail(c0, OCSC_E_HIP, std::string("stream ordering: ") + hipGetErrorString(err));
+  return OCSC_OK;
 }
 
 int ocsc_code_append(ocsc_ctx* c, const void* x, int B, void* codes) {

@@ -36,7 +36,8 @@ KERNEL_CLASS = {"fft": 0, "zstep": 1, "codeplane": 2, "history": 3, "dstep": 4, 
 
 EXPORTS = [
     "ocsc_default_opts", "ocsc_init", "ocsc_destroy", "ocsc_set_dictionary", "ocsc_get_dictionary",
-    "ocsc_code_update", "ocsc_code_append", "ocsc_history_accumulate", "ocsc_dict_update",
+    "ocsc_code_update", "ocsc_code_append", "ocsc_code_update_group", "ocsc_history_accumulate",
+    "ocsc_dict_update",
     "ocsc_dict_update_group", "ocsc_objective",
     "ocsc_objective_terms", "ocsc_surrogate", "ocsc_diagnostics", "ocsc_sync",
     "ocsc_graph_create", "ocsc_graph_launch", "ocsc_graph_destroy",
@@ -100,6 +101,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ocsc_get_dictionary": (i32, [vp, vp]),
         "ocsc_code_update": (i32, [vp, vp, i32, vp]),
         "ocsc_code_append": (i32, [vp, vp, i32, vp]),
+        "ocsc_code_update_group": (i32, [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                         ctypes.POINTER(vp), i32]),
         "ocsc_dict_update_group": (i32, [ctypes.POINTER(vp), i32]),
         "ocsc_history_accumulate": (i32, [vp]),
         "ocsc_dict_update": (i32, [vp]),
@@ -192,6 +195,18 @@ def ocsc_code_update(ctx, x, B, codes_out=None) -> None:
 
 def ocsc_code_append(ctx, x, B, codes_out=None) -> None:
     _check(ctx, load().ocsc_code_append(ctx, _ptr(x), int(B), _ptr(codes_out)))
+
+
+def ocsc_code_update_group(ctxs, xs, Bs, codes_out=None) -> None:
+    """One persistent launch coding xs[s] (Bs[s] samples) on ctxs[s] for every s."""
+    n = len(ctxs)
+    if not (len(xs) == len(Bs) == n) or (codes_out is not None and len(codes_out) != n):
+        raise ValueError("ctxs, xs, Bs (and codes_out) must have the same length")
+    carr = (ctypes.c_void_p * n)(*[c.value for c in ctxs])
+    xarr = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+    barr = (ctypes.c_int * n)(*[int(b) for b in Bs])
+    oarr = None if codes_out is None else (ctypes.c_void_p * n)(*[_ptr(c) for c in codes_out])
+    _check(ctxs[0], load().ocsc_code_update_group(carr, xarr, barr, oarr, n))
 
 
 def ocsc_dict_update_group(ctxs) -> None:
@@ -404,6 +419,24 @@ class OCSC:
 
     def dict_update(self):
         ocsc_dict_update(self.ctx)
+
+    @staticmethod
+    def code_update_group(models, xs, want_codes=True):
+        """Code xs[i] (B_i x pad_h_i x pad_w_i) on models[i], all iterations of
+        all grids in one persistent launch; returns the codes per model."""
+        xs = [m._dev(x) for m, x in zip(models, xs)]
+        xs = [x[None] if x.dim() == 2 else x for x in xs]
+        for m, x in zip(models, xs):
+            if tuple(x.shape[1:]) != m.shape:
+                raise ValueError("samples must have shape (B, pad_h, pad_w) of their model")
+        codes = None
+        if want_codes:
+            codes = [m.torch.empty((x.shape[0], m.K) + m.shape, dtype=m.dtype, device=m.device)
+                     for m, x in zip(models, xs)]
+        ocsc_code_update_group([m.ctx for m in models], xs, [x.shape[0] for x in xs], codes)
+        for m, x in zip(models, xs):
+            m._x_keep = x
+        return codes
 
     @staticmethod
     def dict_update_group(models):
