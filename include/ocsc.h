@@ -297,7 +297,13 @@ int ocsc_graph_destroy(ocsc_graph* graph);
  *                  this many samples, each group running all its iterations
  *                  before the next starts (its workspace can then stay in
  *                  the Infinity Cache); 0 runs the whole batch together.
- * Defaults: plane_threads 1024 for 128 x 128 grids, else 256; 16; 1; 128; 8; 0.
+ *   two_pass:      1 on two-pass grids; on 64 x 64 and 128 x 128 grids 0 (the
+ *                  one-pass plane kernel) or 1 (the column and row passes,
+ *                  more workgroups for small batches; the first selection
+ *                  allocates a max_batch x K spectrum buffer, OCSC_E_OOM);
+ *                  0 on other grids.
+ * Defaults: plane_threads 1024 for 128 x 128 grids, else 256; 16; 1; 128; 8; 0;
+ * 1 on two-pass grids, else 0.
  * ocsc_autotune times whole code updates for the group size.
  * ------------------------------------------------------------------------- */
 typedef struct {
@@ -307,6 +313,7 @@ typedef struct {
   int32_t col_bytes;
   int32_t row_block;
   int32_t chunk_samples;
+  int32_t two_pass;
 } ocsc_tuning;
 
 int ocsc_get_tuning(const ocsc_ctx* ctx, ocsc_tuning* out);

@@ -167,6 +167,9 @@ constexpr bool plane_nt_ok(int ph, int pw, int nt) {
   X(32, 32) X(32, 64) X(32, 128) X(64, 32) X(64, 64) X(64, 128) X(128, 32) X(128, 64) X(128, 128)
 // grids whose planes do not fit in LDS: two-pass transforms (bigplane.hpp)
 #define OCSC_BIG_CASES(X) X(256, 256) X(256, 512) X(512, 256) X(512, 512)
+// one-pass grids whose code-plane step may also run as the two-pass kernels
+#define OCSC_TWO_PASS_SMALL(X) X(64, 64) X(128, 128)
+bool two_pass_capable(int ph, int pw) { return (ph == 64 && pw == 64) || (ph == 128 && pw == 128); }
 
 bool big_grid(int ph, int pw) { return ph > 128 || pw > 128; }
 
@@ -297,13 +300,13 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
   // samples [off, off + nplanes / K) of the code workspace
   cx<T>* const Zh = (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf;
   cx<T>* const S = (cx<T>*)c->S + (size_t)off * c->K * c->Pf;
-  cx<T>* const Yb = c->big ? (cx<T>*)c->Yb + (size_t)off * c->K * c->Pf : nullptr;
+  cx<T>* const Yb = c->tune.two_pass ? (cx<T>*)c->Yb + (size_t)off * c->K * c->Pf : nullptr;
   T* const W = (T*)c->W + (size_t)off * c->K * c->P;
   ProfScope ps(c, OCSC_KC_CODEPLANE);
   const cx<T>* tH = (const cx<T>*)c->twH;
   const cx<T>* tW = (const cx<T>*)c->twW;
   const T kappa = (T)(c->lam / c->rho);
-  if (c->big) {
+  if (c->tune.two_pass) {
     // column inverse of Zh into Y, row pass (U-step, dual, rows of F(U - W)) into S, column pass on S
     bool done = false;
     switch (c->Ph * 1000 + c->Pw) {
@@ -312,6 +315,7 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
     done = big_code_plane<T, A, B>(c, Zh, Yb, W, S, Uout, nplanes, kappa, first, last); \
     break;
       OCSC_BIG_CASES(X)
+      OCSC_TWO_PASS_SMALL(X)
 #undef X
       default:
         break;
@@ -1133,6 +1137,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   c->tune.col_bytes = 128;
   c->tune.row_block = BIG_RB;
   c->tune.chunk_samples = 0;
+  c->tune.two_pass = c->big ? 1 : 0;
   c->chol = (o.flags & OCSC_FLAG_CHOLESKY) != 0;
   c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0 || c->chol;
   c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
@@ -1438,7 +1443,22 @@ bool tuning_valid(const ocsc_ctx* c, const ocsc_tuning& t) {
   const bool rb = t.row_block == 4 || t.row_block == 8 || t.row_block == 16;
   const bool ch = t.chunk_samples == 0 || t.chunk_samples == 1 || t.chunk_samples == 2 || t.chunk_samples == 4 ||
                   t.chunk_samples == 8 || t.chunk_samples == 16;
-  return pt && zf && sb && cb && rb && ch;
+  const bool tp = c->big ? t.two_pass == 1 : (t.two_pass == 0 || (t.two_pass == 1 && two_pass_capable(c->Ph, c->Pw)));
+  return pt && zf && sb && cb && rb && ch && tp;
+}
+
+// The column-pass output of the two-pass code-plane step, allocated when a
+// one-pass grid first selects that step.
+int ensure_column_buffer(ocsc_ctx* c) {
+  if (c->Yb) return OCSC_OK;
+  const size_t bytes = (size_t)c->maxB * c->K * c->Pf * 2 * c->sr;
+  hipError_t e = hipMalloc(&c->Yb, bytes);
+  if (e != hipSuccess) {
+    c->Yb = nullptr;
+    (void)hipGetLastError();
+    return fail(c, OCSC_E_OOM, std::string("column buffer: ") + hipGetErrorString(e));
+  }
+  return OCSC_OK;
 }
 
 struct EventPair {
@@ -1501,24 +1521,33 @@ int autotune_t(ocsc_ctx* c, int B, double* best_ms) {
     if (rc) break;
   }
   c->tune = start;
-  // plane kernel: workgroup size (one-pass grids) or column block x row block (two-pass grids)
-  for (int nt : {256, 512, 1024}) {
-    for (int cby : {128, 256, 512}) {
-      for (int rb : {4, 8, 16}) {
-        if (rc) break;
-        if (!c->big && (cby != start.col_bytes || rb != start.row_block)) continue;
-        c->tune.plane_threads = nt;
-        c->tune.col_bytes = cby;
-        c->tune.row_block = rb;
-        if (!tuning_valid(c, c->tune)) continue;
-        double ms = 0;
-        rc = time_launches(c, ev, [&] { return launch_code_plane<T>(c, 0, B * c->K, nullptr, 0, 0); }, REPS, &ms);
-        if (rc) break;
-        if (ms < best_p) {
-          best_p = ms;
-          best.plane_threads = nt;
-          best.col_bytes = cby;
-          best.row_block = rb;
+  // plane step: workgroup size of the one-pass kernel, or column block x row
+  // block of the two-pass kernels (two-pass grids, and 64 x 64 / 128 x 128
+  // grids as an alternative)
+  if (two_pass_capable(c->Ph, c->Pw)) rc = ensure_column_buffer(c);
+  for (int tp = 0; tp < 2 && !rc; ++tp) {
+    for (int nt : {256, 512, 1024}) {
+      for (int cby : {128, 256, 512}) {
+        for (int rb : {4, 8, 16}) {
+          if (rc) break;
+          // a one-pass shape varies the workgroup size only, a two-pass one the blocks only
+          if (tp == 0 && (cby != start.col_bytes || rb != start.row_block)) continue;
+          if (tp == 1 && nt != start.plane_threads) continue;
+          c->tune.two_pass = tp;
+          c->tune.plane_threads = nt;
+          c->tune.col_bytes = cby;
+          c->tune.row_block = rb;
+          if (!tuning_valid(c, c->tune)) continue;
+          double ms = 0;
+          rc = time_launches(c, ev, [&] { return launch_code_plane<T>(c, 0, B * c->K, nullptr, 0, 0); }, REPS, &ms);
+          if (rc) break;
+          if (ms < best_p) {
+            best_p = ms;
+            best.two_pass = tp;
+            best.plane_threads = nt;
+            best.col_bytes = cby;
+            best.row_block = rb;
+          }
         }
       }
     }
@@ -1635,6 +1664,10 @@ int ocsc_set_tuning(ocsc_ctx* c, const ocsc_tuning* t) {
   if (!c) return OCSC_E_INVALID_ARG;
   if (!t) return fail(c, OCSC_E_INVALID_ARG, "tuning is NULL");
   if (!tuning_valid(c, *t)) return fail(c, OCSC_E_INVALID_ARG, "unsupported launch shape");
+  if (t->two_pass) {
+    const int rc = ensure_column_buffer(c);
+    if (rc) return rc;
+  }
   c->tune = *t;
   return OCSC_OK;
 }

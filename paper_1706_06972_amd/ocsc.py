@@ -68,6 +68,7 @@ class OcscTuning(ctypes.Structure):
         ("col_bytes", ctypes.c_int32),
         ("row_block", ctypes.c_int32),
         ("chunk_samples", ctypes.c_int32),
+        ("two_pass", ctypes.c_int32),
     ]
 
 
@@ -264,7 +265,8 @@ def ocsc_graph_destroy(h) -> None:
     _check(None, load().ocsc_graph_destroy(h))
 
 
-TUNING_FIELDS = ("plane_threads", "zstep_freqs", "zstep_samples", "col_bytes", "row_block", "chunk_samples")
+TUNING_FIELDS = ("plane_threads", "zstep_freqs", "zstep_samples", "col_bytes", "row_block", "chunk_samples",
+                 "two_pass")
 
 
 def ocsc_get_tuning(ctx) -> dict:

@@ -31,17 +31,21 @@ def shapes(ph, pw):
     """Every valid shape: Z-step tiles x (workgroup sizes, one-pass grids, or
     column block x row block, two-pass grids)."""
     z = list(itertools.product((16, 32, 64), (1, 2, 4)))
+    two = [(256, cb, rb, 1) for cb in (128, 256, 512) for rb in (4, 8, 16) if ph * cb <= 131072]
     if max(ph, pw) <= 128:
-        planes = [(nt, 128, 8) for nt in (256, 512, 1024) if nt * 4 <= ph * pw]
+        planes = [(nt, 128, 8, 0) for nt in (256, 512, 1024) if nt * 4 <= ph * pw]
+        if (ph, pw) in ((64, 64), (128, 128)):
+            planes += two
     else:
-        planes = [(256, cb, rb) for cb in (128, 256, 512) for rb in (4, 8, 16) if ph * cb <= 131072]
+        planes = two
     # sample groups of 0 (whole batch), 1 and 2 in turn (the batch has 3 samples)
     return [dict(plane_threads=nt, zstep_freqs=zf, zstep_samples=sb, col_bytes=cb, row_block=rb,
-                 chunk_samples=(0, 1, 2)[i % 3])
-            for i, ((nt, cb, rb), (zf, sb)) in enumerate(itertools.product(planes, z))]
+                 chunk_samples=(0, 1, 2)[i % 3], two_pass=tp)
+            for i, ((nt, cb, rb, tp), (zf, sb)) in enumerate(itertools.product(planes, z))]
 
 
 @pytest.mark.parametrize("prec,ph,pw,K", [("f32", 128, 128, 20), ("f64", 64, 64, 16), ("f32", 32, 64, 40),
+                                          ("f32", 64, 64, 5),
                                           ("f32", 256, 256, 6), ("f64", 128, 128, 3), ("f64", 256, 512, 3),
                                           ("f32", 512, 512, 2)])
 def test_every_shape_gives_the_same_bits(prec, ph, pw, K):
@@ -73,14 +77,16 @@ def test_invalid_shapes_are_refused():
     big = OCSC(4, 5, 5, 256, 256, 0.5, 1.0, precision="f32")
     for g, bad in ((small, dict(plane_threads=512)), (small, dict(plane_threads=128)), (small, dict(zstep_freqs=8)),
                    (small, dict(zstep_samples=3)), (big, dict(plane_threads=1024)), (small, dict(col_bytes=64)),
-                   (small, dict(row_block=2)), (big, dict(row_block=32)), (small, dict(chunk_samples=3))):
+                   (small, dict(row_block=2)), (big, dict(row_block=32)), (small, dict(chunk_samples=3)),
+                   (small, dict(two_pass=1)), (big, dict(two_pass=0))):
         before = g.tuning
         with pytest.raises(L.OcscError) as e:
             g.set_tuning(**bad)
         assert e.value.status == L.OCSC_E_INVALID_ARG
         assert g.tuning == before
     assert small.tuning == dict(plane_threads=256, zstep_freqs=16, zstep_samples=1, col_bytes=128, row_block=8,
-                                chunk_samples=0)
+                                chunk_samples=0, two_pass=0)
+    assert big.tuning["two_pass"] == 1
     big512 = OCSC(2, 5, 5, 512, 512, 0.5, 1.0, precision="f32")
     with pytest.raises(L.OcscError):
         big512.set_tuning(col_bytes=512)   # 512 rows x 512 bytes exceed the column workgroup's LDS
