@@ -96,7 +96,7 @@ def oracle_baseline(wl, n_steps: int):
             "seconds": dt, "host_cpus": os.cpu_count()}
 
 
-def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2, cholesky: bool = False) -> dict:
+def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2, cholesky: bool = False, K=None) -> dict:
     """Minibatch form: B samples coded against one dictionary, folded in index
     order, one DictOCSC per minibatch (same kernels, same precision).  With
     cholesky: the precision form (history on the BF16 matrix cores, C from an
@@ -107,9 +107,10 @@ def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2, cholesky:
     n_img = xs.shape[0]
     reps = (B + n_img - 1) // n_img
     pool = torch.cat([xs] * reps, 0)[:B].contiguous()
-    g = L.OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
+    K = K or wl.K
+    g = L.OCSC(K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=wl.iters_code,
                iters_dict=wl.iters_dict, max_batch=B, precision="f32", cholesky=cholesky, device=dev)
-    g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
+    g.set_dictionary(synth.initial_dictionary(K, wl.filt_h, wl.filt_w, wl.seed))
     shape, _ = g.autotune(B)
 
     def step():
@@ -134,7 +135,7 @@ def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2, cholesky:
     L.ocsc_profile_enable(g.ctx, [])
     del g
     torch.cuda.synchronize()
-    return {"batch": B, "value": B * steps / dt, "unit": "images/s", "ms_per_step": 1000.0 * dt / steps,
+    return {"batch": B, "K": K, "value": B * steps / dt, "unit": "images/s", "ms_per_step": 1000.0 * dt / steps,
             "steps": steps, "warmup": warmup, "launch_shape": shape,
             "form": ("precision form: BF16 matrix-core history + FP64 Cholesky inverse, FP32 code"
                      if cholesky else "minibatch Sherman-Morrison, FP32"),
@@ -455,6 +456,9 @@ def main():
     out["graph"] = graph_run(wl, xs, args.steps, shape=tuned)
     out["batched"] = batched_run(wl, args.batch, xs, dev) if args.batch > 1 else None
     out["precision"] = batched_run(wl, args.batch, xs, dev, cholesky=True) if args.batch > 1 else None
+    # the precision form at K=256 (same grid and minibatch; C from block Cholesky inverses)
+    out["precision_k256"] = (batched_run(wl, args.batch, xs, dev, steps=4, warmup=1, cholesky=True, K=256)
+                             if args.batch > 1 else None)
     out["coding"] = coding_run(dev) if args.coding else None
     out["grouped"] = grouped_run(dev) if args.coding else None
     out["copy_ceiling"] = copy_ceiling(dev)

@@ -20,27 +20,31 @@ __device__ __forceinline__ v4f mfma_bf16(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// One workgroup (4 waves) per frequency p.  Zt[(p * ldt + b) * K + k] holds
-// the nb pending code spectra frequency-major; xh[b * Pf + p] the sample
-// spectra.  H_p (R-form, rows of pitch K + 1 at Hm + p * fs) and G[k][p] are
-// updated in place.  The product tiles on and above the diagonal are spread
-// over the waves; operand layout of v_mfma_f32_16x16x32_bf16: A[i][8g..8g+7]
-// in lane i + 16 g, B[8g..8g+7][j] in lane j + 16 g, D[i][j] in lane
-// j + 16 (i / 4), register i % 4.
-template <int KP>
-__global__ __launch_bounds__(256) void k_herk_bf16(const float2* __restrict__ Zt, int ldt, int nb,
-                                                  const float2* __restrict__ xh, int Pf, float* __restrict__ Hm,
-                                                  int fs, float2* __restrict__ G, int K) {
+// NW waves per workgroup, NSPLIT workgroups per frequency p (blockIdx.x = p,
+// blockIdx.y = share of the tiles).  Zt[(p * ldt + b) * K + k] holds the nb
+// pending code spectra frequency-major; xh[b * Pf + p] the sample spectra.
+// H_p (R-form, rows of pitch K + 1 at Hm + p * fs) and G[k][p] are updated in
+// place.  The product tiles on and above the diagonal are spread over the
+// workgroups and waves (tile = y + NSPLIT (wave + NW tt)); operand layout of
+// v_mfma_f32_16x16x32_bf16: A[i][8g..8g+7] in lane i + 16 g,
+// B[8g..8g+7][j] in lane j + 16 g, D[i][j] in lane j + 16 (i / 4),
+// register i % 4.
+template <int KP, int NW, int NSPLIT>
+__global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict__ Zt, int ldt, int nb,
+                                                      const float2* __restrict__ xh, int Pf, float* __restrict__ Hm,
+                                                      int fs, float2* __restrict__ G, int K) {
+  constexpr int NT = 64 * NW;
   constexpr int NTD = KP / 16;                    // tiles per dimension
   constexpr int NTILE = NTD * (NTD + 1) / 2;      // tiles on or above the diagonal
-  constexpr int TPW = (NTILE + 3) / 4;            // tiles per wave
+  constexpr int TPW = (NTILE + NW * NSPLIT - 1) / (NW * NSPLIT);   // tiles per wave
   __shared__ __align__(16) __bf16 zrh[KP * HERK_LD], zrl[KP * HERK_LD], zih[KP * HERK_LD], zil[KP * HERK_LD];
-  const int p = blockIdx.x;
+  const int p = blockIdx.x, split = blockIdx.y;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  auto tile_of = [&](int tt) { return split + NSPLIT * (wave + NW * tt); };
   int tri[TPW], trj[TPW];
 #pragma unroll
   for (int tt = 0; tt < TPW; ++tt) {   // upper-triangular tile enumeration (row-major)
-    int t = min(wave + 4 * tt, NTILE - 1), i = 0;
+    int t = min(tile_of(tt), NTILE - 1), i = 0;
     while (t >= NTD - i) {
       t -= NTD - i;
       ++i;
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(256) void k_herk_bf16(const float2* __restrict__ Zt
   for (int b0 = 0; b0 < nb; b0 += HERK_B) {
     const int cb = min(HERK_B, nb - b0);
     __syncthreads();   // the previous chunk's operands are no longer read
-    for (int e = tid; e < HERK_B * KP; e += 256) {
+    for (int e = tid; e < HERK_B * KP; e += NT) {
       const int b = e / KP, k = e - b * KP;   // consecutive threads read consecutive k
       float2 z = make_float2(0.f, 0.f);
       if (b < cb && k < K) z = zp[(size_t)(b0 + b) * K + k];
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(256) void k_herk_bf16(const float2* __restrict__ Zt
       zih[o] = ih;
       zil[o] = (__bf16)(z.y - (float)ih);
     }
-    if (tid < K) {   // G_p[k] += sum_b conj(z_bk) x_b (FP32)
+    if (split == 0 && tid < K) {   // G_p[k] += sum_b conj(z_bk) x_b (FP32)
       for (int b = 0; b < cb; ++b) {
         const float2 z = zp[(size_t)(b0 + b) * K + tid];
         const float2 x = xh[(size_t)(b0 + b) * Pf + p];
@@ -78,7 +82,7 @@ __global__ __launch_bounds__(256) void k_herk_bf16(const float2* __restrict__ Zt
     __syncthreads();
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
-      if (wave + 4 * tt >= NTILE) continue;
+      if (tile_of(tt) >= NTILE) continue;
       const int ra = (tri[tt] * 16 + li) * HERK_LD, rb = (trj[tt] * 16 + li) * HERK_LD;
 #pragma unroll
       for (int ks = 0; ks < HERK_B; ks += 32) {
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(256) void k_herk_bf16(const float2* __restrict__ Zt
   const int ld = K + 1;
 #pragma unroll
   for (int tt = 0; tt < TPW; ++tt) {
-    if (wave + 4 * tt >= NTILE) continue;
+    if (tile_of(tt) >= NTILE) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = tri[tt] * 16 + 4 * lg + r, j = trj[tt] * 16 + li;
@@ -122,7 +126,7 @@ __global__ __launch_bounds__(256) void k_herk_bf16(const float2* __restrict__ Zt
       }
     }
   }
-  if (tid < K) {
+  if (split == 0 && tid < K) {
     float2 g = G[(size_t)tid * Pf + p];
     g.x += gr;
     g.y += gi;
@@ -143,13 +147,19 @@ __global__ __launch_bounds__(256) void k_herk_bf16(const float2* __restrict__ Zt
 //      in the R-form of C (rows of pitch K + 1 at Cm + p * fs).
 // Dynamic LDS: (K(K+1)/2 + K) complex doubles.  The trailing loops run on a
 // (CHOL_NT / 16) x 16 thread tiling.
+// FULL = true: the input is A itself, a full Hermitian n x n block in FP64
+// (row pitch CB_N, block p at Ain + p * CB_N * CB_N), and the output is the
+// full inverse in the same layout (the blocks of the K > 128 form below).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int tri_idx(int i, int j) { return i * (i + 1) / 2 + j; }
 
 constexpr int CHOL_NT = 1024;   // threads per workgroup: 16 waves share each step's work
+constexpr int CB_N = 128;       // block size of the K > 128 form
 
-__global__ __launch_bounds__(CHOL_NT) void k_chol_inv(const float* __restrict__ Hm, float* __restrict__ Cm, int K,
-                                                 int fs, double rho_d) {
+template <bool FULL>
+__global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict__ Hm, float* __restrict__ Cm,
+                                                   const double2* __restrict__ Ain, double2* __restrict__ Cout,
+                                                   int K, int fs, double rho_d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double2* L = reinterpret_cast<double2*>(smem_raw);
   double2* col = L + K * (K + 1) / 2;
@@ -157,11 +167,17 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv(const float* __restrict__ 
   constexpr int NY = CHOL_NT / 16;
   const int ty = tid >> 4, tx = tid & 15;
   const int ld = K + 1;
-  const float* R = Hm + (size_t)p * fs;
-  for (int i = ty; i < K; i += NY)
-    for (int j = tx; j <= i; j += 16)
-      L[tri_idx(i, j)] = (i == j) ? make_double2((double)R[i * ld + i] + rho_d, 0.0)
-                                  : make_double2((double)R[j * ld + i], -(double)R[i * ld + j]);
+  if constexpr (FULL) {
+    const double2* A = Ain + (size_t)p * CB_N * CB_N;
+    for (int i = ty; i < K; i += NY)
+      for (int j = tx; j <= i; j += 16) L[tri_idx(i, j)] = A[i * CB_N + j];
+  } else {
+    const float* R = Hm + (size_t)p * fs;
+    for (int i = ty; i < K; i += NY)
+      for (int j = tx; j <= i; j += 16)
+        L[tri_idx(i, j)] = (i == j) ? make_double2((double)R[i * ld + i] + rho_d, 0.0)
+                                    : make_double2((double)R[j * ld + i], -(double)R[i * ld + j]);
+  }
   __syncthreads();
   // 2. Cholesky
   for (int j = 0; j < K; ++j) {
@@ -210,7 +226,6 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv(const float* __restrict__ 
     __syncthreads();
   }
   // 4. C = X^H X (upper triangle and its imaginary parts)
-  float* Co = Cm + (size_t)p * fs;
   for (int i = ty; i < K; i += NY) {
     for (int j = i + tx; j < K; j += 16) {
       double sr = 0.0, si = 0.0;
@@ -219,10 +234,232 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv(const float* __restrict__ 
         sr += a.x * b.x + a.y * b.y;
         si += a.x * b.y - a.y * b.x;
       }
-      Co[i * ld + j] = (float)sr;
-      if (i < j) Co[j * ld + i] = (float)si;
+      if constexpr (FULL) {
+        double2* Co = Cout + (size_t)p * CB_N * CB_N;
+        Co[i * CB_N + j] = make_double2(sr, si);
+        Co[j * CB_N + i] = make_double2(sr, -si);
+      } else {
+        float* Co = Cm + (size_t)p * fs;
+        Co[i * ld + j] = (float)sr;
+        if (i < j) Co[j * ld + i] = (float)si;
+      }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// K > 128 (up to 256): C_p = A^-1 for A = H_p + rho_d I from the FP64 block
+// inverses of two Cholesky factors and a Schur complement.  With the split
+// n1 = 128, n2 = K - 128 and every block stored as a full 128 x 128 FP64
+// matrix (block 2 padded with the identity, so the padding stays out of the
+// top-left K x K result):
+//   P = A11^-1;  B = A21 P;  S = A22 - B A21^H;  Q = S^-1;
+//   C22 = Q;  C21 = -Q B;  C11 = P - B^H C21.
+// S is Hermitian positive definite whenever A is, so both inverses come from
+// Cholesky factors.  Frequencies are processed in chunks; the five blocks of
+// a frequency live at W + (slot * nfreq + f) * 128 * 128.
+// ---------------------------------------------------------------------------
+
+// Blocks A11, A21, A22 (slots 0, 2, 3) of A = H + rho_d I for frequencies
+// [f0, f0 + nf), from H in R-form (FP32, rows of pitch K + 1).
+__global__ __launch_bounds__(256) void k_schur_unpack(const float* __restrict__ Hm, int fs, int K, double rho_d,
+                                                      int f0, int nf, double2* __restrict__ W) {
+  const int f = blockIdx.y;
+  const float* R = Hm + (size_t)(f0 + f) * fs;
+  const int ld = K + 1, n2 = K - CB_N;
+  const size_t bs = (size_t)CB_N * CB_N;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < CB_N * CB_N; e += gridDim.x * 256) {
+    const int i = e / CB_N, j = e - i * CB_N;
+    // entry (a, b) of A for a, b < K
+    auto a_at = [&](int a, int b) -> double2 {
+      if (a == b) return make_double2((double)R[a * ld + a] + rho_d, 0.0);
+      if (a < b) return make_double2((double)R[a * ld + b], (double)R[b * ld + a]);
+      return make_double2((double)R[b * ld + a], -(double)R[a * ld + b]);
+    };
+    W[(0 * (size_t)nf + f) * bs + e] = a_at(i, j);
+    W[(2 * (size_t)nf + f) * bs + e] = (i < n2) ? a_at(CB_N + i, j) : make_double2(0.0, 0.0);
+    W[(3 * (size_t)nf + f) * bs + e] = (i < n2 && j < n2) ? a_at(CB_N + i, CB_N + j)
+                                                          : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+}
+
+// Cout = beta Cin + alpha op(A) op(B) for 128 x 128 complex FP64 blocks, one
+// frequency per blockIdx.z, a 64 x 64 output tile per workgroup (blockIdx.x,
+// blockIdx.y), 256 threads with 4 x 4 outputs each; op = conjugate transpose
+// when HA / HB.  Cin may alias Cout (each output is read, then written, by
+// one thread).
+constexpr int ZG_T = 64, ZG_K = 16;
+
+template <bool HA, bool HB>
+__global__ __launch_bounds__(256) void k_zgemm128(const double2* __restrict__ A, const double2* __restrict__ B,
+                                                  const double2* Cin, double2* Cout, double alpha, double beta) {
+  __shared__ double2 as[ZG_K][ZG_T + 1];   // as[kk][i] = op(A)[i0 + i][k0 + kk]
+  __shared__ double2 bs[ZG_K][ZG_T + 1];   // bs[kk][j] = op(B)[k0 + kk][j0 + j]
+  const size_t off = (size_t)blockIdx.z * CB_N * CB_N;
+  const double2* a = A + off;
+  const double2* b = B + off;
+  const int i0 = blockIdx.y * ZG_T, j0 = blockIdx.x * ZG_T;
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  double2 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < CB_N; k0 += ZG_K) {
+    for (int e = tid; e < ZG_K * ZG_T; e += 256) {
+      // op(A)[i][k]: A[i][k], or conj(A[k][i]); consecutive threads take consecutive memory
+      if (HA) {
+        const int i = e % ZG_T, kk = e / ZG_T;
+        const double2 v = a[(size_t)(k0 + kk) * CB_N + i0 + i];
+        as[kk][i] = make_double2(v.x, -v.y);
+      } else {
+        const int kk = e % ZG_K, i = e / ZG_K;
+        as[kk][i] = a[(size_t)(i0 + i) * CB_N + k0 + kk];
+      }
+      // op(B)[k][j]: B[k][j], or conj(B[j][k])
+      if (HB) {
+        const int kk = e % ZG_K, j = e / ZG_K;
+        const double2 v = b[(size_t)(j0 + j) * CB_N + k0 + kk];
+        bs[kk][j] = make_double2(v.x, -v.y);
+      } else {
+        const int j = e % ZG_T, kk = e / ZG_T;
+        bs[kk][j] = b[(size_t)(k0 + kk) * CB_N + j0 + j];
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < ZG_K; ++kk) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = as[kk][ti + 16 * r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q] = bs[kk][tj + 16 * q];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[r][q].x = fma(av[r].x, bv[q].x, fma(-av[r].y, bv[q].y, acc[r][q].x));
+          acc[r][q].y = fma(av[r].x, bv[q].y, fma(av[r].y, bv[q].x, acc[r][q].y));
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t o = off + (size_t)(i0 + ti + 16 * r) * CB_N + j0 + tj + 16 * q;
+      double2 v = make_double2(alpha * acc[r][q].x, alpha * acc[r][q].y);
+      if (beta != 0.0) {
+        const double2 c = Cin[o];
+        v.x = fma(beta, c.x, v.x);
+        v.y = fma(beta, c.y, v.y);
+      }
+      Cout[o] = v;
+    }
+}
+
+// C_p in R-form (FP32, rows of pitch K + 1) from C11 (slot 1), C21 (slot 2)
+// and C22 (slot 0) of frequencies [f0, f0 + nf).
+__global__ __launch_bounds__(256) void k_schur_pack(const double2* __restrict__ W, int f0, int nf, int K, int fs,
+                                                    float* __restrict__ Cm) {
+  const int f = blockIdx.y;
+  float* Co = Cm + (size_t)(f0 + f) * fs;
+  const int ld = K + 1;
+  const size_t bs = (size_t)CB_N * CB_N;
+  const double2* c11 = W + (1 * (size_t)nf + f) * bs;
+  const double2* c21 = W + (2 * (size_t)nf + f) * bs;
+  const double2* c22 = W + (0 * (size_t)nf + f) * bs;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < K * K; e += gridDim.x * 256) {
+    const int i = e / K, j = e - i * K;   // R[i][j]: Re C_ij (j >= i), Im C_ji (j < i)
+    const int a = j >= i ? i : j, b = j >= i ? j : i;   // C_ab with a <= b
+    double2 v;
+    if (b < CB_N) v = c11[a * CB_N + b];
+    else if (a >= CB_N) v = c22[(a - CB_N) * CB_N + (b - CB_N)];
+    else v = make_double2(c21[(b - CB_N) * CB_N + a].x, -c21[(b - CB_N) * CB_N + a].y);   // C_ab = conj(C_ba)
+    Co[i * ld + j] = (float)(j >= i ? v.x : v.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// D-step d_p = C_p r_p (eq. sub_d_sol, column form) for K > 128, where C_p
+// (R-form, FP32, K (K + 1) reals) does not fit in LDS: one workgroup of 256
+// threads per frequency; C_p passes through LDS in strips of 16 rows read
+// once from HBM.  Each stored value v = R[a][b] serves two outputs:
+//   a < b (v = Re C_ab = Re C_ba):  d_a += v r_b,      d_b += v r_a;
+//   a > b (v = Im C_ba = -Im C_ab): d_a += -i v r_b,   d_b += i v r_a;
+//   a = b:                          d_a += v r_a.
+// The column role (output b) is one thread's running sum; the row role
+// (output a) is summed by 16 lanes and reduced by shuffles.  rhs and d are
+// complex [K][Pf].
+// ---------------------------------------------------------------------------
+constexpr int DS_ROWS = 16, DS_PITCH = 260;
+
+__global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ Cm, int fs, int K, int Pf,
+                                                      const float2* __restrict__ rhs, float2* __restrict__ dout) {
+  __shared__ float strip[DS_ROWS * DS_PITCH];
+  __shared__ float2 rv[256], drow[256];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int ld = K + 1;
+  const float* R = Cm + (size_t)p * fs;
+  if (t < K) {
+    rv[t] = rhs[(size_t)t * Pf + p];
+    drow[t] = make_float2(0.f, 0.f);
+  }
+  float2 dc = make_float2(0.f, 0.f);
+  const int rr = t >> 4, q = t & 15;
+  __syncthreads();
+  for (int a0 = 0; a0 < K; a0 += DS_ROWS) {
+    const int nr = min(DS_ROWS, K - a0);
+    for (int e = t; e < nr * K; e += 256) {
+      const int r = e / K, cc = e - r * K;
+      strip[r * DS_PITCH + cc] = R[(size_t)(a0 + r) * ld + cc];
+    }
+    __syncthreads();
+    if (t < K) {   // column role: output t
+      for (int r = 0; r < nr; ++r) {
+        const int a = a0 + r;
+        const float v = strip[r * DS_PITCH + t];
+        const float2 ra = rv[a];
+        if (a <= t) {
+          dc.x = fma(v, ra.x, dc.x);
+          dc.y = fma(v, ra.y, dc.y);
+        } else {
+          dc.x = fma(-v, ra.y, dc.x);
+          dc.y = fma(v, ra.x, dc.y);
+        }
+      }
+    }
+    float2 sum = make_float2(0.f, 0.f);   // row role: output a0 + rr, columns q, q + 16, ...
+    if (rr < nr) {
+      const int a = a0 + rr;
+      for (int b = q; b < K; b += 16) {
+        if (b == a) continue;
+        const float v = strip[rr * DS_PITCH + b];
+        const float2 rb = rv[b];
+        if (a < b) {
+          sum.x = fma(v, rb.x, sum.x);
+          sum.y = fma(v, rb.y, sum.y);
+        } else {
+          sum.x = fma(v, rb.y, sum.x);
+          sum.y = fma(-v, rb.x, sum.y);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+      sum.x += __shfl_xor(sum.x, off, 16);
+      sum.y += __shfl_xor(sum.y, off, 16);
+    }
+    if (rr < nr && q == 0) {
+      float2 d = drow[a0 + rr];
+      d.x += sum.x;
+      d.y += sum.y;
+      drow[a0 + rr] = d;
+    }
+    __syncthreads();   // the strip is overwritten next
+  }
+  if (t < K) dout[(size_t)t * Pf + p] = make_float2(dc.x + drow[t].x, dc.y + drow[t].y);
 }
 
 }  // namespace ocsc

@@ -51,6 +51,9 @@ struct ocsc_ctx {
   bool big = false;           // two-pass plane transforms (a side above 128)
   bool keep_hist = false;     // OCSC_FLAG_KEEP_HISTORY (implied by OCSC_FLAG_CHOLESKY)
   bool chol = false;          // OCSC_FLAG_CHOLESKY: matrix-core history, C from an FP64 Cholesky
+  bool dstream = false;       // K > 128 (Cholesky form): C_p streamed through LDS by k_dstep_stream
+  int chol_chunk = 0;         // K > 128: frequencies per Schur-complement chunk
+  void* Wchol = nullptr;      // K > 128: five 128 x 128 FP64 blocks per frequency of a chunk
   bool warm = false;          // OCSC_FLAG_WARM_START
   ocsc_tuning tune{};         // launch shapes of the code update (ocsc_set_tuning / ocsc_autotune)
   // runtime
@@ -418,6 +421,17 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
   // in the Infinity Cache at the head of the next
   const int reverse = (int)(c->sweep_count & 1u);
   c->sweep_count++;
+  if (c->dstream) {
+    // K > 128 (Cholesky form, no fold): C_p streamed through LDS
+    if (nfold || !dout) return fail(c, OCSC_E_STATE, "internal: no history fold in the K > 128 form");
+    if constexpr (std::is_same<T, float>::value) {
+      hipLaunchKernelGGL(k_dstep_stream, dim3(c->Pf), dim3(256), 0, c->stream, (const float*)c->Cm, c->fs, c->K,
+                         c->Pf, (const float2*)rhs, (float2*)dout);
+      LAUNCHED(c);
+      return OCSC_OK;
+    }
+    return fail(c, OCSC_E_UNSUPPORTED, "the K > 128 form is FP32");
+  }
   const size_t smem = (dout && nfold == 0) ? c->plain_smem : c->sweep_smem;
 #define OCSC_SWEEP(KT, FPB)                                                                                  \
   hipLaunchKernelGGL((k_dict_sweep<T, KT, FPB>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,               \
@@ -862,18 +876,58 @@ int chol_history(ocsc_ctx* c, int B) {
   switch (KP) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_herk_bf16<N>), dim3(c->Pf), dim3(256), 0, c->stream, (const float2*)c->Zt, c->maxB, B, \
-                       (const float2*)c->xh, c->Pf, (float*)c->Hm, c->fs, (float2*)c->G, c->K);               \
+    hipLaunchKernelGGL((k_herk_bf16<N, 4, 1>), dim3(c->Pf, 1), dim3(256), 0, c->stream, (const float2*)c->Zt,    \
+                       c->maxB, B, (const float2*)c->xh, c->Pf, (float*)c->Hm, c->fs, (float2*)c->G, c->K);     \
     break;
     X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128)
 #undef X
+#define X(N)                                                                                                  \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL((k_herk_bf16<N, 16, 2>), dim3(c->Pf, 2), dim3(1024), 0, c->stream, (const float2*)c->Zt, \
+                       c->maxB, B, (const float2*)c->xh, c->Pf, (float*)c->Hm, c->fs, (float2*)c->G, c->K);     \
+    break;
+    X(144) X(160) X(176) X(192) X(208) X(224) X(240) X(256)
+#undef X
     default:
-      return fail(c, OCSC_E_UNSUPPORTED, "the Cholesky form needs K <= 128");
+      return fail(c, OCSC_E_UNSUPPORTED, "the Cholesky form needs K <= 256");
   }
   LAUNCHED(c);
-  hipLaunchKernelGGL(k_chol_inv, dim3(c->Pf), dim3(CHOL_NT), chol_lds(c->K), c->stream, (const float*)c->Hm,
-                     (float*)c->Cm, c->K, c->fs, c->rho_d);
-  LAUNCHED(c);
+  if (!c->dstream) {
+    hipLaunchKernelGGL((k_chol_inv_t<false>), dim3(c->Pf), dim3(CHOL_NT), chol_lds(c->K), c->stream,
+                       (const float*)c->Hm, (float*)c->Cm, (const double2*)nullptr, (double2*)nullptr, c->K, c->fs,
+                       c->rho_d);
+    LAUNCHED(c);
+    return OCSC_OK;
+  }
+  // K > 128: block inverses and a Schur complement, chunk by chunk of frequencies
+  double2* W = (double2*)c->Wchol;
+  for (int f0 = 0; f0 < c->Pf; f0 += c->chol_chunk) {
+    const int nf = std::min(c->chol_chunk, c->Pf - f0);
+    const size_t bs = (size_t)CB_N * CB_N;
+    double2* s0 = W;
+    double2* s1 = W + 1 * (size_t)nf * bs;
+    double2* s2 = W + 2 * (size_t)nf * bs;
+    double2* s3 = W + 3 * (size_t)nf * bs;
+    double2* s4 = W + 4 * (size_t)nf * bs;
+    const dim3 g(2, 2, nf);
+    hipLaunchKernelGGL(k_schur_unpack, dim3(16, nf), dim3(256), 0, c->stream, (const float*)c->Hm, c->fs, c->K,
+                       c->rho_d, f0, nf, W);
+    hipLaunchKernelGGL((k_chol_inv_t<true>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream, (const float*)nullptr,
+                       (float*)nullptr, (const double2*)s0, s1, CB_N, 0, 0.0);                        // P = A11^-1
+    hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s2,
+                       (const double2*)s1, (const double2*)nullptr, s4, 1.0, 0.0);                   // B = A21 P
+    hipLaunchKernelGGL((k_zgemm128<false, true>), g, dim3(256), 0, c->stream, (const double2*)s4,
+                       (const double2*)s2, (const double2*)s3, s3, -1.0, 1.0);                       // S = A22 - B A21^H
+    hipLaunchKernelGGL((k_chol_inv_t<true>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream, (const float*)nullptr,
+                       (float*)nullptr, (const double2*)s3, s0, CB_N, 0, 0.0);                        // Q = S^-1
+    hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s0,
+                       (const double2*)s4, (const double2*)nullptr, s2, -1.0, 0.0);                  // C21 = -Q B
+    hipLaunchKernelGGL((k_zgemm128<true, false>), g, dim3(256), 0, c->stream, (const double2*)s4,
+                       (const double2*)s2, (const double2*)s1, s1, -1.0, 1.0);                       // C11 = P - B^H C21
+    hipLaunchKernelGGL(k_schur_pack, dim3(32, nf), dim3(256), 0, c->stream, (const double2*)W, f0, nf, c->K, c->fs,
+                       (float*)c->Cm);
+    LAUNCHED(c);
+  }
   return OCSC_OK;
 }
 
@@ -972,7 +1026,7 @@ void free_all(ocsc_ctx* c) {
   void** bufs[] = {&c->xh, &c->Dh, &c->gam, &c->S,    &c->Zh,   &c->W,      &c->G,
                    &c->Cm, &c->d,  &c->Th,  &c->rhs,  &c->V,    &c->apart, &c->twH, &c->twW,
                    &c->xh_obj, &c->Hm, &c->Ubuf, &c->Dv, &c->Dexp, (void**)&c->pend, (void**)&c->hacc,
-                   (void**)&c->dpart, (void**)&c->dres, &c->Yb, &c->Zt};
+                   (void**)&c->dpart, (void**)&c->dres, &c->Yb, &c->Zt, &c->Wchol};
   for (void** b : bufs)
     if (*b) {
       (void)hipFree(*b);
@@ -1075,8 +1129,10 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   if (o.flags & ~(OCSC_FLAG_OWN_STREAM | OCSC_FLAG_KEEP_HISTORY | OCSC_FLAG_WARM_START | OCSC_FLAG_CHOLESKY))
     return fail(nullptr, OCSC_E_INVALID_ARG, "unknown bits in opts->flags");
   if ((o.flags & OCSC_FLAG_CHOLESKY) &&
-      (o.precision != OCSC_FP32 || K > 128 || (o.flags & OCSC_FLAG_WARM_START)))
-    return fail(nullptr, OCSC_E_UNSUPPORTED, "the Cholesky form needs an FP32 context, K <= 128 and a cold start");
+      (o.precision != OCSC_FP32 || K > 256 || (o.flags & OCSC_FLAG_WARM_START)))
+    return fail(nullptr, OCSC_E_UNSUPPORTED, "the Cholesky form needs an FP32 context, K <= 256 and a cold start");
+  // K > 128 runs only in the Cholesky form: its D-step streams C_p instead of holding it in LDS
+  const bool dstream = (o.flags & OCSC_FLAG_CHOLESKY) && K > 128;
   if (!std::isfinite(o.rho_dict)) return fail(nullptr, OCSC_E_INVALID_ARG, "rho_dict must be finite");
   if (big_grid(pad_h, pad_w) && !((pad_h == 256 || pad_h == 512) && (pad_w == 256 || pad_w == 512)))
     return fail(nullptr, OCSC_E_UNSUPPORTED,
@@ -1093,9 +1149,10 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   auto sweep_bytes = [&](int f) { return sweep_lds_bytes(K, f, fs, (int)sr, sweep_nvm_for(K, f, sr)); };
   const size_t max_lds = 160 * 1024 - 1024;
   const size_t max_slot = (size_t)256 * SWEEP_MAXV * 16;
-  if (sweep_bytes(1) > max_lds || (size_t)fs * sr > max_slot ||
-      sweep_plain_lds_bytes(K, 1, fs, (int)sr, sweep_nvm_for(K, 1, sr), 1) > max_lds)
-    return fail(nullptr, OCSC_E_UNSUPPORTED, "K too large for the LDS-resident D-step of this precision");
+  if (!dstream && (sweep_bytes(1) > max_lds || (size_t)fs * sr > max_slot ||
+                   sweep_plain_lds_bytes(K, 1, fs, (int)sr, sweep_nvm_for(K, 1, sr), 1) > max_lds))
+    return fail(nullptr, OCSC_E_UNSUPPORTED,
+                "K too large for the LDS-resident D-step of this precision (K > 128 needs the Cholesky form)");
   while (fpb > 1 && (sweep_bytes(fpb) > 64 * 1024 || (size_t)fpb * fs * sr > max_slot)) fpb /= 2;
 
   ocsc_ctx* c = new (std::nothrow) ocsc_ctx();
@@ -1139,6 +1196,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   c->tune.chunk_samples = 0;
   c->tune.two_pass = c->big ? 1 : 0;
   c->chol = (o.flags & OCSC_FLAG_CHOLESKY) != 0;
+  c->dstream = dstream;
+  c->chol_chunk = dstream ? std::min(c->Pf, 2048) : 0;
   c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0 || c->chol;
   c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
   c->vstep_fused = sr == 8 ? vstep_fused_ok<double>(pad_h, pad_w, filt_h, filt_w)
@@ -1160,11 +1219,13 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     c->own_stream = true;
   }
-  if (c->chol && chol_lds(K) > 64 * 1024) {
-    e = hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds(K));
+  if (c->chol) {
+    const int kb = c->dstream ? CB_N : K;   // the factorised block size
+    const void* fn = c->dstream ? (const void*)k_chol_inv_t<true> : (const void*)k_chol_inv_t<false>;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds(kb));
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
-  if (std::max(c->sweep_smem, c->plain_smem) > 64 * 1024) {
+  if (!c->dstream && std::max(c->sweep_smem, c->plain_smem) > 64 * 1024) {
     const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>
 #define X(T, KT, FPB) , (const void*)k_dict_sweep<T, KT, FPB>
                          OCSC_SWEEP_SPECS(X)
@@ -1198,7 +1259,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
       {&c->Ubuf, c->keep_hist ? B * K_ * c->P * sr : 0},
       {(void**)&c->pend, c->keep_hist ? 2 * B * 64 * sizeof(double) : 0},
       {&c->Yb, c->big ? B * K_ * Pf * sc : 0},
-      {&c->Zt, c->chol ? Pf * B * K_ * sc : 0}};
+      {&c->Zt, c->chol ? Pf * B * K_ * sc : 0},
+      {&c->Wchol, c->dstream ? (size_t)5 * c->chol_chunk * CB_N * CB_N * 16 : 0}};
   for (auto& a : allocs) {
     if (a.n == 0) continue;
     e = hipMalloc(a.p, a.n);

@@ -65,11 +65,16 @@ def test_init_rejects_bad_opts():
 
 
 def test_cholesky_form_limits():
-    for prec, K, extra in ((B.OCSC_FP64, 16, 0), (B.OCSC_FP32, 200, 0), (B.OCSC_FP32, 16, B.OCSC_FLAG_WARM_START)):
+    for prec, K, extra in ((B.OCSC_FP64, 16, 0), (B.OCSC_FP32, 257, 0), (B.OCSC_FP32, 16, B.OCSC_FLAG_WARM_START)):
         o = B.ocsc_default_opts()
         o.precision, o.flags = prec, B.OCSC_FLAG_CHOLESKY | extra
         rc, _, msg = init_rc(K=K, opts=ctypes.byref(o))
         assert rc == B.OCSC_E_UNSUPPORTED and "Cholesky" in msg
+    # K > 128 is only offered in the Cholesky form (its D-step streams C_p)
+    o = B.ocsc_default_opts()
+    o.precision = B.OCSC_FP32
+    rc, _, msg = init_rc(K=200, opts=ctypes.byref(o))
+    assert rc == B.OCSC_E_UNSUPPORTED and "Cholesky form" in msg
 
 
 def test_unsupported_sizes_are_reported():

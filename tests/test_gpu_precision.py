@@ -1,7 +1,8 @@
 """Precision form (OCSC_FLAG_CHOLESKY): the minibatch history on the BF16
 matrix cores with a split-precision correction, C recomputed from an FP64
-Cholesky per frequency; FP32 code ADMM.  Against the FP64 oracle every
-quantity must be within 1e-3 (norm-wise relative); the errors are printed.
+Cholesky per frequency (for K > 128 through two 128-blocks and a Schur
+complement); FP32 code ADMM.  Against the FP64 oracle every quantity must be
+within 1e-3 (norm-wise relative); the errors are printed.
 """
 import numpy as np
 import pytest
@@ -21,11 +22,12 @@ def images(n, ph, K_true, seed):
     return synth.images(wl, range(n))
 
 
-@pytest.mark.parametrize("K,B,batches", [(16, 8, 2), (100, 6, 2), (40, 70, 1)])
-def test_cholesky_form_matches_oracle(K, B, batches):
-    say(f"case precision form K={K} B={B}")
+@pytest.mark.parametrize("K,B,batches,n", [(16, 8, 2, 64), (100, 6, 2, 64), (40, 70, 1, 64), (256, 4, 2, 32),
+                                           (200, 3, 1, 32), (129, 2, 1, 32)])
+def test_cholesky_form_matches_oracle(K, B, batches, n):
+    """K > 128 takes the block (Schur complement) inverse and the streaming D-step."""
+    say(f"case precision form K={K} B={B} grid {n}")
     from paper_1706_06972_amd.ocsc import OCSC
-    n = 64
     xs = images(B * batches, n, 16, 11)
     g = OCSC(K, 11, 11, n, n, 1.0, 1.0, precision="f32", max_batch=B, cholesky=True)
     o = O.OCSC(K, 11, 11, n, n, 1.0, 1.0, keep_history=True)
