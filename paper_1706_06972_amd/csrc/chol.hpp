@@ -138,22 +138,35 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
 // C_p = (H_p + rho_d I)^-1 in FP64, one workgroup per frequency, the lower
 // triangle in LDS (packed, element (i, j) at i(i+1)/2 + j):
 //   1. A = H + rho_d I (lower triangle, A_ij = conj(H_ji) for i > j);
-//   2. Cholesky A = L L^H, right-looking: per column j, L_.j = A_.j / sqrt(A_jj),
-//      then the trailing update A_ik -= L_ij conj(L_kj);
-//   3. X = L^-1 in place, right-looking on [L | I]: per step k, row k of X is
-//      B_k. / L_kk, then B_ij -= L_ik X_kj for i > k, j <= k (B starts as I;
-//      column k of L is copied out before its slots take B);
+//   2. Cholesky A = L L^H, right-looking, CHOL_B columns per step;
+//   3. X = L^-1 in place, right-looking on [L | I], CHOL_B rows per step;
 //   4. C = X^H X, C_ij = sum_{k >= max(i, j)} conj(X_ki) X_kj, rounded to FP32
 //      in the R-form of C (rows of pitch K + 1 at Cm + p * fs).
-// Dynamic LDS: (K(K+1)/2 + K) complex doubles.  The trailing loops run on a
-// (CHOL_NT / 16) x 16 thread tiling.
+// Blocking by CHOL_B cuts the barrier phases and the passes over the
+// trailing triangle by CHOL_B; the small diagonal blocks are factorised and
+// inverted redundantly by every thread in registers.
+// Dynamic LDS: (N(N+1)/2 + CHOL_B N + CHOL_B^2) complex doubles, N = K
+// rounded up to CHOL_B.  The trailing updates are flat lists of 2 x 2 tiles
+// shared by all threads, so every step keeps the threads evenly busy.
 // FULL = true: the input is A itself, a full Hermitian n x n block in FP64
 // (row pitch CB_N, block p at Ain + p * CB_N * CB_N), and the output is the
 // full inverse in the same layout (the blocks of the K > 128 form below).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int tri_idx(int i, int j) { return i * (i + 1) / 2 + j; }
 
+// v - a conj(b), v - a b and v + conj(a) b as four fused multiply-adds
+__device__ __forceinline__ double2 zsub_mulc(double2 v, double2 a, double2 b) {
+  return make_double2(fma(-a.x, b.x, fma(-a.y, b.y, v.x)), fma(-a.y, b.x, fma(a.x, b.y, v.y)));
+}
+__device__ __forceinline__ double2 zsub_mul(double2 v, double2 a, double2 b) {
+  return make_double2(fma(-a.x, b.x, fma(a.y, b.y, v.x)), fma(-a.x, b.y, fma(-a.y, b.x, v.y)));
+}
+__device__ __forceinline__ double2 zadd_cmul(double2 v, double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, fma(a.y, b.y, v.x)), fma(a.x, b.y, fma(-a.y, b.x, v.y)));
+}
+
 constexpr int CHOL_NT = 1024;   // threads per workgroup: 16 waves share each step's work
+constexpr int CHOL_B = 4;       // columns (rows) per step of the factorisation (inverse)
 constexpr int CB_N = 128;       // block size of the K > 128 form
 
 template <bool FULL>
@@ -161,87 +174,282 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
                                                    const double2* __restrict__ Ain, double2* __restrict__ Cout,
                                                    int K, int fs, double rho_d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // the factorisation runs on N = K rounded up to CHOL_B, padded with the
+  // identity (which stays outside the top-left K x K of the inverse)
+  const int N = (K + CHOL_B - 1) / CHOL_B * CHOL_B;
   double2* L = reinterpret_cast<double2*>(smem_raw);
-  double2* col = L + K * (K + 1) / 2;
+  double2* cb = L + N * (N + 1) / 2;      // [N][CHOL_B]: the column block being factorised / consumed
+  double2* xdb = cb + N * CHOL_B;        // [CHOL_B][CHOL_B]: factor (step 2) / inverse (step 3) of the diagonal block
   const int p = blockIdx.x, tid = threadIdx.x;
-  constexpr int NY = CHOL_NT / 16;
-  const int ty = tid >> 4, tx = tid & 15;
   const int ld = K + 1;
-  if constexpr (FULL) {
-    const double2* A = Ain + (size_t)p * CB_N * CB_N;
-    for (int i = ty; i < K; i += NY)
-      for (int j = tx; j <= i; j += 16) L[tri_idx(i, j)] = A[i * CB_N + j];
-  } else {
-    const float* R = Hm + (size_t)p * fs;
-    for (int i = ty; i < K; i += NY)
-      for (int j = tx; j <= i; j += 16)
-        L[tri_idx(i, j)] = (i == j) ? make_double2((double)R[i * ld + i] + rho_d, 0.0)
-                                    : make_double2((double)R[j * ld + i], -(double)R[i * ld + j]);
+  for (int e = tid; e < N * (N + 1) / 2; e += CHOL_NT) {
+    int i = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
+    while (tri_idx(i + 1, 0) <= e) ++i;
+    while (tri_idx(i, 0) > e) --i;
+    const int j = e - tri_idx(i, 0);
+    double2 v;
+    if (i >= K) {
+      v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    } else if constexpr (FULL) {
+      v = Ain[(size_t)p * CB_N * CB_N + i * CB_N + j];
+    } else {
+      const float* R = Hm + (size_t)p * fs;
+      v = (i == j) ? make_double2((double)R[i * ld + i] + rho_d, 0.0)
+                   : make_double2((double)R[j * ld + i], -(double)R[i * ld + j]);
+    }
+    L[e] = v;
   }
   __syncthreads();
-  // 2. Cholesky
-  for (int j = 0; j < K; ++j) {
-    const double d = sqrt(L[tri_idx(j, j)].x);
-    const double inv = 1.0 / d;
-    for (int i = j + tid; i < K; i += CHOL_NT) {
-      const double2 v = L[tri_idx(i, j)];
-      col[i] = (i == j) ? make_double2(d, 0.0) : make_double2(v.x * inv, v.y * inv);
+  // 2. Cholesky A = L L^H, CHOL_B columns per step (right-looking):
+  //    the CHOL_B x CHOL_B diagonal factor D is formed by every thread in
+  //    registers; the rows below solve l_i D^H = a_i into cb; then the
+  //    trailing block takes the rank-CHOL_B update A_ik -= sum_c l_ic conj(l_kc).
+  for (int j = 0; j < N; j += CHOL_B) {
+    const int nb = CHOL_B;
+    if (tid < 64) {   // one wave factors the diagonal block D (identical in every lane); lane 0 shares it
+      double2 d[CHOL_B][CHOL_B];
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c)
+#pragma unroll
+        for (int r = 0; r < CHOL_B; ++r) d[r][c] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) {
+        double sdiag = L[tri_idx(j + c, j + c)].x;
+#pragma unroll
+        for (int m = 0; m < c; ++m) sdiag -= d[c][m].x * d[c][m].x + d[c][m].y * d[c][m].y;
+        const double dc = sqrt(sdiag), ic = 1.0 / dc;
+        d[c][c] = make_double2(dc, ic);   // the diagonal is real; its .y carries 1 / d_cc
+#pragma unroll
+        for (int r = c + 1; r < CHOL_B; ++r) {
+          double2 v = L[tri_idx(j + r, j + c)];
+#pragma unroll
+          for (int m = 0; m < c; ++m) v = zsub_mulc(v, d[r][m], d[c][m]);
+          d[r][c] = make_double2(v.x * ic, v.y * ic);
+        }
+      }
+      if (tid == 0)
+#pragma unroll
+        for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+          for (int c = 0; c < CHOL_B; ++c) xdb[r * CHOL_B + c] = d[r][c];
     }
     __syncthreads();
-    for (int i = j + tid; i < K; i += CHOL_NT) L[tri_idx(i, j)] = col[i];
-    for (int i = j + 1 + ty; i < K; i += NY) {
-      const double2 a = col[i];
-      for (int k = j + 1 + tx; k <= i; k += 16) {   // A_ik -= L_ij conj(L_kj)
-        const double2 b = col[k];
-        double2 v = L[tri_idx(i, k)];
-        v.x -= a.x * b.x + a.y * b.y;
-        v.y -= a.y * b.x - a.x * b.y;
-        L[tri_idx(i, k)] = v;
+    double2 d[CHOL_B][CHOL_B];
+    double dinv[CHOL_B];
+#pragma unroll
+    for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) d[r][c] = xdb[r * CHOL_B + c];
+#pragma unroll
+    for (int c = 0; c < CHOL_B; ++c) {
+      dinv[c] = d[c][c].y;
+      d[c][c].y = 0.0;
+    }
+    for (int i = j + nb + tid; i < N; i += CHOL_NT) {
+      double2 l[CHOL_B];
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) {
+        l[c] = make_double2(0.0, 0.0);
+        if (c < nb) {
+          double2 v = L[tri_idx(i, j + c)];
+#pragma unroll
+          for (int m = 0; m < c; ++m) v = zsub_mulc(v, l[m], d[c][m]);
+          l[c] = make_double2(v.x * dinv[c], v.y * dinv[c]);
+        }
+        cb[i * CHOL_B + c] = l[c];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+      for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c)
+          if (r < nb) L[tri_idx(j + r, j + c)] = d[r][c];
+    }
+    for (int i = j + nb + tid; i < N; i += CHOL_NT)
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) L[tri_idx(i, j + c)] = cb[i * CHOL_B + c];
+    {
+      // trailing triangle in 2 x 2 tiles, a flat list over all threads
+      const int j0 = j + nb, t2 = (N - j0) / 2;
+      for (int t = tid; t < t2 * (t2 + 1) / 2; t += CHOL_NT) {
+        int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+        while (tri_idx(ti + 1, 0) <= t) ++ti;
+        while (tri_idx(ti, 0) > t) --ti;
+        const int tk = t - tri_idx(ti, 0);
+        const int i = j0 + 2 * ti, k = j0 + 2 * tk;   // rows i, i+1; columns k, k+1 (k <= i)
+        double2 a[2][CHOL_B], b[2][CHOL_B];
+#pragma unroll
+        for (int c = 0; c < CHOL_B; ++c) {
+          a[0][c] = cb[i * CHOL_B + c];
+          a[1][c] = cb[(i + 1) * CHOL_B + c];
+          b[0][c] = cb[k * CHOL_B + c];
+          b[1][c] = cb[(k + 1) * CHOL_B + c];
+        }
+        const int r0 = tri_idx(i, 0), r1 = tri_idx(i + 1, 0);
+        double2 v00 = L[r0 + k], v10 = L[r1 + k], v11 = L[r1 + k + 1];
+        double2 v01 = (k + 1 <= i) ? L[r0 + k + 1] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < CHOL_B; ++c) {   // A_ik -= sum_c l_ic conj(l_kc)
+          v00 = zsub_mulc(v00, a[0][c], b[0][c]);
+          v01 = zsub_mulc(v01, a[0][c], b[1][c]);
+          v10 = zsub_mulc(v10, a[1][c], b[0][c]);
+          v11 = zsub_mulc(v11, a[1][c], b[1][c]);
+        }
+        L[r0 + k] = v00;
+        L[r1 + k] = v10;
+        L[r1 + k + 1] = v11;
+        if (k + 1 <= i) L[r0 + k + 1] = v01;
       }
     }
     __syncthreads();
   }
-  // 3. X = L^-1 in place
-  for (int k = 0; k < K; ++k) {
-    // X_kk stays in a register until the end of the step: slot (k, k) still
-    // holds L_kk for the threads that read it at the start
-    const double xkk = 1.0 / L[tri_idx(k, k)].x;
-    for (int i = k + 1 + tid; i < K; i += CHOL_NT) col[i] = L[tri_idx(i, k)];   // column k of L
-    for (int j = tid; j < k; j += CHOL_NT) {                                    // row k of X
-      const double2 bkj = L[tri_idx(k, j)];
-      L[tri_idx(k, j)] = make_double2(bkj.x * xkk, bkj.y * xkk);
+  // 3. X = L^-1 in place, CHOL_B rows per step (right-looking on [L | I]):
+  //    B starts as I; per step the diagonal block's inverse Xd (registers of
+  //    every thread, and xdb in LDS) turns rows k.. of B into rows of X, and
+  //    the rows below take B_ij -= sum_c L_i,k+c X_k+c,j.  Slot (i, j) holds L
+  //    until column j is consumed, then B, then X.
+  for (int k = 0; k < N; k += CHOL_B) {
+    const int nb = CHOL_B;
+    if (tid < 64) {   // one wave inverts the diagonal block; lane 0 shares Xd
+      double2 xd[CHOL_B][CHOL_B];
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c)
+#pragma unroll
+        for (int r = 0; r < CHOL_B; ++r) xd[r][c] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) {
+        xd[c][c] = make_double2(1.0 / L[tri_idx(k + c, k + c)].x, 0.0);
+#pragma unroll
+        for (int r = c + 1; r < CHOL_B; ++r) {
+          // xd[r][c] = -(sum_{m=c}^{r-1} L_{k+r,k+m} xd[m][c]) / L_{k+r,k+r}
+          double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int m = c; m < r; ++m) v = zsub_mul(v, L[tri_idx(k + r, k + m)], xd[m][c]);
+          const double ir = 1.0 / L[tri_idx(k + r, k + r)].x;
+          xd[r][c] = make_double2(v.x * ir, v.y * ir);
+        }
+      }
+      if (tid == 0)
+#pragma unroll
+        for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+          for (int c = 0; c < CHOL_B; ++c) xdb[r * CHOL_B + c] = xd[r][c];
     }
+    for (int i = k + nb + tid; i < N; i += CHOL_NT)
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) cb[i * CHOL_B + c] = L[tri_idx(i, k + c)];
     __syncthreads();
-    for (int i = k + 1 + ty; i < K; i += NY) {
-      const double2 l = col[i];
-      for (int j = tx; j <= k; j += 16) {   // B_ij -= L_ik X_kj (B_ik starts at 0)
-        const double2 x = (j == k) ? make_double2(xkk, 0.0) : L[tri_idx(k, j)];
-        double2 v = (j == k) ? make_double2(0.0, 0.0) : L[tri_idx(i, j)];
-        v.x -= l.x * x.x - l.y * x.y;
-        v.y -= l.x * x.y + l.y * x.x;
-        L[tri_idx(i, j)] = v;
+    double2 xd[CHOL_B][CHOL_B];
+#pragma unroll
+    for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) xd[r][c] = xdb[r * CHOL_B + c];
+    for (int jj = tid; jj < k; jj += CHOL_NT) {   // rows k.. of X, columns left of the block
+      double2 bq[CHOL_B];
+#pragma unroll
+      for (int m = 0; m < CHOL_B; ++m) bq[m] = m < nb ? L[tri_idx(k + m, jj)] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = 0; r < CHOL_B; ++r) {
+        if (r < nb) {
+          double2 x = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int m = 0; m <= r; ++m) x = zsub_mul(x, make_double2(-xd[r][m].x, -xd[r][m].y), bq[m]);
+          L[tri_idx(k + r, jj)] = x;
+        }
       }
     }
-    if (tid == 0) L[tri_idx(k, k)] = make_double2(xkk, 0.0);
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+      for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c)
+          if (r < nb) L[tri_idx(k + r, k + c)] = xd[r][c];
+    }
+    {
+      // rows below the block x columns left of its end, in 2 x 2 tiles
+      const int nr = (N - k - nb) / 2, nc = (k + nb) / 2;
+      for (int t = tid; t < nr * nc; t += CHOL_NT) {
+        const int i = k + nb + 2 * (t / nc), jj = 2 * (t % nc);
+        double2 a[2][CHOL_B], x[CHOL_B][2];
+#pragma unroll
+        for (int c = 0; c < CHOL_B; ++c) {
+          a[0][c] = cb[i * CHOL_B + c];
+          a[1][c] = cb[(i + 1) * CHOL_B + c];
+          if (jj < k) {   // X rows k.. (written above), left of the diagonal block
+            x[c][0] = L[tri_idx(k + c, jj)];
+            x[c][1] = L[tri_idx(k + c, jj + 1)];
+          } else {        // inside the diagonal block: X = Xd (zero above its diagonal)
+            x[c][0] = xdb[c * CHOL_B + (jj - k)];
+            x[c][1] = xdb[c * CHOL_B + (jj + 1 - k)];
+          }
+        }
+        const int r0 = tri_idx(i, 0), r1 = tri_idx(i + 1, 0);
+        double2 v[2][2];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            v[rr][q] = jj < k ? L[(rr ? r1 : r0) + jj + q] : make_double2(0.0, 0.0);   // B; new columns start at 0
+#pragma unroll
+        for (int c = 0; c < CHOL_B; ++c)
+#pragma unroll
+          for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) v[rr][q] = zsub_mul(v[rr][q], a[rr][c], x[c][q]);
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) L[(rr ? r1 : r0) + jj + q] = v[rr][q];
+      }
+    }
     __syncthreads();
   }
-  // 4. C = X^H X (upper triangle and its imaginary parts)
-  for (int i = ty; i < K; i += NY) {
-    for (int j = i + tx; j < K; j += 16) {
-      double sr = 0.0, si = 0.0;
-      for (int k = j; k < K; ++k) {
-        const double2 a = L[tri_idx(k, i)], b = L[tri_idx(k, j)];   // conj(X_ki) X_kj
-        sr += a.x * b.x + a.y * b.y;
-        si += a.x * b.y - a.y * b.x;
-      }
-      if constexpr (FULL) {
-        double2* Co = Cout + (size_t)p * CB_N * CB_N;
-        Co[i * CB_N + j] = make_double2(sr, si);
-        Co[j * CB_N + i] = make_double2(sr, -si);
-      } else {
-        float* Co = Cm + (size_t)p * fs;
-        Co[i * ld + j] = (float)sr;
-        if (i < j) Co[j * ld + i] = (float)si;
+  // 4. C = X^H X, C_ij = sum_{m >= j} conj(X_mi) X_mj for i <= j, in 2 x 2
+  //    blocks (four loads for four products per m)
+  auto xat = [&](int m, int cidx) -> double2 {
+    return (cidx <= m && cidx < K) ? L[tri_idx(m, cidx)] : make_double2(0.0, 0.0);
+  };
+  const int n2 = (K + 1) / 2;
+  for (int t = tid; t < n2 * (n2 + 1) / 2; t += CHOL_NT) {
+    int bi = 0, rem = t;
+    while (rem >= n2 - bi) {
+      rem -= n2 - bi;
+      ++bi;
+    }
+    const int bj = bi + rem;
+    const int i0 = 2 * bi, j0 = 2 * bj;
+    double2 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int m = j0; m < K; ++m) {
+      const double2 xi[2] = {xat(m, i0), xat(m, i0 + 1)};
+      const double2 xj[2] = {xat(m, j0), xat(m, j0 + 1)};
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = zadd_cmul(acc[a][b], xi[a], xj[b]);   // + conj(xi) xj
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = i0 + a, jx = j0 + b;
+        if (i >= K || jx >= K || i > jx) continue;
+        const double sr = acc[a][b].x, si = acc[a][b].y;
+        if constexpr (FULL) {
+          double2* Co = Cout + (size_t)p * CB_N * CB_N;
+          Co[i * CB_N + jx] = make_double2(sr, si);
+          Co[jx * CB_N + i] = make_double2(sr, -si);
+        } else {
+          float* Co = Cm + (size_t)p * fs;
+          Co[i * ld + jx] = (float)sr;
+          if (i < jx) Co[jx * ld + i] = (float)si;
+        }
       }
     }
   }

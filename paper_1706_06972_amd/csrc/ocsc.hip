@@ -865,7 +865,10 @@ int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* ou
 
 // Kept history: H_p += sum_b conj(z_bp) z_bp^T and the running sums, at
 // accumulation time (the fold of G and C may still be deferred).
-size_t chol_lds(int K) { return ((size_t)K * (K + 1) / 2 + K) * 16; }
+size_t chol_lds(int K) {
+  const size_t n = (size_t)(K + CHOL_B - 1) / CHOL_B * CHOL_B;   // padded to whole column blocks
+  return (n * (n + 1) / 2 + n * CHOL_B + CHOL_B * CHOL_B) * 16;
+}
 
 // Precision form: H += conj(Z)^T Z and G += conj(Z)^T x on the matrix cores
 // (BF16 split, FP32 accumulation), then C = (H + rho_d I)^-1 by an FP64
