@@ -469,25 +469,41 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
 // ---------------------------------------------------------------------------
 
 // Blocks A11, A21, A22 (slots 0, 2, 3) of A = H + rho_d I for frequencies
-// [f0, f0 + nf), from H in R-form (FP32, rows of pitch K + 1).
+// [f0, f0 + nf), from H in R-form (FP32, rows of pitch K + 1).  Workgroup
+// (blockIdx.x = block * 16 + 32 x 32 tile, blockIdx.y = frequency): the tile
+// of R and its transpose pass through LDS, so both reads are row reads.
+constexpr int SU_T = 32;
+
 __global__ __launch_bounds__(256) void k_schur_unpack(const float* __restrict__ Hm, int fs, int K, double rho_d,
                                                       int f0, int nf, double2* __restrict__ W) {
-  const int f = blockIdx.y;
+  __shared__ float t1[SU_T][SU_T + 1], t2[SU_T][SU_T + 1];   // t1[r][c] = R[a][b], t2[c][r] = R[b][a]
+  const int f = blockIdx.y, blk = blockIdx.x / 16, tile = blockIdx.x % 16;
+  const int slot = blk == 0 ? 0 : (blk == 1 ? 2 : 3);
+  const int abase = blk == 0 ? 0 : CB_N, bbase = blk == 2 ? CB_N : 0;
+  const int a0 = abase + (tile / 4) * SU_T, b0 = bbase + (tile % 4) * SU_T;
   const float* R = Hm + (size_t)(f0 + f) * fs;
-  const int ld = K + 1, n2 = K - CB_N;
-  const size_t bs = (size_t)CB_N * CB_N;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < CB_N * CB_N; e += gridDim.x * 256) {
-    const int i = e / CB_N, j = e - i * CB_N;
-    // entry (a, b) of A for a, b < K
-    auto a_at = [&](int a, int b) -> double2 {
-      if (a == b) return make_double2((double)R[a * ld + a] + rho_d, 0.0);
-      if (a < b) return make_double2((double)R[a * ld + b], (double)R[b * ld + a]);
-      return make_double2((double)R[b * ld + a], -(double)R[a * ld + b]);
-    };
-    W[(0 * (size_t)nf + f) * bs + e] = a_at(i, j);
-    W[(2 * (size_t)nf + f) * bs + e] = (i < n2) ? a_at(CB_N + i, j) : make_double2(0.0, 0.0);
-    W[(3 * (size_t)nf + f) * bs + e] = (i < n2 && j < n2) ? a_at(CB_N + i, CB_N + j)
-                                                          : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  const int ld = K + 1;
+  for (int e = threadIdx.x; e < SU_T * SU_T; e += 256) {
+    const int r = e / SU_T, c = e % SU_T;
+    t1[r][c] = (a0 + r < K && b0 + c < K) ? R[(size_t)(a0 + r) * ld + b0 + c] : 0.f;
+    t2[r][c] = (b0 + r < K && a0 + c < K) ? R[(size_t)(b0 + r) * ld + a0 + c] : 0.f;   // row b0 + r of R
+  }
+  __syncthreads();
+  double2* out = W + ((size_t)slot * nf + f) * CB_N * CB_N;
+  for (int e = threadIdx.x; e < SU_T * SU_T; e += 256) {
+    const int r = e / SU_T, c = e % SU_T;
+    const int a = a0 + r, b = b0 + c;
+    double2 v;
+    if (a >= K || b >= K) {
+      v = make_double2(a == b ? 1.0 : 0.0, 0.0);   // identity padding (block 2 only)
+    } else if (a == b) {
+      v = make_double2((double)t1[r][c] + rho_d, 0.0);
+    } else if (a < b) {
+      v = make_double2((double)t1[r][c], (double)t2[c][r]);    // Re at R[a][b], Im at R[b][a]
+    } else {
+      v = make_double2((double)t2[c][r], -(double)t1[r][c]);   // conj(H_ba)
+    }
+    out[(size_t)(a - abase) * CB_N + (b - bbase)] = v;
   }
 }
 
@@ -568,24 +584,41 @@ __global__ __launch_bounds__(256) void k_zgemm128(const double2* __restrict__ A,
 }
 
 // C_p in R-form (FP32, rows of pitch K + 1) from C11 (slot 1), C21 (slot 2)
-// and C22 (slot 0) of frequencies [f0, f0 + nf).
+// and C22 (slot 0) of frequencies [f0, f0 + nf): R[i][j] = Re C_ij for
+// j >= i, -Im C_ij for j < i.  Workgroup (blockIdx.x = 32 x 32 tile of R,
+// blockIdx.y = frequency); C_ij for i < 128 <= j is conj(C21[j-128][i]),
+// whose tile is transposed through LDS.
 __global__ __launch_bounds__(256) void k_schur_pack(const double2* __restrict__ W, int f0, int nf, int K, int fs,
                                                     float* __restrict__ Cm) {
-  const int f = blockIdx.y;
+  __shared__ double2 tt[SU_T][SU_T + 1];
+  const int f = blockIdx.y, kt = (K + SU_T - 1) / SU_T;
+  const int i0 = (blockIdx.x / kt) * SU_T, j0 = (blockIdx.x % kt) * SU_T;
   float* Co = Cm + (size_t)(f0 + f) * fs;
   const int ld = K + 1;
   const size_t bs = (size_t)CB_N * CB_N;
   const double2* c11 = W + (1 * (size_t)nf + f) * bs;
   const double2* c21 = W + (2 * (size_t)nf + f) * bs;
   const double2* c22 = W + (0 * (size_t)nf + f) * bs;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < K * K; e += gridDim.x * 256) {
-    const int i = e / K, j = e - i * K;   // R[i][j]: Re C_ij (j >= i), Im C_ji (j < i)
-    const int a = j >= i ? i : j, b = j >= i ? j : i;   // C_ab with a <= b
+  if (i0 < CB_N && j0 >= CB_N) {
+    for (int e = threadIdx.x; e < SU_T * SU_T; e += 256) {
+      const int r = e / SU_T, c = e % SU_T;   // row j0 + r of C21, column i0 + c
+      tt[r][c] = (j0 + r < K) ? c21[(size_t)(j0 + r - CB_N) * CB_N + i0 + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < SU_T * SU_T; e += 256) {
+      const int r = e / SU_T, c = e % SU_T, i = i0 + r, j = j0 + c;
+      if (i < K && j < K) Co[i * ld + j] = (float)tt[c][r].x;   // Re C_ij = Re C21[j-128][i]
+    }
+    return;
+  }
+  for (int e = threadIdx.x; e < SU_T * SU_T; e += 256) {
+    const int r = e / SU_T, c = e % SU_T, i = i0 + r, j = j0 + c;
+    if (i >= K || j >= K) continue;
     double2 v;
-    if (b < CB_N) v = c11[a * CB_N + b];
-    else if (a >= CB_N) v = c22[(a - CB_N) * CB_N + (b - CB_N)];
-    else v = make_double2(c21[(b - CB_N) * CB_N + a].x, -c21[(b - CB_N) * CB_N + a].y);   // C_ab = conj(C_ba)
-    Co[i * ld + j] = (float)(j >= i ? v.x : v.y);
+    if (i < CB_N && j < CB_N) v = c11[i * CB_N + j];
+    else if (i >= CB_N && j >= CB_N) v = c22[(i - CB_N) * CB_N + (j - CB_N)];
+    else v = c21[(i - CB_N) * CB_N + j];   // i >= 128 > j
+    Co[i * ld + j] = (float)(j >= i ? v.x : -v.y);
   }
 }
 
@@ -616,14 +649,33 @@ __global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ 
   }
   float2 dc = make_float2(0.f, 0.f);
   const int rr = t >> 4, q = t & 15;
+  // the next strip is fetched into registers while the current one is used
+  float pf[DS_ROWS];
+  auto fetch = [&](int a0) {
+    const int n = min(DS_ROWS, K - a0) * K;
+#pragma unroll
+    for (int m = 0; m < DS_ROWS; ++m) {
+      const int e = t + m * 256;
+      if (e < n) {
+        const int r = e / K, cc = e - r * K;
+        pf[m] = R[(size_t)(a0 + r) * ld + cc];
+      }
+    }
+  };
+  fetch(0);
   __syncthreads();
   for (int a0 = 0; a0 < K; a0 += DS_ROWS) {
     const int nr = min(DS_ROWS, K - a0);
-    for (int e = t; e < nr * K; e += 256) {
-      const int r = e / K, cc = e - r * K;
-      strip[r * DS_PITCH + cc] = R[(size_t)(a0 + r) * ld + cc];
+#pragma unroll
+    for (int m = 0; m < DS_ROWS; ++m) {
+      const int e = t + m * 256;
+      if (e < nr * K) {
+        const int r = e / K, cc = e - r * K;
+        strip[r * DS_PITCH + cc] = pf[m];
+      }
     }
     __syncthreads();
+    if (a0 + DS_ROWS < K) fetch(a0 + DS_ROWS);
     if (t < K) {   // column role: output t
       for (int r = 0; r < nr; ++r) {
         const int a = a0 + r;

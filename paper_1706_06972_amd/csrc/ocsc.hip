@@ -913,7 +913,7 @@ int chol_history(ocsc_ctx* c, int B) {
     double2* s3 = W + 3 * (size_t)nf * bs;
     double2* s4 = W + 4 * (size_t)nf * bs;
     const dim3 g(2, 2, nf);
-    hipLaunchKernelGGL(k_schur_unpack, dim3(16, nf), dim3(256), 0, c->stream, (const float*)c->Hm, c->fs, c->K,
+    hipLaunchKernelGGL(k_schur_unpack, dim3(3 * 16, nf), dim3(256), 0, c->stream, (const float*)c->Hm, c->fs, c->K,
                        c->rho_d, f0, nf, W);
     hipLaunchKernelGGL((k_chol_inv_t<true>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream, (const float*)nullptr,
                        (float*)nullptr, (const double2*)s0, s1, CB_N, 0, 0.0);                        // P = A11^-1
@@ -927,8 +927,9 @@ int chol_history(ocsc_ctx* c, int B) {
                        (const double2*)s4, (const double2*)nullptr, s2, -1.0, 0.0);                  // C21 = -Q B
     hipLaunchKernelGGL((k_zgemm128<true, false>), g, dim3(256), 0, c->stream, (const double2*)s4,
                        (const double2*)s2, (const double2*)s1, s1, -1.0, 1.0);                       // C11 = P - B^H C21
-    hipLaunchKernelGGL(k_schur_pack, dim3(32, nf), dim3(256), 0, c->stream, (const double2*)W, f0, nf, c->K, c->fs,
-                       (float*)c->Cm);
+    const int kt = (c->K + SU_T - 1) / SU_T;
+    hipLaunchKernelGGL(k_schur_pack, dim3(kt * kt, nf), dim3(256), 0, c->stream, (const double2*)W, f0, nf, c->K,
+                       c->fs, (float*)c->Cm);
     LAUNCHED(c);
   }
   return OCSC_OK;
