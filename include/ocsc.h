@@ -80,12 +80,16 @@ typedef struct {
 /* opts.flags: warm-start DictOCSC: each ocsc_dict_update continues from the
  * V and Theta of the previous one instead of V = Theta = 0. */
 #define OCSC_FLAG_WARM_START 4
-/* opts.flags: precision form of the history (FP32 contexts, K <= 128, cold
+/* opts.flags: precision form of the history (FP32 contexts, K <= 256, cold
  * start).  ocsc_history_accumulate adds the minibatch to H and G with the
  * product conj(Z)^T Z on the BF16 matrix cores (FP32 accumulation, z split
  * into two BF16 parts, the products hi*hi + hi*lo + lo*hi), then recomputes
- * C_p = (H_p + rho_d I)^-1 for every frequency from an FP64 Cholesky factor,
- * instead of the Sherman-Morrison recursion.  Implies OCSC_FLAG_KEEP_HISTORY. */
+ * C_p = (H_p + rho_d I)^-1 for every frequency from FP64 Cholesky factors,
+ * instead of the Sherman-Morrison recursion (for K > 128: the inverses of
+ * two 128-blocks joined by their Schur complement).  Implies
+ * OCSC_FLAG_KEEP_HISTORY.  K > 128 is available only in this form: its D-step
+ * streams C_p from HBM instead of holding it in LDS.  K > 128 also needs a
+ * workspace of up to 2048 x 1.25 MB. */
 #define OCSC_FLAG_CHOLESKY 8
 
 /* Fill *opts with the defaults listed above. */
