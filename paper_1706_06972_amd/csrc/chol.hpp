@@ -408,27 +408,29 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
     __syncthreads();
   }
   // 4. C = X^H X, C_ij = sum_{m >= j} conj(X_mi) X_mj for i <= j, in 2 x 2
-  //    blocks (four loads for four products per m)
-  auto xat = [&](int m, int cidx) -> double2 {
-    return (cidx <= m && cidx < K) ? L[tri_idx(m, cidx)] : make_double2(0.0, 0.0);
-  };
-  const int n2 = (K + 1) / 2;
+  //    blocks (four loads for four products per m).  X is block diagonal
+  //    with the identity padding, so the sums may run to N; only m = j0 meets
+  //    the zero upper triangle (X_m,j0+1 for m = j0).
+  const int n2 = N / 2;
   for (int t = tid; t < n2 * (n2 + 1) / 2; t += CHOL_NT) {
-    int bi = 0, rem = t;
-    while (rem >= n2 - bi) {
-      rem -= n2 - bi;
-      ++bi;
-    }
-    const int bj = bi + rem;
-    const int i0 = 2 * bi, j0 = 2 * bj;
+    int r = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);   // t = r (r + 1) / 2 + c, c <= r
+    while (tri_idx(r + 1, 0) <= t) ++r;
+    while (tri_idx(r, 0) > t) --r;
+    const int i0 = 2 * (t - tri_idx(r, 0)), j0 = 2 * r;   // tile rows i0, i0 + 1 <= columns j0, j0 + 1
     double2 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
-    for (int m = j0; m < K; ++m) {
-      const double2 xi[2] = {xat(m, i0), xat(m, i0 + 1)};
-      const double2 xj[2] = {xat(m, j0), xat(m, j0 + 1)};
+    {
+      const int r0 = tri_idx(j0, 0);   // m = j0: X_j0,j0+1 = 0
+      const double2 xi0 = L[r0 + i0], xi1 = (i0 + 1 <= j0) ? L[r0 + i0 + 1] : make_double2(0.0, 0.0);
+      const double2 xj0 = L[r0 + j0];
+      acc[0][0] = zadd_cmul(make_double2(0.0, 0.0), xi0, xj0);
+      acc[1][0] = zadd_cmul(make_double2(0.0, 0.0), xi1, xj0);
+      acc[0][1] = make_double2(0.0, 0.0);
+      acc[1][1] = make_double2(0.0, 0.0);
+    }
+    for (int m = j0 + 1; m < N; ++m) {
+      const int rm = tri_idx(m, 0);
+      const double2 xi[2] = {L[rm + i0], L[rm + i0 + 1]};
+      const double2 xj[2] = {L[rm + j0], L[rm + j0 + 1]};
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll

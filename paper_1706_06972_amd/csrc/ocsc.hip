@@ -1420,46 +1420,13 @@ int ocsc_dict_update_group(ocsc_ctx* const* ctxs, int n) {
     if (ctxs[s]->t == 0) return fail(c0, OCSC_E_STATE, "every context needs at least one accumulated sample");
   }
   // run on the first context's stream, after every member's earlier work
-  hipStream_t ls = c0->stream;
-  std::vector<hipStream_t> saved(n);
-  std::vector<hipEvent_t> evs;
-  auto cleanup = [&]() {
-    for (int s = 0; s < n; ++s) ctxs[s]->stream = saved[s];
-    for (auto e : evs) (void)hipEventDestroy(e);
-  };
-  for (int s = 0; s < n; ++s) saved[s] = ctxs[s]->stream;
-  for (int s = 1; s < n; ++s) {
-    if (saved[s] == ls) continue;
-    hipEvent_t e = nullptr;
-    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-    if (err == hipSuccess) {
-      evs.push_back(e);
-      err = hipEventRecord(e, saved[s]);
-    }
-    if (err == hipSuccess) err = hipStreamWaitEvent(ls, e, 0);
-    if (err != hipSuccess) {
-      cleanup();
-      return fail(c0, OCSC_E_HIP, std::string("stream ordering: ") + hipGetErrorString(err));
-    }
-  }
-  for (int s = 0; s < n; ++s) {
-    ctxs[s]->stream = ls;
-    ctxs[s]->pending_B = 0;
-  }
+  StreamJoin join(ctxs, n);
+  hipError_t err = join.enter();
+  if (err != hipSuccess) return fail(c0, OCSC_E_HIP, std::string("stream ordering: ") + hipGetErrorString(err));
+  for (int s = 0; s < n; ++s) ctxs[s]->pending_B = 0;
   const int rc = c0->sr == 8 ? dict_update_group_t<double>(ctxs, n) : dict_update_group_t<float>(ctxs, n);
   // later work on every member's stream waits for the update
-  hipError_t err = hipSuccess;
-  for (int s = 1; s < n && rc == OCSC_OK && err == hipSuccess; ++s) {
-    if (saved[s] == ls) continue;
-    hipEvent_t e = nullptr;
-    err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-    if (err == hipSuccess) {
-      evs.push_back(e);
-      err = hipEventRecord(e, ls);
-    }
-    if (err == hipSuccess) err = hipStreamWaitEvent(saved[s], e, 0);
-  }
-  cleanup();
+  err = join.leave();
   if (rc) return rc;
   if (err != hipSuccess) return fail(c0, OCSC_E_HIP, std::string("stream ordering: ") + hipGetErrorString(err));
   return OCSC_OK;
