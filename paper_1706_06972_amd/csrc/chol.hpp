@@ -145,9 +145,11 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
 // Blocking by CHOL_B cuts the barrier phases and the passes over the
 // trailing triangle by CHOL_B; the small diagonal blocks are factorised and
 // inverted redundantly by every thread in registers.
-// Dynamic LDS: (N(N+1)/2 + CHOL_B N + CHOL_B^2) complex doubles, N = K
-// rounded up to CHOL_B.  The trailing updates are flat lists of 2 x 2 tiles
-// shared by all threads, so every step keeps the threads evenly busy.
+// Dynamic LDS: (N(N+1)/2 + CHOL_B^2) complex doubles, N = K rounded up to
+// CHOL_B (81 KB at K = 100, so that two workgroups of NT = 512 share a CU and
+// cover each other's serial diagonal-block phases).  The trailing updates are
+// flat lists of 2 x 2 tiles shared by all threads, so every step keeps the
+// threads evenly busy.
 // FULL = true: the input is A itself, a full Hermitian n x n block in FP64
 // (row pitch CB_N, block p at Ain + p * CB_N * CB_N), and the output is the
 // full inverse in the same layout (the blocks of the K > 128 form below).
@@ -169,8 +171,8 @@ constexpr int CHOL_NT = 1024;   // threads per workgroup: 16 waves share each st
 constexpr int CHOL_B = 4;       // columns (rows) per step of the factorisation (inverse)
 constexpr int CB_N = 128;       // block size of the K > 128 form
 
-template <bool FULL>
-__global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict__ Hm, float* __restrict__ Cm,
+template <bool FULL, int NT>
+__global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm, float* __restrict__ Cm,
                                                    const double2* __restrict__ Ain, double2* __restrict__ Cout,
                                                    int K, int fs, double rho_d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -178,11 +180,10 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
   // identity (which stays outside the top-left K x K of the inverse)
   const int N = (K + CHOL_B - 1) / CHOL_B * CHOL_B;
   double2* L = reinterpret_cast<double2*>(smem_raw);
-  double2* cb = L + N * (N + 1) / 2;      // [N][CHOL_B]: the column block being factorised / consumed
-  double2* xdb = cb + N * CHOL_B;        // [CHOL_B][CHOL_B]: factor (step 2) / inverse (step 3) of the diagonal block
+  double2* xdb = L + N * (N + 1) / 2;   // [CHOL_B][CHOL_B]: factor (step 2) / inverse (step 3) of the diagonal block
   const int p = blockIdx.x, tid = threadIdx.x;
   const int ld = K + 1;
-  for (int e = tid; e < N * (N + 1) / 2; e += CHOL_NT) {
+  for (int e = tid; e < N * (N + 1) / 2; e += NT) {
     int i = (int)((sqrtf(8.f * (float)e + 1.f) - 1.f) * 0.5f);
     while (tri_idx(i + 1, 0) <= e) ++i;
     while (tri_idx(i, 0) > e) --i;
@@ -201,12 +202,12 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
   }
   __syncthreads();
   // 2. Cholesky A = L L^H, CHOL_B columns per step (right-looking):
-  //    the CHOL_B x CHOL_B diagonal factor D is formed by every thread in
-  //    registers; the rows below solve l_i D^H = a_i into cb; then the
-  //    trailing block takes the rank-CHOL_B update A_ik -= sum_c l_ic conj(l_kc).
+  //    one wave factors the CHOL_B x CHOL_B diagonal block D and shares it
+  //    through LDS; each row below solves l_i D^H = a_i in place; then the
+  //    trailing triangle takes the rank-CHOL_B update
+  //    A_ik -= sum_c l_ic conj(l_kc) in 2 x 2 tiles.
   for (int j = 0; j < N; j += CHOL_B) {
-    const int nb = CHOL_B;
-    if (tid < 64) {   // one wave factors the diagonal block D (identical in every lane); lane 0 shares it
+    if (tid < 64) {
       double2 d[CHOL_B][CHOL_B];
 #pragma unroll
       for (int c = 0; c < CHOL_B; ++c)
@@ -245,49 +246,45 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
       dinv[c] = d[c][c].y;
       d[c][c].y = 0.0;
     }
-    for (int i = j + nb + tid; i < N; i += CHOL_NT) {
+    // panel rows in place (each thread reads and writes its own rows)
+    for (int i = j + CHOL_B + tid; i < N; i += NT) {
+      const int ri = tri_idx(i, 0) + j;
       double2 l[CHOL_B];
 #pragma unroll
       for (int c = 0; c < CHOL_B; ++c) {
-        l[c] = make_double2(0.0, 0.0);
-        if (c < nb) {
-          double2 v = L[tri_idx(i, j + c)];
+        double2 v = L[ri + c];
 #pragma unroll
-          for (int m = 0; m < c; ++m) v = zsub_mulc(v, l[m], d[c][m]);
-          l[c] = make_double2(v.x * dinv[c], v.y * dinv[c]);
-        }
-        cb[i * CHOL_B + c] = l[c];
+        for (int m = 0; m < c; ++m) v = zsub_mulc(v, l[m], d[c][m]);
+        l[c] = make_double2(v.x * dinv[c], v.y * dinv[c]);
       }
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) L[ri + c] = l[c];
     }
-    __syncthreads();
     if (tid == 0) {
 #pragma unroll
       for (int r = 0; r < CHOL_B; ++r)
 #pragma unroll
-        for (int c = 0; c <= r; ++c)
-          if (r < nb) L[tri_idx(j + r, j + c)] = d[r][c];
+        for (int c = 0; c <= r; ++c) L[tri_idx(j + r, j + c)] = d[r][c];
     }
-    for (int i = j + nb + tid; i < N; i += CHOL_NT)
-#pragma unroll
-      for (int c = 0; c < CHOL_B; ++c) L[tri_idx(i, j + c)] = cb[i * CHOL_B + c];
+    __syncthreads();
     {
       // trailing triangle in 2 x 2 tiles, a flat list over all threads
-      const int j0 = j + nb, t2 = (N - j0) / 2;
-      for (int t = tid; t < t2 * (t2 + 1) / 2; t += CHOL_NT) {
+      const int j0 = j + CHOL_B, t2 = (N - j0) / 2;
+      for (int t = tid; t < t2 * (t2 + 1) / 2; t += NT) {
         int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
         while (tri_idx(ti + 1, 0) <= t) ++ti;
         while (tri_idx(ti, 0) > t) --ti;
         const int tk = t - tri_idx(ti, 0);
         const int i = j0 + 2 * ti, k = j0 + 2 * tk;   // rows i, i+1; columns k, k+1 (k <= i)
+        const int r0 = tri_idx(i, 0), r1 = tri_idx(i + 1, 0), q0 = tri_idx(k, 0), q1 = tri_idx(k + 1, 0);
         double2 a[2][CHOL_B], b[2][CHOL_B];
 #pragma unroll
         for (int c = 0; c < CHOL_B; ++c) {
-          a[0][c] = cb[i * CHOL_B + c];
-          a[1][c] = cb[(i + 1) * CHOL_B + c];
-          b[0][c] = cb[k * CHOL_B + c];
-          b[1][c] = cb[(k + 1) * CHOL_B + c];
+          a[0][c] = L[r0 + j + c];
+          a[1][c] = L[r1 + j + c];
+          b[0][c] = L[q0 + j + c];
+          b[1][c] = L[q1 + j + c];
         }
-        const int r0 = tri_idx(i, 0), r1 = tri_idx(i + 1, 0);
         double2 v00 = L[r0 + k], v10 = L[r1 + k], v11 = L[r1 + k + 1];
         double2 v01 = (k + 1 <= i) ? L[r0 + k + 1] : make_double2(0.0, 0.0);
 #pragma unroll
@@ -306,13 +303,14 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
     __syncthreads();
   }
   // 3. X = L^-1 in place, CHOL_B rows per step (right-looking on [L | I]):
-  //    B starts as I; per step the diagonal block's inverse Xd (registers of
-  //    every thread, and xdb in LDS) turns rows k.. of B into rows of X, and
-  //    the rows below take B_ij -= sum_c L_i,k+c X_k+c,j.  Slot (i, j) holds L
+  //    B starts as I; per step one wave inverts the diagonal block (Xd, shared
+  //    through LDS), rows k.. of B become rows of X, then the rows below take
+  //    B_ij -= sum_c L_i,k+c X_k+c,j: first for the columns left of the block
+  //    (which read the block's column of L), then for the block's own columns
+  //    (which overwrite it; one thread per row pair).  Slot (i, j) holds L
   //    until column j is consumed, then B, then X.
   for (int k = 0; k < N; k += CHOL_B) {
-    const int nb = CHOL_B;
-    if (tid < 64) {   // one wave inverts the diagonal block; lane 0 shares Xd
+    if (tid < 64) {
       double2 xd[CHOL_B][CHOL_B];
 #pragma unroll
       for (int c = 0; c < CHOL_B; ++c)
@@ -337,62 +335,51 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
 #pragma unroll
           for (int c = 0; c < CHOL_B; ++c) xdb[r * CHOL_B + c] = xd[r][c];
     }
-    for (int i = k + nb + tid; i < N; i += CHOL_NT)
-#pragma unroll
-      for (int c = 0; c < CHOL_B; ++c) cb[i * CHOL_B + c] = L[tri_idx(i, k + c)];
     __syncthreads();
-    double2 xd[CHOL_B][CHOL_B];
+    for (int jj = tid; jj < k; jj += NT) {   // rows k.. of X, columns left of the block
+      double2 xd[CHOL_B][CHOL_B];
 #pragma unroll
-    for (int r = 0; r < CHOL_B; ++r)
+      for (int r = 0; r < CHOL_B; ++r)
 #pragma unroll
-      for (int c = 0; c < CHOL_B; ++c) xd[r][c] = xdb[r * CHOL_B + c];
-    for (int jj = tid; jj < k; jj += CHOL_NT) {   // rows k.. of X, columns left of the block
+        for (int c = 0; c <= r; ++c) xd[r][c] = xdb[r * CHOL_B + c];
       double2 bq[CHOL_B];
 #pragma unroll
-      for (int m = 0; m < CHOL_B; ++m) bq[m] = m < nb ? L[tri_idx(k + m, jj)] : make_double2(0.0, 0.0);
+      for (int m = 0; m < CHOL_B; ++m) bq[m] = L[tri_idx(k + m, jj)];
 #pragma unroll
       for (int r = 0; r < CHOL_B; ++r) {
-        if (r < nb) {
-          double2 x = make_double2(0.0, 0.0);
+        double2 x = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int m = 0; m <= r; ++m) x = zsub_mul(x, make_double2(-xd[r][m].x, -xd[r][m].y), bq[m]);
-          L[tri_idx(k + r, jj)] = x;
-        }
+        for (int m = 0; m <= r; ++m) x = zsub_mul(x, make_double2(-xd[r][m].x, -xd[r][m].y), bq[m]);
+        L[tri_idx(k + r, jj)] = x;
       }
     }
-    __syncthreads();
     if (tid == 0) {
 #pragma unroll
       for (int r = 0; r < CHOL_B; ++r)
 #pragma unroll
-        for (int c = 0; c <= r; ++c)
-          if (r < nb) L[tri_idx(k + r, k + c)] = xd[r][c];
+        for (int c = 0; c <= r; ++c) L[tri_idx(k + r, k + c)] = xdb[r * CHOL_B + c];
     }
+    __syncthreads();
     {
-      // rows below the block x columns left of its end, in 2 x 2 tiles
-      const int nr = (N - k - nb) / 2, nc = (k + nb) / 2;
-      for (int t = tid; t < nr * nc; t += CHOL_NT) {
-        const int i = k + nb + 2 * (t / nc), jj = 2 * (t % nc);
+      // rows below the block x columns left of it, in 2 x 2 tiles
+      const int nr = (N - k - CHOL_B) / 2, nc = k / 2;
+      for (int t = tid; t < nr * nc; t += NT) {
+        const int i = k + CHOL_B + 2 * (t / nc), jj = 2 * (t % nc);
+        const int r0 = tri_idx(i, 0), r1 = tri_idx(i + 1, 0);
         double2 a[2][CHOL_B], x[CHOL_B][2];
 #pragma unroll
         for (int c = 0; c < CHOL_B; ++c) {
-          a[0][c] = cb[i * CHOL_B + c];
-          a[1][c] = cb[(i + 1) * CHOL_B + c];
-          if (jj < k) {   // X rows k.. (written above), left of the diagonal block
-            x[c][0] = L[tri_idx(k + c, jj)];
-            x[c][1] = L[tri_idx(k + c, jj + 1)];
-          } else {        // inside the diagonal block: X = Xd (zero above its diagonal)
-            x[c][0] = xdb[c * CHOL_B + (jj - k)];
-            x[c][1] = xdb[c * CHOL_B + (jj + 1 - k)];
-          }
+          a[0][c] = L[r0 + k + c];
+          a[1][c] = L[r1 + k + c];
+          const int rx = tri_idx(k + c, 0) + jj;   // X rows k.. (written above)
+          x[c][0] = L[rx];
+          x[c][1] = L[rx + 1];
         }
-        const int r0 = tri_idx(i, 0), r1 = tri_idx(i + 1, 0);
         double2 v[2][2];
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
-          for (int q = 0; q < 2; ++q)
-            v[rr][q] = jj < k ? L[(rr ? r1 : r0) + jj + q] : make_double2(0.0, 0.0);   // B; new columns start at 0
+          for (int q = 0; q < 2; ++q) v[rr][q] = L[(rr ? r1 : r0) + jj + q];
 #pragma unroll
         for (int c = 0; c < CHOL_B; ++c)
 #pragma unroll
@@ -406,13 +393,31 @@ __global__ __launch_bounds__(CHOL_NT) void k_chol_inv_t(const float* __restrict_
       }
     }
     __syncthreads();
+    // the block's own columns: B_i,k+q = -sum_{c >= q} L_i,k+c Xd[c][q] (B starts at 0)
+    for (int i = k + CHOL_B + 2 * tid; i < N; i += 2 * NT) {
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) {
+        const int ri = tri_idx(i + rr, 0) + k;
+        double2 a[CHOL_B];
+#pragma unroll
+        for (int c = 0; c < CHOL_B; ++c) a[c] = L[ri + c];
+#pragma unroll
+        for (int q = 0; q < CHOL_B; ++q) {
+          double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int c = q; c < CHOL_B; ++c) v = zsub_mul(v, a[c], xdb[c * CHOL_B + q]);   // Xd from LDS
+          L[ri + q] = v;
+        }
+      }
+    }
+    __syncthreads();
   }
   // 4. C = X^H X, C_ij = sum_{m >= j} conj(X_mi) X_mj for i <= j, in 2 x 2
   //    blocks (four loads for four products per m).  X is block diagonal
   //    with the identity padding, so the sums may run to N; only m = j0 meets
   //    the zero upper triangle (X_m,j0+1 for m = j0).
   const int n2 = N / 2;
-  for (int t = tid; t < n2 * (n2 + 1) / 2; t += CHOL_NT) {
+  for (int t = tid; t < n2 * (n2 + 1) / 2; t += NT) {
     int r = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);   // t = r (r + 1) / 2 + c, c <= r
     while (tri_idx(r + 1, 0) <= t) ++r;
     while (tri_idx(r, 0) > t) --r;

@@ -867,8 +867,10 @@ int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* ou
 // accumulation time (the fold of G and C may still be deferred).
 size_t chol_lds(int K) {
   const size_t n = (size_t)(K + CHOL_B - 1) / CHOL_B * CHOL_B;   // padded to whole column blocks
-  return (n * (n + 1) / 2 + n * CHOL_B + CHOL_B * CHOL_B) * 16;
+  return (n * (n + 1) / 2 + CHOL_B * CHOL_B) * 16;
 }
+// two workgroups of 512 threads per CU when the factor takes at most half the LDS
+bool chol_small(int K) { return chol_lds(K) <= 80 * 1024; }
 
 // Precision form: H += conj(Z)^T Z and G += conj(Z)^T x on the matrix cores
 // (BF16 split, FP32 accumulation), then C = (H + rho_d I)^-1 by an FP64
@@ -896,9 +898,14 @@ int chol_history(ocsc_ctx* c, int B) {
   }
   LAUNCHED(c);
   if (!c->dstream) {
-    hipLaunchKernelGGL((k_chol_inv_t<false>), dim3(c->Pf), dim3(CHOL_NT), chol_lds(c->K), c->stream,
-                       (const float*)c->Hm, (float*)c->Cm, (const double2*)nullptr, (double2*)nullptr, c->K, c->fs,
-                       c->rho_d);
+    if (chol_small(c->K))
+      hipLaunchKernelGGL((k_chol_inv_t<false, 512>), dim3(c->Pf), dim3(512), chol_lds(c->K), c->stream,
+                         (const float*)c->Hm, (float*)c->Cm, (const double2*)nullptr, (double2*)nullptr, c->K, c->fs,
+                         c->rho_d);
+    else
+      hipLaunchKernelGGL((k_chol_inv_t<false, CHOL_NT>), dim3(c->Pf), dim3(CHOL_NT), chol_lds(c->K), c->stream,
+                         (const float*)c->Hm, (float*)c->Cm, (const double2*)nullptr, (double2*)nullptr, c->K, c->fs,
+                         c->rho_d);
     LAUNCHED(c);
     return OCSC_OK;
   }
@@ -915,14 +922,14 @@ int chol_history(ocsc_ctx* c, int B) {
     const dim3 g(2, 2, nf);
     hipLaunchKernelGGL(k_schur_unpack, dim3(3 * 16, nf), dim3(256), 0, c->stream, (const float*)c->Hm, c->fs, c->K,
                        c->rho_d, f0, nf, W);
-    hipLaunchKernelGGL((k_chol_inv_t<true>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream, (const float*)nullptr,
-                       (float*)nullptr, (const double2*)s0, s1, CB_N, 0, 0.0);                        // P = A11^-1
+    hipLaunchKernelGGL((k_chol_inv_t<true, CHOL_NT>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream,
+                       (const float*)nullptr, (float*)nullptr, (const double2*)s0, s1, CB_N, 0, 0.0);   // P = A11^-1
     hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s2,
                        (const double2*)s1, (const double2*)nullptr, s4, 1.0, 0.0);                   // B = A21 P
     hipLaunchKernelGGL((k_zgemm128<false, true>), g, dim3(256), 0, c->stream, (const double2*)s4,
                        (const double2*)s2, (const double2*)s3, s3, -1.0, 1.0);                       // S = A22 - B A21^H
-    hipLaunchKernelGGL((k_chol_inv_t<true>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream, (const float*)nullptr,
-                       (float*)nullptr, (const double2*)s3, s0, CB_N, 0, 0.0);                        // Q = S^-1
+    hipLaunchKernelGGL((k_chol_inv_t<true, CHOL_NT>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream,
+                       (const float*)nullptr, (float*)nullptr, (const double2*)s3, s0, CB_N, 0, 0.0);   // Q = S^-1
     hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s0,
                        (const double2*)s4, (const double2*)nullptr, s2, -1.0, 0.0);                  // C21 = -Q B
     hipLaunchKernelGGL((k_zgemm128<true, false>), g, dim3(256), 0, c->stream, (const double2*)s4,
@@ -1225,7 +1232,9 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   }
   if (c->chol) {
     const int kb = c->dstream ? CB_N : K;   // the factorised block size
-    const void* fn = c->dstream ? (const void*)k_chol_inv_t<true> : (const void*)k_chol_inv_t<false>;
+    const void* fn = c->dstream ? (const void*)k_chol_inv_t<true, CHOL_NT>
+                                : (chol_small(K) ? (const void*)k_chol_inv_t<false, 512>
+                                                 : (const void*)k_chol_inv_t<false, CHOL_NT>);
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds(kb));
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
