@@ -38,6 +38,9 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
   constexpr int NTILE = NTD * (NTD + 1) / 2;      // tiles on or above the diagonal
   constexpr int TPW = (NTILE + NW * NSPLIT - 1) / (NW * NSPLIT);   // tiles per wave
   __shared__ __align__(16) __bf16 zrh[KP * HERK_LD], zrl[KP * HERK_LD], zih[KP * HERK_LD], zil[KP * HERK_LD];
+  // G: GS threads per filter k, each summing every GS-th sample of a chunk; x_b staged in LDS
+  constexpr int GS = NT / KP > 8 ? 8 : NT / KP;
+  __shared__ float2 xs[HERK_B], gpart[GS * KP];
   const int p = blockIdx.x, split = blockIdx.y;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   auto tile_of = [&](int tt) { return split + NSPLIT * (wave + NW * tt); };
@@ -56,10 +59,12 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
 #pragma unroll
   for (int tt = 0; tt < TPW; ++tt) re[tt] = im1[tt] = im2[tt] = v4f{0, 0, 0, 0};
   float gr = 0.f, gi = 0.f;
+  const int gk = tid % KP, gsl = tid / KP;   // this thread's filter and sample slice for G
   const float2* zp = Zt + (size_t)p * ldt * K;
   for (int b0 = 0; b0 < nb; b0 += HERK_B) {
     const int cb = min(HERK_B, nb - b0);
     __syncthreads();   // the previous chunk's operands are no longer read
+    if (tid < HERK_B) xs[tid] = tid < cb ? xh[(size_t)(b0 + tid) * Pf + p] : make_float2(0.f, 0.f);
     for (int e = tid; e < HERK_B * KP; e += NT) {
       const int b = e / KP, k = e - b * KP;   // consecutive threads read consecutive k
       float2 z = make_float2(0.f, 0.f);
@@ -71,15 +76,15 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
       zih[o] = ih;
       zil[o] = (__bf16)(z.y - (float)ih);
     }
-    if (split == 0 && tid < K) {   // G_p[k] += sum_b conj(z_bk) x_b (FP32)
-      for (int b = 0; b < cb; ++b) {
-        const float2 z = zp[(size_t)(b0 + b) * K + tid];
-        const float2 x = xh[(size_t)(b0 + b) * Pf + p];
+    __syncthreads();
+    if (split == 0 && gsl < GS && gk < K) {   // G_p[k] += sum_b conj(z_bk) x_b (FP32), samples gsl, gsl + GS, ...
+      for (int b = gsl; b < cb; b += GS) {
+        const float2 z = zp[(size_t)(b0 + b) * K + gk];
+        const float2 x = xs[b];
         gr += z.x * x.x + z.y * x.y;
         gi += z.x * x.y - z.y * x.x;
       }
     }
-    __syncthreads();
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
       if (tile_of(tt) >= NTILE) continue;
@@ -126,11 +131,18 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
       }
     }
   }
-  if (split == 0 && tid < K) {
-    float2 g = G[(size_t)tid * Pf + p];
-    g.x += gr;
-    g.y += gi;
-    G[(size_t)tid * Pf + p] = g;
+  if (split == 0) {
+    if (gsl < GS) gpart[gsl * KP + gk] = make_float2(gr, gi);
+    __syncthreads();
+    if (tid < K) {
+      float2 g = G[(size_t)tid * Pf + p];
+#pragma unroll
+      for (int sl = 0; sl < GS; ++sl) {
+        g.x += gpart[sl * KP + tid].x;
+        g.y += gpart[sl * KP + tid].y;
+      }
+      G[(size_t)tid * Pf + p] = g;
+    }
   }
 }
 

@@ -881,7 +881,7 @@ int chol_history(ocsc_ctx* c, int B) {
   switch (KP) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_herk_bf16<N, 4, 1>), dim3(c->Pf, 1), dim3(256), 0, c->stream, (const float2*)c->Zt,    \
+    hipLaunchKernelGGL((k_herk_bf16<N, 8, 1>), dim3(c->Pf, 1), dim3(512), 0, c->stream, (const float2*)c->Zt,    \
                        c->maxB, B, (const float2*)c->xh, c->Pf, (float*)c->Hm, c->fs, (float2*)c->G, c->K);     \
     break;
     X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128)
