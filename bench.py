@@ -305,15 +305,19 @@ def served_run(dev, K: int = 100) -> dict:
         out[f"mix_{int(rate)}"] = summarize(reqs, m["wall_s"], m["dictionary_updates"], warmup=n // 10)
     out["mix_slots"] = srv.slots
     srv.close()
-    srv = Server(K, 11, D0, grids=(128,), shares=(1,), update_every=256, budget=64e9,
-                 max_launch={128: 64})
-    for rate, n in ((4000.0, 6000), (20000.0, 6000)):
-        reqs = poisson_requests(n, rate, (128,), (1,), seed=7)
-        m = srv.run(reqs)
-        out[f"grid128_{int(rate)}"] = summarize(reqs, m["wall_s"], m["dictionary_updates"], warmup=n // 10)
-    srv.close()
+    for chol in (False, True):
+        # the 128x128 stream with the Sherman-Morrison fold, then in the precision form
+        srv = Server(K, 11, D0, grids=(128,), shares=(1,), update_every=256, budget=64e9,
+                     max_launch={128: 64}, cholesky=chol)
+        for rate, n in ((4000.0, 6000), (20000.0, 6000)):
+            reqs = poisson_requests(n, rate, (128,), (1,), seed=7)
+            m = srv.run(reqs)
+            key = f"grid128{'_precision' if chol else ''}_{int(rate)}"
+            out[key] = summarize(reqs, m["wall_s"], m["dictionary_updates"], warmup=n // 10)
+        srv.close()
     out["note"] = ("latency = completion event - arrival; inputs copied from pinned host memory inside the "
-                   "latency; dictionary updated every 256 requests (shared across grids)")
+                   "latency; dictionary updated every 256 requests (shared across grids); grid128_precision: "
+                   "the history on the BF16 matrix cores and C from FP64 Cholesky factors")
     return out
 
 

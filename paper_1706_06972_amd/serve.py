@@ -18,6 +18,9 @@ Design (host loop over the C calls; every arithmetic step runs in the library):
   history is folded) are sized so that all contexts fit the HBM budget.
 * Each grid's code-update launch shapes are autotuned at start-up for a full
   launch (``ocsc_autotune``); every shape gives the same bits.
+* ``cholesky=True`` serves in the precision form: each fold adds the pending
+  samples to the history on the matrix cores and rebuilds C from FP64
+  Cholesky factors, instead of folding sample after sample.
 * Every ``update_every`` completed requests the pending samples of every grid
   are accumulated and one shared dictionary update is enqueued; requests
   coded afterwards carry the next dictionary version.  A grid whose slots are
@@ -42,35 +45,39 @@ class Request:
     codes: object = None    # device tensor (K x grid x grid) when kept
 
 
-def slot_bytes(K: int, n: int, real_bytes: int = 4) -> int:
+def slot_bytes(K: int, n: int, real_bytes: int = 4, cholesky: bool = False) -> int:
     """Device bytes one pending slot of an n x n context holds: the sample and
-    code spectra, the code-ADMM dual and transform workspace."""
+    code spectra, the code-ADMM dual and transform workspace (and, in the
+    precision form, the frequency-major code spectra and a codes buffer)."""
     Pf, P = n * (n // 2 + 1), n * n
     spec = 2 * real_bytes
     b = Pf * spec * 2 + 2 * K * Pf * spec + K * P * real_bytes
     if n > 128:
         b += K * Pf * spec
+    if cholesky:
+        b += K * Pf * spec + K * P * real_bytes
     return b
 
 
-def fixed_bytes(K: int, n: int, real_bytes: int = 4) -> int:
-    """Device bytes of an n x n context independent of its slots (C dominates)."""
+def fixed_bytes(K: int, n: int, real_bytes: int = 4, cholesky: bool = False) -> int:
+    """Device bytes of an n x n context independent of its slots (C, and H in
+    the precision form, dominate)."""
     Pf = n * (n // 2 + 1)
     fs = (K * (K + 1) + 3) // 4 * 4
-    return Pf * fs * real_bytes + 8 * K * Pf * 2 * real_bytes
+    return Pf * fs * real_bytes * (2 if cholesky else 1) + 8 * K * Pf * 2 * real_bytes
 
 
 def plan_slots(K: int, grids: Sequence[int], shares: Sequence[float], budget: float,
-               max_launch: Dict[int, int]) -> Dict[int, int]:
+               max_launch: Dict[int, int], cholesky: bool = False) -> Dict[int, int]:
     """Pending slots per grid: what remains of the budget after the fixed
     state, split in proportion to share x slot size, at least one launch's
     worth per grid."""
-    free = budget - sum(fixed_bytes(K, n) for n in grids)
-    weights = [s * slot_bytes(K, n) for s, n in zip(shares, grids)]
+    free = budget - sum(fixed_bytes(K, n, cholesky=cholesky) for n in grids)
+    weights = [s * slot_bytes(K, n, cholesky=cholesky) for s, n in zip(shares, grids)]
     tot = sum(weights)
     out = {}
     for n, w in zip(grids, weights):
-        slots = int(free * w / tot // slot_bytes(K, n)) if free > 0 else 0
+        slots = int(free * w / tot // slot_bytes(K, n, cholesky=cholesky)) if free > 0 else 0
         slots = min(slots, 65535 // K)
         if slots < max_launch[n]:
             raise ValueError(f"HBM budget too small for the {n}x{n} grid")
@@ -97,20 +104,20 @@ class Server:
                  shares: Sequence[float] = (8, 4, 2, 1), lam: float = 1.0, rho: float = 1.0,
                  update_every: int = 256, budget: float = 64e9, max_launch: Optional[Dict[int, int]] = None,
                  iters_code: int = 10, iters_dict: int = 10, keep_codes: bool = False, device: str = "cuda:0",
-                 slots: Optional[Dict[int, int]] = None, autotune: bool = True):
+                 slots: Optional[Dict[int, int]] = None, autotune: bool = True, cholesky: bool = False):
         import torch
         from paper_1706_06972_amd.ocsc import OCSC
         self.torch = torch
         self.K, self.update_every, self.keep_codes = K, update_every, keep_codes
         self.device = torch.device(device)
         max_launch = max_launch or {64: 64, 128: 32, 256: 8, 512: 2}
-        self.slots = dict(slots) if slots else plan_slots(K, grids, shares, budget, max_launch)
+        self.slots = dict(slots) if slots else plan_slots(K, grids, shares, budget, max_launch, cholesky)
         self.grids: Dict[int, _Grid] = {}
         for n in grids:
             st = torch.cuda.Stream(device=self.device)
             with torch.cuda.stream(st):
                 m = OCSC(K, filt, filt, n, n, lam, rho, iters_code=iters_code, iters_dict=iters_dict,
-                         max_batch=self.slots[n], precision="f32", device=self.device)
+                         max_batch=self.slots[n], precision="f32", cholesky=cholesky, device=self.device)
                 m.set_dictionary(D0)
                 if autotune:   # launch shapes for full launches of this grid (same bits for every shape)
                     m.autotune(min(max_launch[n], self.slots[n]))

@@ -42,15 +42,16 @@ def test_same_alone_and_in_the_mix():
     srv.close()
 
 
-def test_served_run_matches_oracle_replay():
-    say("case serving: oracle replay with updates")
+@pytest.mark.parametrize("cholesky", [False, True])
+def test_served_run_matches_oracle_replay(cholesky):
+    say(f"case serving: oracle replay with updates, precision form {cholesky}")
     from paper_1706_06972_amd.serve import Server, poisson_requests
     K, filt = 3, 5
     grids, shares = (32, 64), (2, 1)
     D0 = synth.initial_dictionary(K, filt, filt, 4)
     reqs = poisson_requests(30, 5000.0, grids, shares, seed=5)
     srv = Server(K, filt, D0, grids=grids, shares=shares, update_every=7, keep_codes=True,
-                 max_launch={32: 4, 64: 2}, slots={32: 6, 64: 4}, lam=0.3)
+                 max_launch={32: 4, 64: 2}, slots={32: 6, 64: 4}, lam=0.3, cholesky=cholesky)
     srv.run(reqs)
     assert srv.updates >= 3
     # replay on the oracle, one learner per grid
