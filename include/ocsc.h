@@ -99,7 +99,9 @@ void ocsc_default_opts(ocsc_opts* opts);
  * Create a learner (Algorithm 3, initialisation): history G = 0 and
  * C_p = I / rho_d at every frequency, t = 0, dictionary spectrum zero until
  * ocsc_set_dictionary.
- *   K >= 1; 1 <= filt_h <= pad_h; 1 <= filt_w <= pad_w; pad_h, pad_w powers of
+ *   1 <= K <= 128 in FP32 and 1 <= K <= 92 in FP64 (the D-step holds C_p in
+ *   LDS), K <= 256 with OCSC_FLAG_CHOLESKY; 1 <= filt_h <= pad_h;
+ *   1 <= filt_w <= pad_w; pad_h, pad_w powers of
  *   two, both in [32, 128] (planes transformed in LDS) or both in {256, 512}
  *   (two-pass transforms; then max_batch * K <= 65535); lambda >= 0 (the l1
  *   weight beta of eq. csc); rho > 0 (the code-ADMM penalty).  opts may be NULL

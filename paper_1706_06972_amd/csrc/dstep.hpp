@@ -233,17 +233,23 @@ __device__ __forceinline__ void herm_rank1_ct(T* __restrict__ R, const cx<T>* v,
   __syncthreads();
 }
 
-// 16-byte vectors of one slot (fpb consecutive frequencies) held by one thread.
+// 16-byte vectors of one slot (fpb consecutive frequencies) held by one
+// thread: at most SWEEP_MAXV in the generic kernel (KT = 0), at most
+// SWEEP_MAXV_L in the generic kernel for large slots (KT = -1; one frequency of
+// up to 69,632 bytes: FP32 K <= 131, FP64 K <= 92).
 constexpr int SWEEP_MAXV = 12;
+constexpr int SWEEP_MAXV_L = 17;
 
 // 16-byte vectors of one slot per thread: exact for the compile-time
-// specialisations, SWEEP_MAXV for the generic kernel.
+// specialisations (KT > 0), the bound of the generic kernels otherwise.
 template <typename T, int KT, int FPB>
 __host__ __device__ constexpr int sweep_nvm() {
   if constexpr (KT > 0) {
     constexpr int VR = 16 / (int)sizeof(T);
     constexpr int fs = (KT * (KT + 1) + VR - 1) / VR * VR;
     return (FPB * fs * (int)sizeof(T) / 16 + 255) / 256;
+  } else if constexpr (KT < 0) {
+    return SWEEP_MAXV_L;
   } else {
     return SWEEP_MAXV;
   }
@@ -354,7 +360,8 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
                                                     cx<T>* __restrict__ dout,
                                                     int K_, int Pf, int fpb_, int fs_, int slots_per_wg,
                                                     int reverse) {
-  // KT > 0: K and fpb fixed at compile time (the arguments then equal them)
+  // KT > 0: K and fpb fixed at compile time (the arguments then equal them);
+  // KT = 0, -1: generic, slots of up to SWEEP_MAXV, SWEEP_MAXV_L vectors per thread
   constexpr bool CT = KT > 0;
   constexpr int VR = 16 / (int)sizeof(T);
   const int K = CT ? KT : K_;

@@ -402,15 +402,21 @@ int launch_gamma(ocsc_ctx* c) {
 }
 
 // Compile-time specialisations of the D-step sweep (real type, K, fpb); the
-// generic kernel serves every other shape.
+// generic kernels serve every other shape.
 #define OCSC_SWEEP_SPECS(X) X(float, 100, 1) X(float, 16, 16) X(double, 16, 8)
+
+// bytes of one D-step slot: C of fpb frequencies in the R-form
+size_t sweep_slot_bytes(int K, int fpb, size_t sr) {
+  const int vr = (int)(16 / sr);
+  return (size_t)fpb * ((size_t)(K * (K + 1) + vr - 1) / vr * vr) * sr;
+}
 
 int sweep_nvm_for(int K, int fpb, size_t sr) {
 #define X(T, KT, FPB) \
   if (sr == sizeof(T) && K == KT && fpb == FPB) return sweep_nvm<T, KT, FPB>();
   OCSC_SWEEP_SPECS(X)
 #undef X
-  return SWEEP_MAXV;
+  return sweep_slot_bytes(K, fpb, sr) <= (size_t)256 * SWEEP_MAXV * 16 ? SWEEP_MAXV : SWEEP_MAXV_L;
 }
 
 // One D-step sweep; nfold > 0 folds the kept spectra of nfold samples first.
@@ -448,7 +454,10 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
   }
   OCSC_SWEEP_SPECS(X)
 #undef X
-  if (!done) OCSC_SWEEP(0, 0);
+  if (!done) {
+    if (sweep_nvm_for(c->K, c->fpb, sizeof(T)) == SWEEP_MAXV_L) OCSC_SWEEP(-1, 0);
+    else OCSC_SWEEP(0, 0);
+  }
 #undef OCSC_SWEEP
   LAUNCHED(c);
   return OCSC_OK;
@@ -1152,7 +1161,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     return fail(nullptr, OCSC_E_UNSUPPORTED, "max_batch * K must be <= 65535 on grids above 128");
   const size_t sr = o.precision == OCSC_FP64 ? 8 : 4;
   // D-step sweep: C_p (K rows of pitch K+1) must fit in LDS; a slot of fpb
-  // frequencies must fit the prefetch registers (256 threads x SWEEP_MAXV x 16 B)
+  // frequencies must fit the prefetch registers (256 threads x SWEEP_MAXV x 16 B,
+  // or SWEEP_MAXV_L vectors for a single frequency)
   const int vr = (int)(16 / sr);
   const int fs = (K * (K + 1) + vr - 1) / vr * vr;
   int fpb = 1;
@@ -1160,10 +1170,12 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   auto sweep_bytes = [&](int f) { return sweep_lds_bytes(K, f, fs, (int)sr, sweep_nvm_for(K, f, sr)); };
   const size_t max_lds = 160 * 1024 - 1024;
   const size_t max_slot = (size_t)256 * SWEEP_MAXV * 16;
-  if (!dstream && (sweep_bytes(1) > max_lds || (size_t)fs * sr > max_slot ||
+  if (!dstream && K > 128)
+    return fail(nullptr, OCSC_E_UNSUPPORTED, "K > 128 needs the Cholesky form (FP32, K <= 256)");
+  if (!dstream && (sweep_bytes(1) > max_lds || sweep_slot_bytes(K, 1, sr) > (size_t)256 * SWEEP_MAXV_L * 16 ||
                    sweep_plain_lds_bytes(K, 1, fs, (int)sr, sweep_nvm_for(K, 1, sr), 1) > max_lds))
     return fail(nullptr, OCSC_E_UNSUPPORTED,
-                "K too large for the LDS-resident D-step of this precision (K > 128 needs the Cholesky form)");
+                "K too large for the LDS-resident D-step of this precision (FP64: K <= 92; FP32: K <= 128)");
   while (fpb > 1 && (sweep_bytes(fpb) > 64 * 1024 || (size_t)fpb * fs * sr > max_slot)) fpb /= 2;
 
   ocsc_ctx* c = new (std::nothrow) ocsc_ctx();
@@ -1239,7 +1251,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
   if (!c->dstream && std::max(c->sweep_smem, c->plain_smem) > 64 * 1024) {
-    const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>
+    const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>,
+                         (const void*)k_dict_sweep<double, -1, 0>, (const void*)k_dict_sweep<float, -1, 0>
 #define X(T, KT, FPB) , (const void*)k_dict_sweep<T, KT, FPB>
                          OCSC_SWEEP_SPECS(X)
 #undef X

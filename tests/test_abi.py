@@ -81,10 +81,21 @@ def test_unsupported_sizes_are_reported():
     for ph, pw in ((1024, 1024), (128, 256), (512, 64)):
         rc, _, msg = init_rc(ph=ph, pw=pw)
         assert rc == B.OCSC_E_UNSUPPORTED and "256, 512" in msg, (ph, pw)
+    # the Sherman-Morrison form holds C_p in LDS: FP64 K <= 92, FP32 K <= 128
     o = B.ocsc_default_opts()
     o.precision = B.OCSC_FP64
-    rc, _, msg = init_rc(K=200, opts=ctypes.byref(o))
+    rc, _, msg = init_rc(K=93, opts=ctypes.byref(o))
     assert rc == B.OCSC_E_UNSUPPORTED and "LDS" in msg
+    o.precision = B.OCSC_FP32
+    rc, _, msg = init_rc(K=129, opts=ctypes.byref(o))
+    assert rc == B.OCSC_E_UNSUPPORTED and "Cholesky form" in msg
+    # the largest sizes pass the checks (without a GPU the call then fails in HIP)
+    for prec, K in ((B.OCSC_FP64, 92), (B.OCSC_FP32, 128)):
+        o.precision = prec
+        rc, ctx, msg = init_rc(K=K, ph=32, pw=32, opts=ctypes.byref(o))
+        assert rc in (B.OCSC_OK, B.OCSC_E_HIP), (K, msg)
+        if rc == B.OCSC_OK:
+            B.load().ocsc_destroy(ctx)
 
 
 def test_null_context_calls():

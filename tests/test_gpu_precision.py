@@ -23,7 +23,7 @@ def images(n, ph, K_true, seed):
 
 
 @pytest.mark.parametrize("K,B,batches,n", [(16, 8, 2, 64), (100, 6, 2, 64), (40, 70, 1, 64), (256, 4, 2, 32),
-                                           (200, 3, 1, 32), (129, 2, 1, 32)])
+                                           (200, 3, 1, 32), (129, 2, 1, 32), (120, 3, 1, 32)])
 def test_cholesky_form_matches_oracle(K, B, batches, n):
     """K > 128 takes the block (Schur complement) inverse and the streaming D-step."""
     say(f"case precision form K={K} B={B} grid {n}")
