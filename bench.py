@@ -9,8 +9,9 @@ before the timed region.
 
 Prints one JSON line.  The roofline object covers the dominant kernel, the
 D-step sweep that streams the inverse history matrices C (K x K per
-frequency), timed with HIP events on the library's stream over the timed
-region.  The cpu_baseline object times the FP64 oracle on a bounded sample of
+frequency), timed over the timed region by HIP events that each sweep launch
+carries on the library's stream (they take the kernel's own start and end and
+add no packets between kernels).  The cpu_baseline object times the FP64 oracle on a bounded sample of
 the same workload on the host cores.
 """
 from __future__ import annotations
@@ -406,7 +407,7 @@ def main():
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    # timed region: HIP events bracket only the D-step sweeps (the dominant kernel)
+    # timed region: each D-step sweep (the dominant kernel) carries its own start/stop events
     L.ocsc_profile_enable(g.ctx, ["dstep"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()

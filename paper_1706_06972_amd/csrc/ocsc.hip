@@ -3,6 +3,7 @@
 // One context owns the learner state of Algorithm 3 on one device and a HIP
 // stream; every call validates its arguments on the host, then enqueues the
 // kernels of kernels.hpp on that stream.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -156,6 +157,43 @@ struct ProfScope {
     if (c->prof_live.size() >= 4096) prof_collect(c);
   }
 };
+
+// One timed kernel launch: the start and stop events travel with the launch
+// (hipExtLaunchKernelGGL) and take the kernel's own start and end, so no
+// event packets sit between the kernels of the stream.  Without timing the
+// launch is a plain one.
+struct LaunchTimer {
+  ocsc_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  LaunchTimer(ocsc_ctx* c_, int cls_) : c(c_), cls(cls_) {
+    if (c->prof_mask & (1u << cls)) {
+      a = ev_get(c);
+      b = a ? ev_get(c) : nullptr;
+      if (a && !b) {
+        c->ev_pool.push_back(a);
+        a = nullptr;
+      }
+    }
+  }
+  void launched() {
+    if (!a) return;
+    c->prof_live.push_back({cls, a, b});
+    a = b = nullptr;
+    if (c->prof_live.size() >= 4096) prof_collect(c);
+  }
+  ~LaunchTimer() {
+    if (a) {
+      c->ev_pool.push_back(a);
+      c->ev_pool.push_back(b);
+    }
+  }
+};
+#define TIMED_LAUNCH(tm, kernel, grid, block, smem, stream, ...)                                    \
+  do {                                                                                             \
+    if ((tm).a) hipExtLaunchKernelGGL(kernel, grid, block, smem, stream, (tm).a, (tm).b, 0, __VA_ARGS__); \
+    else hipLaunchKernelGGL(kernel, grid, block, smem, stream, __VA_ARGS__);                       \
+  } while (0)
 
 // ---------------------------------------------------------------- dispatch
 // 128 x 128 planes: 16 waves per workgroup, so that one CU has enough waves
@@ -422,7 +460,7 @@ int sweep_nvm_for(int K, int fpb, size_t sr) {
 // One D-step sweep; nfold > 0 folds the kept spectra of nfold samples first.
 template <typename T>
 int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dout, int cls) {
-  ProfScope ps(c, cls);
+  LaunchTimer tm(c, cls);
   // successive sweeps alternate direction, so the tail of one sweep is still
   // in the Infinity Cache at the head of the next
   const int reverse = (int)(c->sweep_count & 1u);
@@ -431,19 +469,19 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
     // K > 128 (Cholesky form, no fold): C_p streamed through LDS
     if (nfold || !dout) return fail(c, OCSC_E_STATE, "internal: no history fold in the K > 128 form");
     if constexpr (std::is_same<T, float>::value) {
-      hipLaunchKernelGGL(k_dstep_stream, dim3(c->Pf), dim3(256), 0, c->stream, (const float*)c->Cm, c->fs, c->K,
-                         c->Pf, (const float2*)rhs, (float2*)dout);
+      TIMED_LAUNCH(tm, k_dstep_stream, dim3(c->Pf), dim3(256), 0, c->stream, (const float*)c->Cm, c->fs, c->K,
+                   c->Pf, (const float2*)rhs, (float2*)dout);
       LAUNCHED(c);
+      tm.launched();
       return OCSC_OK;
     }
     return fail(c, OCSC_E_UNSUPPORTED, "the K > 128 form is FP32");
   }
   const size_t smem = (dout && nfold == 0) ? c->plain_smem : c->sweep_smem;
 #define OCSC_SWEEP(KT, FPB)                                                                                  \
-  hipLaunchKernelGGL((k_dict_sweep<T, KT, FPB>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,               \
-                     (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh,     \
-                     nfold, (cx<T>*)rfold, (cx<T>*)dout, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg, \
-                     reverse)
+  TIMED_LAUNCH(tm, (k_dict_sweep<T, KT, FPB>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,                 \
+               (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh,           \
+               nfold, (cx<T>*)rfold, (cx<T>*)dout, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg, reverse)
   bool done = false;
 #define X(TT, KT, FPB)                                                          \
   if constexpr (std::is_same<T, TT>::value) {                                  \
@@ -460,6 +498,7 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
   }
 #undef OCSC_SWEEP
   LAUNCHED(c);
+  tm.launched();
   return OCSC_OK;
 }
 
