@@ -370,7 +370,7 @@ def main():
                     help="only run device copies of MIB MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single MI355X (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)

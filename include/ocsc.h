@@ -51,7 +51,7 @@ typedef enum {
   OCSC_E_OOM = -3,         /* device allocation failed */
   OCSC_E_HIP = -4,         /* a HIP runtime call failed; text in ocsc_last_error */
   OCSC_E_NUMERIC = -5,     /* non-finite input or result */
-  OCSC_E_UNSUPPORTED = -6  /* valid request this build has no kernel for */
+  OCSC_E_UNSUPPORTED = -6  /* valid request the library has no kernel for */
 } ocsc_status;
 
 typedef enum {

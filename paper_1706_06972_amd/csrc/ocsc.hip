@@ -1195,7 +1195,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   if (!std::isfinite(o.rho_dict)) return fail(nullptr, OCSC_E_INVALID_ARG, "rho_dict must be finite");
   if (big_grid(pad_h, pad_w) && !((pad_h == 256 || pad_h == 512) && (pad_w == 256 || pad_w == 512)))
     return fail(nullptr, OCSC_E_UNSUPPORTED,
-                "this build has plane kernels for grids with both sides <= 128 or both sides in {256, 512}");
+                "plane kernels exist for grids with both sides <= 128 or both sides in {256, 512}");
   if (big_grid(pad_h, pad_w) && (size_t)o.max_batch * K > 65535)
     return fail(nullptr, OCSC_E_UNSUPPORTED, "max_batch * K must be <= 65535 on grids above 128");
   const size_t sr = o.precision == OCSC_FP64 ? 8 : 4;
