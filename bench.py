@@ -354,6 +354,57 @@ def copy_calibration(mib: int) -> None:
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 5}), flush=True)
 
 
+def quality_run(dev, n_train: int = 1000, n_test: int = 16, passes: int = 2, j_eval: int = 200):
+    """Quality on the synthetic stand-in, as the paper's section 4 measures it:
+    test objective and PSNR of held-out images coded against D_0, against the
+    exported learned dictionary and against the generator's ground-truth
+    filters, with the learner's J_z code iterations and with J_eval (codes
+    close to converged); per pass the relative changes of the codes and of the
+    dictionary (the quantities of the stopping rule) and the test objective;
+    and the code-ADMM objective against the iteration count J (the code side
+    of the synthetic study of Appendix B).  B = 1, FP32, the workload's K,
+    lambda and rho."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1706_06972_amd import evaluate as E
+    from paper_1706_06972_amd.ocsc import OCSC
+
+    wl = synth.WORKLOADS[WORKLOAD]
+    order = synth.pass_order(wl.n_images, wl.seed, 0)
+    train = torch.as_tensor(synth.images(wl, order[:n_train]), dtype=torch.float32, device=dev).contiguous()
+    test_np = synth.images(wl, order[-n_test:])   # never presented for learning
+    test = torch.as_tensor(test_np, dtype=torch.float32, device=dev).contiguous()
+    peak = float(np.abs(test_np).max())
+
+    def make(J=wl.iters_code):
+        return OCSC(wl.K, wl.filt_h, wl.filt_w, wl.pad_h, wl.pad_w, wl.lam, wl.rho, iters_code=J,
+                    iters_dict=wl.iters_dict, precision="f32", device=dev)
+
+    def scores(D):
+        out = {}
+        for J in (wl.iters_code, j_eval):
+            m = make(J)
+            m.set_dictionary(D)
+            out[f"J{J}"] = {"test_objective": E.test_objective(m, test), "psnr_db": E.psnr(m, test, peak)}
+            m.close()
+        return out
+
+    D0 = synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed)
+    g = make()
+    g.set_dictionary(D0)
+    t0 = time.perf_counter()
+    hist = E.learn(g, train, passes, tol=1e-3, order_seed=wl.seed + 3, test_xs=test)
+    torch.cuda.synchronize()
+    learn_s = time.perf_counter() - t0
+    D = g.get_dictionary()
+    g.close()
+    study = E.code_admm_study(make, D, test[:4], [1, 2, 5, 10, 20, 50, 100, 200])
+    return {"train_images": n_train, "test_images": n_test, "passes": passes, "psnr_peak": peak,
+            "initial": scores(D0), "learned": scores(D), "ground_truth_filters": scores(synth.truth_filters(wl)),
+            "per_pass": hist, "learn_seconds": learn_s, "code_admm_objective_vs_iters": study}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +417,8 @@ def main():
                     help="also time minibatch steps of this many samples (0: skip)")
     ap.add_argument("--coding", type=int, default=1, help="also time coding on 64..512 grids (0: skip)")
     ap.add_argument("--served", type=int, default=1, help="also run the serving form (0: skip)")
+    ap.add_argument("--quality", type=int, default=1,
+                    help="also measure test objective / PSNR before and after learning (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -468,6 +521,7 @@ def main():
     out["grouped"] = grouped_run(dev) if args.coding else None
     out["copy_ceiling"] = copy_ceiling(dev)
     out["served"] = served_run(dev) if args.served else None
+    out["quality"] = quality_run(dev) if args.quality else None
     if args.cpu_steps > 0:
         out["cpu_baseline"] = oracle_baseline(wl, args.cpu_steps)
     else:
