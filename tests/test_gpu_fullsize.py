@@ -1,0 +1,88 @@
+"""The minibatch forms at the full size of the 128x128, K=100 FP32 workload,
+in the launch configuration bench.py times (B = 64, shapes from
+ocsc_autotune), through the C ABI.
+
+The FP64 oracle codes about a second per sample here, so it is run on
+sampled outputs and the rest is checked through identities that hold at any
+size:
+* codes of four sampled samples of the minibatch against the oracle's codes
+  of the same samples (the code update is independent per sample);
+* at 32 sampled frequencies, from the library's own last Z-step spectra:
+  G_p = sum_b conj(z_bp) x_bp and H_p = sum_b conj(z_bp) z_bp^T (eqs.
+  A_update, B_update, unnormalised), and C_p (H_p + rho_d I) = I for the
+  inverse the library keeps (Sherman-Morrison fold, or the FP64 Cholesky
+  inverse of the precision form);
+* after the DictOCSC call: every V_k in the unit ball.
+The D-step and V-step kernels of this size (K = 100 on 128 x 128) are checked
+against the oracle at B = 1 by the parity tests.
+Tolerance 1e-3 (norm-wise relative), as for every FP32 context.
+"""
+import numpy as np
+import pytest
+
+import oracle.ocsc_oracle as O
+import synth
+from tests.gpu_util import rel, say, spectra, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+WL = synth.WORKLOADS["ocsc_128x128_k100_f32"]
+B = 64
+
+
+def packed(flat, K, idx):
+    """[Pf][K][K] packed Hermitian reals (Re on/above the diagonal, Im below)
+    at the frequencies idx -> complex (len(idx), K, K)."""
+    R = flat.reshape(-1, K, K)[idx]
+    up = np.triu(R)
+    re = up + np.triu(R, 1).transpose(0, 2, 1)
+    lo = np.tril(R, -1)
+    im = lo.transpose(0, 2, 1) - lo
+    return re + 1j * im
+
+
+@pytest.mark.parametrize("cholesky", [False, True])
+def test_minibatch_forms_at_full_size(cholesky):
+    say(f"case full size 128x128 K=100 B=64 {'precision' if cholesky else 'Sherman-Morrison'} form")
+    from paper_1706_06972_amd.ocsc import OCSC
+    K, ph, pw = WL.K, WL.pad_h, WL.pad_w
+    order = synth.pass_order(WL.n_images, WL.seed, 0)[:B]
+    xs = synth.images(WL, order)
+    D0 = synth.initial_dictionary(K, WL.filt_h, WL.filt_w, WL.seed)
+    g = OCSC(K, WL.filt_h, WL.filt_w, ph, pw, WL.lam, WL.rho, iters_code=WL.iters_code,
+             iters_dict=WL.iters_dict, max_batch=B, precision="f32", cholesky=cholesky)
+    g.set_dictionary(D0)
+    shape, _ = g.autotune(B)
+    g.set_tuning(**shape)
+    U = to_np(g.code_update(xs))
+    o = O.OCSC(K, WL.filt_h, WL.filt_w, ph, pw, WL.lam, WL.rho, iters_code=WL.iters_code,
+               iters_dict=WL.iters_dict)
+    o.set_dictionary(D0)
+    picks = [0, 21, 42, 63]
+    Uo = o.code_update(xs[picks])
+    assert np.count_nonzero(Uo) > 0
+    err_codes = rel(U[picks], Uo)
+    Zh = spectra(to_np(g.state("zhat")), (B, K), ph, pw).reshape(B, K, -1)   # the library's own spectra
+    xh = spectra(to_np(g.state("xhat")), (B,), ph, pw).reshape(B, -1)
+    g.history_accumulate()
+    Pf = Zh.shape[-1]
+    idx = np.random.default_rng(7).choice(Pf, 32, replace=False)
+    z = Zh[:, :, idx].transpose(2, 0, 1)                       # (32, B, K)
+    H = np.matmul(np.conj(z).transpose(0, 2, 1), z)            # H_p[k][l] = sum_b conj(z_bk) z_bl
+    Gs = np.einsum("pbk,bp->pk", np.conj(z), xh[:, idx])
+    G = spectra(to_np(g.state("G")), (K,), ph, pw).reshape(K, -1)
+    err_G = rel(G[:, idx].T, Gs)
+    A = H + WL.rho * ph * pw * np.eye(K)                      # rho_d = rho P (eq. sub_d_sol)
+    C = packed(to_np(g.state("cinv")), K, idx)
+    res = np.linalg.norm(A @ C - np.eye(K), axis=(-2, -1)) / np.sqrt(K)
+    err_H = rel(packed(to_np(g.state("H")), K, idx), H) if cholesky else 0.0
+    g.dict_update()
+    Vn = np.linalg.norm(to_np(g.state("V")).reshape(K, -1), axis=1)
+    say(f"  codes {err_codes:.2e}  G {err_G:.2e}  H {err_H:.2e}  solve residual {res.max():.2e}  "
+        f"max ||V_k|| {Vn.max():.6f}")
+    assert err_codes < 1e-3 and err_G < 1e-3 and err_H < 1e-3
+    assert res.max() < 1e-3
+    assert Vn.max() <= 1.0 + 1e-5
+    g.close()
+
