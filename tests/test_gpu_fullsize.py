@@ -1,6 +1,7 @@
-"""The minibatch forms at the full size of the 128x128, K=100 FP32 workload,
-in the launch configuration bench.py times (B = 64, shapes from
-ocsc_autotune), through the C ABI.
+"""The minibatch forms at the full size of the 128x128 FP32 workload, in the
+launch configurations bench.py times (B = 64, shapes from ocsc_autotune):
+K = 100 in both forms, and K = 256 in the precision form (block inverse and
+streamed D-step), through the C ABI.
 
 The FP64 oracle codes about a second per sample here, so it is run on
 sampled outputs and the rest is checked through identities that hold at any
@@ -13,8 +14,8 @@ size:
   inverse the library keeps (Sherman-Morrison fold, or the FP64 Cholesky
   inverse of the precision form);
 * after the DictOCSC call: every V_k in the unit ball.
-The D-step and V-step kernels of this size (K = 100 on 128 x 128) are checked
-against the oracle at B = 1 by the parity tests.
+The D-step and V-step kernels of K = 100 on 128 x 128 are checked against the
+oracle at B = 1 by the parity tests, those of K = 256 at smaller grids.
 Tolerance 1e-3 (norm-wise relative), as for every FP32 context.
 """
 import numpy as np
@@ -42,11 +43,11 @@ def packed(flat, K, idx):
     return re + 1j * im
 
 
-@pytest.mark.parametrize("cholesky", [False, True])
-def test_minibatch_forms_at_full_size(cholesky):
-    say(f"case full size 128x128 K=100 B=64 {'precision' if cholesky else 'Sherman-Morrison'} form")
+@pytest.mark.parametrize("K,cholesky", [(100, False), (100, True), (256, True)])
+def test_minibatch_forms_at_full_size(K, cholesky):
+    say(f"case full size 128x128 K={K} B=64 {'precision' if cholesky else 'Sherman-Morrison'} form")
     from paper_1706_06972_amd.ocsc import OCSC
-    K, ph, pw = WL.K, WL.pad_h, WL.pad_w
+    ph, pw = WL.pad_h, WL.pad_w
     order = synth.pass_order(WL.n_images, WL.seed, 0)[:B]
     xs = synth.images(WL, order)
     D0 = synth.initial_dictionary(K, WL.filt_h, WL.filt_w, WL.seed)
