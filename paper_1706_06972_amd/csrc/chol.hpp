@@ -107,13 +107,15 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
         re[tt] = mfma_bf16(aih, bih, re[tt]);
         re[tt] = mfma_bf16(aih, bil, re[tt]);
         re[tt] = mfma_bf16(ail, bih, re[tt]);
-        // Im H_ij = sum_b zr_i zi_j - zi_i zr_j
-        im1[tt] = mfma_bf16(arh, bih, im1[tt]);
-        im1[tt] = mfma_bf16(arh, bil, im1[tt]);
-        im1[tt] = mfma_bf16(arl, bih, im1[tt]);
-        im2[tt] = mfma_bf16(aih, brh, im2[tt]);
-        im2[tt] = mfma_bf16(aih, brl, im2[tt]);
-        im2[tt] = mfma_bf16(ail, brh, im2[tt]);
+        // Im H_ij = sum_b zr_i zi_j - zi_i zr_j, formed transposed (row j,
+        // column i: the j-block as operand A) so that the lower triangle of
+        // the R-form, which holds it, is written row by row
+        im1[tt] = mfma_bf16(bih, arh, im1[tt]);
+        im1[tt] = mfma_bf16(bil, arh, im1[tt]);
+        im1[tt] = mfma_bf16(bih, arl, im1[tt]);
+        im2[tt] = mfma_bf16(brh, aih, im2[tt]);
+        im2[tt] = mfma_bf16(brl, aih, im2[tt]);
+        im2[tt] = mfma_bf16(brh, ail, im2[tt]);
       }
     }
   }
@@ -124,11 +126,10 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
     if (tile_of(tt) >= NTILE) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = tri[tt] * 16 + 4 * lg + r, j = trj[tt] * 16 + li;
-      if (i < K && j < K && i <= j) {
-        R[i * ld + j] += re[tt][r];
-        if (i < j) R[j * ld + i] += im1[tt][r] - im2[tt][r];
-      }
+      const int i = tri[tt] * 16 + 4 * lg + r, j = trj[tt] * 16 + li;   // Re H_ij at R[i][j], i <= j
+      if (i < K && j < K && i <= j) R[i * ld + j] += re[tt][r];
+      const int jt = trj[tt] * 16 + 4 * lg + r, it = tri[tt] * 16 + li;  // Im H_it,jt at R[jt][it], it < jt
+      if (it < K && jt < K && it < jt) R[jt * ld + it] += im1[tt][r] - im2[tt][r];
     }
   }
   if (split == 0) {
