@@ -218,7 +218,10 @@ int ocsc_dict_update_group(ocsc_ctx* const* ctxs, int n);
  *   x_dev: real [B][pad_h][pad_w]; codes_dev: real [B][K][pad_h][pad_w];
  *   out_host: B doubles in host memory.  Waits for completion.
  * May overwrite the library's code workspace, but not the spectra kept for
- * ocsc_history_accumulate.  1 <= B <= max_batch.
+ * ocsc_history_accumulate.  1 <= B <= max_batch.  OCSC_E_NUMERIC when a value
+ * is not finite (the calls that do not wait never inspect values: a
+ * non-finite sample propagates through the codes and the history, and this
+ * call, ocsc_surrogate and ocsc_diagnostics report it).
  */
 int ocsc_objective(ocsc_ctx* ctx, const void* x_dev, const void* codes_dev, int B,
                    double* out_host);

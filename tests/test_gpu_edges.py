@@ -140,3 +140,27 @@ def test_unit_impulse_filter_gives_the_soft_threshold(prec):
     o.set_dictionary(np.ones((1, 1, 1)))
     assert rel(U, o.code_update(x[None])[0, 0]) < TOL[prec]
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_non_finite_input_is_reported(prec):
+    """A sample with a NaN: the asynchronous calls enqueue as usual; the calls
+    that bring results back to the host report OCSC_E_NUMERIC."""
+    say(f"case non-finite input {prec}")
+    from paper_1706_06972_amd import ocsc as L
+    from paper_1706_06972_amd.ocsc import OCSC
+    K, ph, pw = 4, 32, 32
+    g = OCSC(K, 5, 5, ph, pw, 1.0, 1.0, precision=prec)
+    g.set_dictionary(synth.initial_dictionary(K, 5, 5, 0))
+    x = images(1, ph, pw, seed=8)
+    x[0, 3, 4] = np.nan
+    U = g.code_update(x)
+    with pytest.raises(L.OcscError) as e:
+        g.objective(x, U)
+    assert e.value.status == L.OCSC_E_NUMERIC
+    g.history_accumulate()
+    g.dict_update()
+    with pytest.raises(L.OcscError) as e:
+        g.diagnostics()
+    assert e.value.status == L.OCSC_E_NUMERIC
+    g.close()
