@@ -345,16 +345,22 @@ __device__ __forceinline__ void run_store(const cx<T>* rb, cx<T>* __restrict__ d
 // nfold > 0: before the D-step the kept spectra of nfold samples are folded
 // into the history in sample order (eqs. B_update and C_update):
 //   u = conj(z_p);  G_p += u x_p;  v = C_p u;  C_p <- C_p - v v^H / (1 + u^H v),
+// with z_p read from Zh ([B][K][Pf], one sample) or, for several samples, from
+// the frequency-major copy Zt ([Pf][ldt][K], each sample's K values
+// contiguous), fetched a few samples ahead;
 // the updated C_p is written back and the right-hand side is the updated G_p
 // (the first DictOCSC iterate, from V = Theta = 0).  With rfold (warm start)
 // the right-hand side is instead the carried G + rho_d (F(V) - Theta), which
 // the fold advances by the same increments as G and writes back.
 // dout == nullptr: fold only.
+// MF: compiled for nfold > 1 only (the multi-sample fold's registers are then
+// not charged to the plain and one-sample sweeps, and the other way round).
 // ---------------------------------------------------------------------------
-template <typename T, int KT, int FPB>
+template <typename T, int KT, int FPB, bool MF>
 __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>* __restrict__ G,
                                                     const cx<T>* __restrict__ rhs,
                                                     const cx<T>* __restrict__ Zh,
+                                                    const cx<T>* __restrict__ Zt, int ldt,
                                                     const cx<T>* __restrict__ xh, int nfold,
                                                     cx<T>* __restrict__ rfold,
                                                     cx<T>* __restrict__ dout,
@@ -422,7 +428,7 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       const int sn = slot_of(s + 1);
       slot_fetch<NVM>(reg, reinterpret_cast<const v4f*>(Cm + (size_t)sn * fpb * fs), slot_vecs(sn), tid);
     }
-    if (plain) {
+    if (!MF && plain) {
       // d_p replaces its right-hand side in the run buffer (p - f0 < slots_per_wg * fpb)
       cx<T>* xr = rb + (size_t)(p - f0) * K;
       if constexpr (CT) {
@@ -432,7 +438,7 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       } else {
         herm_matvec<T>(R, K, ld, xr, xr, rpart, lt, tpg, ns);
       }
-    } else if (nfold == 1) {
+    } else if (!MF) {
       // one sample: v = C u and g = C G_new in one pass; d = g - beta v (v^H G_new)
       if (ok && lt < K) {
         const cx<T> u = cconj<T>(Zh[(size_t)lt * Pf + p]);
@@ -477,24 +483,47 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
       const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
       for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
-    } else {
-      // several samples, folded one after another in sample order
-      cx<T> dsum = mk<T>(0, 0);
-      for (int b = 0; b < nfold; ++b) {
-        if (ok && lt < K) {
-          const cx<T> u = cconj<T>(Zh[((size_t)b * K + lt) * Pf + p]);
-          const cx<T> du = cmul<T>(u, xh[(size_t)b * Pf + p]);
-          xv[lt] = u;
-          G[(size_t)lt * Pf + p] = cadd<T>(G[(size_t)lt * Pf + p], du);
-          dsum = cadd<T>(dsum, du);
+    } else if constexpr (MF) {
+      // several samples, folded one after another in sample order; z and x of
+      // sample b + FQ are fetched while sample b is folded, and G_p stays in a
+      // register until the last sample (the same sums in the same order)
+      constexpr int FQ = sizeof(T) == 4 ? 4 : 2;
+      cx<T> dsum = mk<T>(0, 0), gacc = mk<T>(0, 0);
+      cx<T> zq[FQ], xq[FQ];
+      const cx<T>* zt = Zt + (size_t)p * ldt * K;
+      if (ok && lt < K) {
+        gacc = G[(size_t)lt * Pf + p];
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+          zq[q] = q < nfold ? zt[(size_t)q * K + lt] : mk<T>(0, 0);
+          xq[q] = q < nfold ? xh[(size_t)q * Pf + p] : mk<T>(0, 0);
         }
-        __syncthreads();
-        herm_matvec<T>(R, K, ld, xv, vv, part, lt, tpg, ns);
-        T acc = 0;
-        if (lt < K) acc = xv[lt].x * vv[lt].x + xv[lt].y * vv[lt].y;   // Re(u^H v)
-        acc = group_sum<T>(acc, tpg, wsum);
-        herm_rank1<T>(R, K, ld, vv, (T)1 / ((T)1 + acc), lt, tpg, ns);
       }
+      for (int b0 = 0; b0 < nfold; b0 += FQ) {
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+          const int b = b0 + q;
+          if (b >= nfold) break;   // the same for every thread
+          if (ok && lt < K) {
+            const cx<T> u = cconj<T>(zq[q]);
+            const cx<T> du = cmul<T>(u, xq[q]);
+            if (b + FQ < nfold) {
+              zq[q] = zt[(size_t)(b + FQ) * K + lt];
+              xq[q] = xh[(size_t)(b + FQ) * Pf + p];
+            }
+            xv[lt] = u;
+            gacc = cadd<T>(gacc, du);
+            dsum = cadd<T>(dsum, du);
+          }
+          __syncthreads();
+          herm_matvec<T>(R, K, ld, xv, vv, part, lt, tpg, ns);
+          T acc = 0;
+          if (lt < K) acc = xv[lt].x * vv[lt].x + xv[lt].y * vv[lt].y;   // Re(u^H v)
+          acc = group_sum<T>(acc, tpg, wsum);
+          herm_rank1<T>(R, K, ld, vv, (T)1 / ((T)1 + acc), lt, tpg, ns);
+        }
+      }
+      if (ok && lt < K) G[(size_t)lt * Pf + p] = gacc;
       v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
       const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
       for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
@@ -503,7 +532,7 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
         rfold[(size_t)lt * Pf + p] = rn;
         if (dout) xv[lt] = rn;
       } else if (dout && ok && lt < K) {
-        xv[lt] = G[(size_t)lt * Pf + p];
+        xv[lt] = gacc;
       }
       __syncthreads();
       if (dout) herm_matvec<T>(R, K, ld, xv, yv, part, lt, tpg, ns);

@@ -72,7 +72,7 @@ struct ocsc_ctx {
   // spectrum of given filters, exported filters, reduction partials, results
   void *Hm = nullptr, *Ubuf = nullptr, *Dv = nullptr, *Dexp = nullptr;
   void* Yb = nullptr;   // inverse column pass of the code spectra (two-pass grids)
-  void* Zt = nullptr;   // last code spectra frequency-major [Pf][max_batch][K] (Cholesky form)
+  void* Zt = nullptr;   // last code spectra frequency-major [Pf][max_batch][K] (Cholesky form, max_batch > 1)
   double *pend = nullptr, *hacc = nullptr, *dpart = nullptr, *dres = nullptr;
   // host-side bookkeeping
   int64_t t = 0;
@@ -415,8 +415,9 @@ bool zstep_shape(ocsc_ctx* c, int off, int B, int first, cx<T>* Zt) {
 template <typename T>
 int launch_zstep(ocsc_ctx* c, int off, int B, int first, bool last) {
   ProfScope ps(c, OCSC_KC_ZSTEP);
-  // the last iterate also goes frequency-major to the matrix-core history update
-  cx<T>* Zt = (last && c->chol) ? (cx<T>*)c->Zt : nullptr;
+  // the last iterate also goes frequency-major, for the matrix-core history
+  // update and for the fold of several samples
+  cx<T>* Zt = (last && c->Zt) ? (cx<T>*)c->Zt : nullptr;
   const int K = c->K;
   bool ok = false;
   if (K <= 16) ok = zstep_shape<T, 1>(c, off, B, first, Zt);
@@ -478,10 +479,17 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
     return fail(c, OCSC_E_UNSUPPORTED, "the K > 128 form is FP32");
   }
   const size_t smem = (dout && nfold == 0) ? c->plain_smem : c->sweep_smem;
-#define OCSC_SWEEP(KT, FPB)                                                                                  \
-  TIMED_LAUNCH(tm, (k_dict_sweep<T, KT, FPB>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,                 \
-               (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->xh,           \
-               nfold, (cx<T>*)rfold, (cx<T>*)dout, c->K, c->Pf, c->fpb, c->fs, c->slots_per_wg, reverse)
+  const bool mf = nfold > 1;
+#define OCSC_SWEEP_MF(KT, FPB, MF)                                                                            \
+  TIMED_LAUNCH(tm, (k_dict_sweep<T, KT, FPB, MF>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,             \
+               (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->Zt, c->maxB,  \
+               (const cx<T>*)c->xh, nfold, (cx<T>*)rfold, (cx<T>*)dout, c->K, c->Pf, c->fpb, c->fs,            \
+               c->slots_per_wg, reverse)
+#define OCSC_SWEEP(KT, FPB)                 \
+  do {                                      \
+    if (mf) OCSC_SWEEP_MF(KT, FPB, true);   \
+    else OCSC_SWEEP_MF(KT, FPB, false);     \
+  } while (0)
   bool done = false;
 #define X(TT, KT, FPB)                                                          \
   if constexpr (std::is_same<T, TT>::value) {                                  \
@@ -497,6 +505,7 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
     else OCSC_SWEEP(0, 0);
   }
 #undef OCSC_SWEEP
+#undef OCSC_SWEEP_MF
   LAUNCHED(c);
   tm.launched();
   return OCSC_OK;
@@ -697,7 +706,7 @@ int code_group_t(ocsc_ctx* const* cs, const void* const* xs, const int* Bs, void
     g.W[s] = (T*)c->W;
     g.Yb[s] = (cx<T>*)c->Yb;
     g.U[s] = U[s];
-    g.Zt[s] = c->chol ? (cx<T>*)c->Zt : nullptr;
+    g.Zt[s] = (cx<T>*)c->Zt;
     g.twH[s] = (const cx<T>*)c->twH;
     g.twW[s] = (const cx<T>*)c->twW;
     g.kappa[s] = (T)(c->lam / c->rho);
@@ -1290,9 +1299,11 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
   if (!c->dstream && std::max(c->sweep_smem, c->plain_smem) > 64 * 1024) {
-    const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0>, (const void*)k_dict_sweep<float, 0, 0>,
-                         (const void*)k_dict_sweep<double, -1, 0>, (const void*)k_dict_sweep<float, -1, 0>
-#define X(T, KT, FPB) , (const void*)k_dict_sweep<T, KT, FPB>
+    const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0, false>, (const void*)k_dict_sweep<float, 0, 0, false>,
+                         (const void*)k_dict_sweep<double, -1, 0, false>, (const void*)k_dict_sweep<float, -1, 0, false>,
+                         (const void*)k_dict_sweep<double, 0, 0, true>, (const void*)k_dict_sweep<float, 0, 0, true>,
+                         (const void*)k_dict_sweep<double, -1, 0, true>, (const void*)k_dict_sweep<float, -1, 0, true>
+#define X(T, KT, FPB) , (const void*)k_dict_sweep<T, KT, FPB, false>, (const void*)k_dict_sweep<T, KT, FPB, true>
                          OCSC_SWEEP_SPECS(X)
 #undef X
     };
@@ -1324,7 +1335,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
       {&c->Ubuf, c->keep_hist ? B * K_ * c->P * sr : 0},
       {(void**)&c->pend, c->keep_hist ? 2 * B * 64 * sizeof(double) : 0},
       {&c->Yb, c->big ? B * K_ * Pf * sc : 0},
-      {&c->Zt, c->chol ? Pf * B * K_ * sc : 0},
+      {&c->Zt, (c->chol || B > 1) ? Pf * B * K_ * sc : 0},
       {&c->Wchol, c->dstream ? (size_t)5 * c->chol_chunk * CB_N * CB_N * 16 : 0}};
   for (auto& a : allocs) {
     if (a.n == 0) continue;
