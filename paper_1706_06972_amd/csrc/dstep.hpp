@@ -233,6 +233,106 @@ __device__ __forceinline__ void herm_rank1_ct(T* __restrict__ R, const cx<T>* v,
   __syncthreads();
 }
 
+// N sums over the tpg threads of one group at once (as group_sum; scratch:
+// N values per wave of the block).  Contains block-wide barriers when tpg > 64.
+template <typename T, int N>
+__device__ __forceinline__ void group_sum_vec(T (&v)[N], int tpg, T* scratch) {
+  const int w = tpg < 64 ? tpg : 64;
+#pragma unroll
+  for (int n = 0; n < N; ++n)
+    for (int off = w >> 1; off > 0; off >>= 1) v[n] += __shfl_xor(v[n], off, 64);
+  if (tpg <= 64) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+#pragma unroll
+    for (int n = 0; n < N; ++n) scratch[wave * N + n] = v[n];
+  __syncthreads();
+  const int nw = tpg >> 6, w0 = (wave / nw) * nw;
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    T s = 0;
+    for (int i = 0; i < nw; ++i) s += scratch[(w0 + i) * N + n];
+    v[n] = s;
+  }
+  __syncthreads();
+}
+
+// Y_n = C X_n for NB vectors in one pass over C (thread layout of
+// herm_matvec); X, Y: [NB][K]; part: [NB][ns][K].
+template <typename T, int NB>
+__device__ __forceinline__ void herm_matvec_n(const T* __restrict__ R, int K, int ld, const cx<T>* X, cx<T>* Y,
+                                              cx<T>* part, int lt, int tpg, int ns) {
+  const int chunk = (K + ns - 1) / ns;
+  for (int task = lt; task < K * ns; task += tpg) {
+    const int h = task / K, i = task - h * K;
+    const int j0 = h * chunk, j1 = min(K, j0 + chunk);
+    const T* rowp = R + i * ld;
+    const T* colp = R + i;
+    T yr[NB], yi[NB];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) yr[n] = yi[n] = 0;
+#pragma unroll 2
+    for (int j = j0; j < j1; ++j) {
+      const T p = rowp[j], q = colp[j * ld];
+      const bool up = j > i;
+      const T a = up ? p : q;
+      const T b = up ? q : -p;
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        const cx<T> xv = X[n * K + j];
+        yr[n] += a * xv.x - b * xv.y;
+        yi[n] += a * xv.y + b * xv.x;
+      }
+    }
+    if (i >= j0 && i < j1) {   // the loop took Im C_ii = -R[i][i]; it is zero
+      const T dg = rowp[i];
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        const cx<T> xv = X[n * K + i];
+        yr[n] -= dg * xv.y;
+        yi[n] += dg * xv.x;
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NB; ++n) part[(n * ns + h) * K + i] = mk<T>(yr[n], yi[n]);
+  }
+  __syncthreads();
+  for (int i = lt; i < K; i += tpg) {
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      cx<T> s = part[(n * ns) * K + i];
+      for (int h = 1; h < ns; ++h) s = cadd<T>(s, part[(n * ns + h) * K + i]);
+      Y[n * K + i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// C <- C - sum_n beta_n v_n v_n^H on the stored reals (as herm_rank1); V: [NB][K].
+template <typename T, int NB>
+__device__ __forceinline__ void herm_rank_n(T* __restrict__ R, int K, int ld, const cx<T>* V, const T (&beta)[NB],
+                                            int lt, int tpg, int ns) {
+  const int chunk = (K + ns - 1) / ns;
+  for (int task = lt; task < K * ns; task += tpg) {
+    const int h = task / K, i = task - h * K;
+    const int j0 = h * chunk, j1 = min(K, j0 + chunk);
+    cx<T> vi[NB];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) vi[n] = V[n * K + i];
+    T* rowp = R + i * ld;
+    for (int j = j0; j < j1; ++j) {
+      T dlt = 0;
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        const cx<T> vj = V[n * K + j];
+        dlt += beta[n] * (j >= i ? (vi[n].x * vj.x + vi[n].y * vj.y) : (vj.y * vi[n].x - vj.x * vi[n].y));
+      }
+      rowp[j] -= dlt;
+    }
+  }
+  __syncthreads();
+}
+
 // 16-byte vectors of one slot (fpb consecutive frequencies) held by one
 // thread: at most SWEEP_MAXV in the generic kernel (KT = 0), at most
 // SWEEP_MAXV_L in the generic kernel for large slots (KT = -1; one frequency of
@@ -484,44 +584,125 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
       for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
     } else if constexpr (MF) {
-      // several samples, folded one after another in sample order; z and x of
-      // sample b + FQ are fetched while sample b is folded, and G_p stays in a
-      // register until the last sample (the same sums in the same order)
-      constexpr int FQ = sizeof(T) == 4 ? 4 : 2;
+      // several samples, folded in sample order in blocks of FB (the
+      // recursion of eq. C_update applied FB times per pass over C).  With
+      // u_q = conj(z_q) and Y_q = C u_q for the block (one pass), M_jk = u_j^H Y_k:
+      //   v_j = C_(j-1) u_j = sum_k T_kj Y_k,
+      //   T_.j = e_j - sum_(i<j) beta_i (v_i^H u_j) T_.i,   v_i^H u_j = sum_k conj(T_ki) conj(M_jk),
+      //   beta_j = 1 / (1 + Re u_j^H v_j) = 1 / (1 + Re sum_k T_kj M_jk),
+      // then C <- C - sum_j beta_j v_j v_j^H in one pass.  The block's z and x
+      // come from the frequency-major copy (each sample's K values contiguous)
+      // and the next block's are fetched during this one; G_p stays in a
+      // register (the same sums in the same order as one sample at a time).
+      constexpr int FB = 3;
+      __shared__ T wsv[4 * 2 * FB * FB];
+      cx<T>* U = xv;                   // [FB][K]: u, then v
+      cx<T>* Y = xv + FB * K;          // [FB][K]
+      cx<T>* P = xv + 2 * FB * K;      // [FB][2][K] (the group's area holds >= 12 K)
+      const int ns2 = ns < 2 ? ns : 2;
       cx<T> dsum = mk<T>(0, 0), gacc = mk<T>(0, 0);
-      cx<T> zq[FQ], xq[FQ];
+      cx<T> zq[FB], xq[FB];
       const cx<T>* zt = Zt + (size_t)p * ldt * K;
+#pragma unroll
+      for (int q = 0; q < FB; ++q) zq[q] = xq[q] = mk<T>(0, 0);
       if (ok && lt < K) {
         gacc = G[(size_t)lt * Pf + p];
 #pragma unroll
-        for (int q = 0; q < FQ; ++q) {
-          zq[q] = q < nfold ? zt[(size_t)q * K + lt] : mk<T>(0, 0);
-          xq[q] = q < nfold ? xh[(size_t)q * Pf + p] : mk<T>(0, 0);
+        for (int q = 0; q < FB; ++q) {
+          if (q < nfold) {
+            zq[q] = zt[(size_t)q * K + lt];
+            xq[q] = xh[(size_t)q * Pf + p];
+          }
         }
       }
-      for (int b0 = 0; b0 < nfold; b0 += FQ) {
+      for (int b0 = 0; b0 < nfold; b0 += FB) {
+        if (lt < K) {
 #pragma unroll
-        for (int q = 0; q < FQ; ++q) {
-          const int b = b0 + q;
-          if (b >= nfold) break;   // the same for every thread
-          if (ok && lt < K) {
-            const cx<T> u = cconj<T>(zq[q]);
-            const cx<T> du = cmul<T>(u, xq[q]);
-            if (b + FQ < nfold) {
-              zq[q] = zt[(size_t)(b + FQ) * K + lt];
-              xq[q] = xh[(size_t)(b + FQ) * Pf + p];
+          for (int q = 0; q < FB; ++q) {
+            cx<T> u = mk<T>(0, 0);
+            if (ok && b0 + q < nfold) {
+              u = cconj<T>(zq[q]);
+              const cx<T> du = cmul<T>(u, xq[q]);
+              gacc = cadd<T>(gacc, du);
+              dsum = cadd<T>(dsum, du);
             }
-            xv[lt] = u;
-            gacc = cadd<T>(gacc, du);
-            dsum = cadd<T>(dsum, du);
+            U[q * K + lt] = u;
           }
-          __syncthreads();
-          herm_matvec<T>(R, K, ld, xv, vv, part, lt, tpg, ns);
-          T acc = 0;
-          if (lt < K) acc = xv[lt].x * vv[lt].x + xv[lt].y * vv[lt].y;   // Re(u^H v)
-          acc = group_sum<T>(acc, tpg, wsum);
-          herm_rank1<T>(R, K, ld, vv, (T)1 / ((T)1 + acc), lt, tpg, ns);
+          if (ok) {
+#pragma unroll
+            for (int q = 0; q < FB; ++q) {
+              const int bn = b0 + FB + q;
+              if (bn < nfold) {
+                zq[q] = zt[(size_t)bn * K + lt];
+                xq[q] = xh[(size_t)bn * Pf + p];
+              }
+            }
+          }
         }
+        __syncthreads();
+        herm_matvec_n<T, FB>(R, K, ld, U, Y, P, lt, tpg, ns2);
+        T m[2 * FB * FB];
+#pragma unroll
+        for (int j = 0; j < FB; ++j) {
+#pragma unroll
+          for (int k = 0; k < FB; ++k) {
+            T sr = 0, si = 0;
+            if (lt < K) {
+              const cx<T> uj = U[j * K + lt], yk = Y[k * K + lt];
+              sr = uj.x * yk.x + uj.y * yk.y;   // conj(u_j) y_k
+              si = uj.x * yk.y - uj.y * yk.x;
+            }
+            m[2 * (j * FB + k)] = sr;
+            m[2 * (j * FB + k) + 1] = si;
+          }
+        }
+        group_sum_vec<T, 2 * FB * FB>(m, tpg, wsv);
+        cx<T> tc[FB][FB];   // tc[k][j] = T_kj
+        T beta[FB];
+#pragma unroll
+        for (int j = 0; j < FB; ++j) {
+#pragma unroll
+          for (int k = 0; k < FB; ++k) tc[k][j] = mk<T>(k == j ? (T)1 : (T)0, 0);
+#pragma unroll
+          for (int i = 0; i < j; ++i) {
+            T cr = 0, ci = 0;   // v_i^H u_j
+#pragma unroll
+            for (int k = 0; k < FB; ++k) {
+              const T mr = m[2 * (j * FB + k)], mi = m[2 * (j * FB + k) + 1];
+              const cx<T> t = tc[k][i];   // conj(t) conj(M_jk) = conj(t M_jk)
+              cr += t.x * mr - t.y * mi;
+              ci -= t.x * mi + t.y * mr;
+            }
+            const T fr = beta[i] * cr, fi = beta[i] * ci;
+#pragma unroll
+            for (int k = 0; k < FB; ++k) {
+              const cx<T> t = tc[k][i];
+              tc[k][j] = mk<T>(tc[k][j].x - (fr * t.x - fi * t.y), tc[k][j].y - (fr * t.y + fi * t.x));
+            }
+          }
+          T sj = 0;   // Re u_j^H v_j
+#pragma unroll
+          for (int k = 0; k < FB; ++k) {
+            const T mr = m[2 * (j * FB + k)], mi = m[2 * (j * FB + k) + 1];
+            sj += tc[k][j].x * mr - tc[k][j].y * mi;
+          }
+          beta[j] = (T)1 / ((T)1 + sj);
+        }
+        __syncthreads();   // U (read for M) is overwritten by v below
+        if (lt < K) {
+#pragma unroll
+          for (int j = 0; j < FB; ++j) {
+            cx<T> v = mk<T>(0, 0);
+#pragma unroll
+            for (int k = 0; k < FB; ++k) {
+              const cx<T> y = Y[k * K + lt], t = tc[k][j];
+              v = mk<T>(v.x + t.x * y.x - t.y * y.y, v.y + t.x * y.y + t.y * y.x);
+            }
+            U[j * K + lt] = v;
+          }
+        }
+        __syncthreads();
+        herm_rank_n<T, FB>(R, K, ld, U, beta, lt, tpg, ns);
       }
       if (ok && lt < K) G[(size_t)lt * Pf + p] = gacc;
       v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
