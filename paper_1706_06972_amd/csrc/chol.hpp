@@ -204,7 +204,7 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
 // Blocking by CHOL_B cuts the barrier phases and the passes over the
 // trailing triangle by CHOL_B; the small diagonal blocks are factorised and
 // inverted redundantly by every thread in registers.
-// Dynamic LDS: (N(N+1)/2 + CHOL_B^2) complex doubles, N = K rounded up to
+// Dynamic LDS: (N(N+1)/2 + 2 CHOL_B^2) complex doubles, N = K rounded up to
 // CHOL_B (81 KB at K = 100, so that two workgroups of NT = 512 share a CU and
 // cover each other's serial diagonal-block phases).  The trailing updates are
 // flat lists of 2 x 2 tiles shared by all threads, so every step keeps the
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
   // identity (which stays outside the top-left K x K of the inverse)
   const int N = (K + CHOL_B - 1) / CHOL_B * CHOL_B;
   double2* L = reinterpret_cast<double2*>(smem_raw);
-  double2* xdb = L + N * (N + 1) / 2;   // [CHOL_B][CHOL_B]: factor (step 2) / inverse (step 3) of the diagonal block
+  double2* xdb = L + N * (N + 1) / 2;   // 2 x [CHOL_B][CHOL_B]: factor (step 2) / inverses (step 3) of diagonal blocks
   const int p = blockIdx.x, tid = threadIdx.x;
   const int ld = K + 1;
   for (int e = tid; e < N * (N + 1) / 2; e += NT) {
@@ -265,41 +265,56 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
   //    through LDS; each row below solves l_i D^H = a_i in place; then the
   //    trailing triangle takes the rank-CHOL_B update
   //    A_ik -= sum_c l_ic conj(l_kc) in 2 x 2 tiles.
-  for (int j = 0; j < N; j += CHOL_B) {
-    if (tid < 64) {
-      double2 d[CHOL_B][CHOL_B];
+  //    Look-ahead: the next diagonal block needs only this step's update of
+  //    its own entries.  Wave 0 applies that update in registers and factors
+  //    the block while the other waves update the rest of the trailing
+  //    triangle (its L entries are stale until the factor overwrites them in
+  //    the next step); the factors alternate between two LDS buffers.
+  auto factor_block = [&](const double2 (&a)[CHOL_B][CHOL_B], double2* dst) {   // a: lower triangle
+    double2 d[CHOL_B][CHOL_B];
 #pragma unroll
-      for (int c = 0; c < CHOL_B; ++c)
+    for (int c = 0; c < CHOL_B; ++c)
 #pragma unroll
-        for (int r = 0; r < CHOL_B; ++r) d[r][c] = make_double2(0.0, 0.0);
+      for (int r = 0; r < CHOL_B; ++r) d[r][c] = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int c = 0; c < CHOL_B; ++c) {
-        double sdiag = L[tri_idx(j + c, j + c)].x;
+    for (int c = 0; c < CHOL_B; ++c) {
+      double sdiag = a[c][c].x;
 #pragma unroll
-        for (int m = 0; m < c; ++m) sdiag -= d[c][m].x * d[c][m].x + d[c][m].y * d[c][m].y;
-        const double dc = sqrt(sdiag), ic = 1.0 / dc;
-        d[c][c] = make_double2(dc, ic);   // the diagonal is real; its .y carries 1 / d_cc
+      for (int m = 0; m < c; ++m) sdiag -= d[c][m].x * d[c][m].x + d[c][m].y * d[c][m].y;
+      const double dc = sqrt(sdiag), ic = 1.0 / dc;
+      d[c][c] = make_double2(dc, ic);   // the diagonal is real; its .y carries 1 / d_cc
 #pragma unroll
-        for (int r = c + 1; r < CHOL_B; ++r) {
-          double2 v = L[tri_idx(j + r, j + c)];
+      for (int r = c + 1; r < CHOL_B; ++r) {
+        double2 v = a[r][c];
 #pragma unroll
-          for (int m = 0; m < c; ++m) v = zsub_mulc(v, d[r][m], d[c][m]);
-          d[r][c] = make_double2(v.x * ic, v.y * ic);
-        }
+        for (int m = 0; m < c; ++m) v = zsub_mulc(v, d[r][m], d[c][m]);
+        d[r][c] = make_double2(v.x * ic, v.y * ic);
       }
-      if (tid == 0)
-#pragma unroll
-        for (int r = 0; r < CHOL_B; ++r)
-#pragma unroll
-          for (int c = 0; c < CHOL_B; ++c) xdb[r * CHOL_B + c] = d[r][c];
     }
-    __syncthreads();
+    if (tid == 0)
+#pragma unroll
+      for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+        for (int c = 0; c < CHOL_B; ++c) dst[r * CHOL_B + c] = d[r][c];
+  };
+  if (tid < 64) {
+    double2 a[CHOL_B][CHOL_B];
+#pragma unroll
+    for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+      for (int c = 0; c < CHOL_B; ++c) a[r][c] = c <= r ? L[tri_idx(r, c)] : make_double2(0.0, 0.0);
+    factor_block(a, xdb);
+  }
+  __syncthreads();
+  for (int j = 0, cur = 0; j < N; j += CHOL_B, cur ^= 1) {
+    const double2* xc = xdb + cur * CHOL_B * CHOL_B;   // this block's factor
+    double2* xn = xdb + (cur ^ 1) * CHOL_B * CHOL_B;   // the next block's
     double2 d[CHOL_B][CHOL_B];
     double dinv[CHOL_B];
 #pragma unroll
     for (int r = 0; r < CHOL_B; ++r)
 #pragma unroll
-      for (int c = 0; c < CHOL_B; ++c) d[r][c] = xdb[r * CHOL_B + c];
+      for (int c = 0; c < CHOL_B; ++c) d[r][c] = xc[r * CHOL_B + c];
 #pragma unroll
     for (int c = 0; c < CHOL_B; ++c) {
       dinv[c] = d[c][c].y;
@@ -326,10 +341,31 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
         for (int c = 0; c <= r; ++c) L[tri_idx(j + r, j + c)] = d[r][c];
     }
     __syncthreads();
-    {
-      // trailing triangle in 2 x 2 tiles, a flat list over all threads
-      const int j0 = j + CHOL_B, t2 = (N - j0) / 2;
-      for (int t = tid; t < t2 * (t2 + 1) / 2; t += NT) {
+    const int j0 = j + CHOL_B;
+    if (tid < 64) {
+      if (j0 < N) {   // the next diagonal block: this step's update, then its factor
+        double2 a[CHOL_B][CHOL_B];
+#pragma unroll
+        for (int r = 0; r < CHOL_B; ++r) {
+#pragma unroll
+          for (int c = 0; c < CHOL_B; ++c) {
+            double2 v = make_double2(0.0, 0.0);
+            if (c <= r) {
+              v = L[tri_idx(j0 + r, j0 + c)];
+#pragma unroll
+              for (int q = 0; q < CHOL_B; ++q)
+                v = zsub_mulc(v, L[tri_idx(j0 + r, j + q)], L[tri_idx(j0 + c, j + q)]);
+            }
+            a[r][c] = v;
+          }
+        }
+        factor_block(a, xn);
+      }
+    } else {
+      // the rest of the trailing triangle in 2 x 2 tiles, a flat list over
+      // waves 1..; tiles 0..2 are the next diagonal block
+      const int t2 = (N - j0) / 2;
+      for (int t = 3 + tid - 64; t < t2 * (t2 + 1) / 2; t += NT - 64) {
         int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
         while (tri_idx(ti + 1, 0) <= t) ++ti;
         while (tri_idx(ti, 0) > t) --ti;
@@ -368,39 +404,45 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
   //    (which read the block's column of L), then for the block's own columns
   //    (which overwrite it; one thread per row pair).  Slot (i, j) holds L
   //    until column j is consumed, then B, then X.
-  for (int k = 0; k < N; k += CHOL_B) {
-    if (tid < 64) {
-      double2 xd[CHOL_B][CHOL_B];
+  //    Look-ahead: the inverse of the next diagonal block (final L, untouched
+  //    by this step) is formed by wave 0 while the other waves update the
+  //    rows below; the two inverses alternate between two LDS buffers.
+  auto inv_diag = [&](int k, double2* dst) {   // every lane of wave 0 alike; lane 0 stores
+    double2 xd[CHOL_B][CHOL_B];
 #pragma unroll
-      for (int c = 0; c < CHOL_B; ++c)
+    for (int c = 0; c < CHOL_B; ++c)
 #pragma unroll
-        for (int r = 0; r < CHOL_B; ++r) xd[r][c] = make_double2(0.0, 0.0);
+      for (int r = 0; r < CHOL_B; ++r) xd[r][c] = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int c = 0; c < CHOL_B; ++c) {
-        xd[c][c] = make_double2(1.0 / L[tri_idx(k + c, k + c)].x, 0.0);
+    for (int c = 0; c < CHOL_B; ++c) {
+      xd[c][c] = make_double2(1.0 / L[tri_idx(k + c, k + c)].x, 0.0);
 #pragma unroll
-        for (int r = c + 1; r < CHOL_B; ++r) {
-          // xd[r][c] = -(sum_{m=c}^{r-1} L_{k+r,k+m} xd[m][c]) / L_{k+r,k+r}
-          double2 v = make_double2(0.0, 0.0);
+      for (int r = c + 1; r < CHOL_B; ++r) {
+        // xd[r][c] = -(sum_{m=c}^{r-1} L_{k+r,k+m} xd[m][c]) / L_{k+r,k+r}
+        double2 v = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int m = c; m < r; ++m) v = zsub_mul(v, L[tri_idx(k + r, k + m)], xd[m][c]);
-          const double ir = 1.0 / L[tri_idx(k + r, k + r)].x;
-          xd[r][c] = make_double2(v.x * ir, v.y * ir);
-        }
+        for (int m = c; m < r; ++m) v = zsub_mul(v, L[tri_idx(k + r, k + m)], xd[m][c]);
+        const double ir = 1.0 / L[tri_idx(k + r, k + r)].x;
+        xd[r][c] = make_double2(v.x * ir, v.y * ir);
       }
-      if (tid == 0)
-#pragma unroll
-        for (int r = 0; r < CHOL_B; ++r)
-#pragma unroll
-          for (int c = 0; c < CHOL_B; ++c) xdb[r * CHOL_B + c] = xd[r][c];
     }
-    __syncthreads();
+    if (tid == 0)
+#pragma unroll
+      for (int r = 0; r < CHOL_B; ++r)
+#pragma unroll
+        for (int c = 0; c < CHOL_B; ++c) dst[r * CHOL_B + c] = xd[r][c];
+  };
+  if (tid < 64) inv_diag(0, xdb);
+  __syncthreads();
+  for (int k = 0, cur = 0; k < N; k += CHOL_B, cur ^= 1) {
+    const double2* xc = xdb + cur * CHOL_B * CHOL_B;         // this block's inverse
+    double2* xn = xdb + (cur ^ 1) * CHOL_B * CHOL_B;         // the next block's
     for (int jj = tid; jj < k; jj += NT) {   // rows k.. of X, columns left of the block
       double2 xd[CHOL_B][CHOL_B];
 #pragma unroll
       for (int r = 0; r < CHOL_B; ++r)
 #pragma unroll
-        for (int c = 0; c <= r; ++c) xd[r][c] = xdb[r * CHOL_B + c];
+        for (int c = 0; c <= r; ++c) xd[r][c] = xc[r * CHOL_B + c];
       double2 bq[CHOL_B];
 #pragma unroll
       for (int m = 0; m < CHOL_B; ++m) bq[m] = L[tri_idx(k + m, jj)];
@@ -416,13 +458,15 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
 #pragma unroll
       for (int r = 0; r < CHOL_B; ++r)
 #pragma unroll
-        for (int c = 0; c <= r; ++c) L[tri_idx(k + r, k + c)] = xdb[r * CHOL_B + c];
+        for (int c = 0; c <= r; ++c) L[tri_idx(k + r, k + c)] = xc[r * CHOL_B + c];
     }
     __syncthreads();
-    {
-      // rows below the block x columns left of it, in 2 x 2 tiles
+    if (tid < 64) {
+      if (k + CHOL_B < N) inv_diag(k + CHOL_B, xn);
+    } else {
+      // rows below the block x columns left of it, in 2 x 2 tiles (waves 1..)
       const int nr = (N - k - CHOL_B) / 2, nc = k / 2;
-      for (int t = tid; t < nr * nc; t += NT) {
+      for (int t = tid - 64; t < nr * nc; t += NT - 64) {
         const int i = k + CHOL_B + 2 * (t / nc), jj = 2 * (t % nc);
         const int r0 = tri_idx(i, 0), r1 = tri_idx(i + 1, 0);
         double2 a[2][CHOL_B], x[CHOL_B][2];
@@ -464,7 +508,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
         for (int q = 0; q < CHOL_B; ++q) {
           double2 v = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int c = q; c < CHOL_B; ++c) v = zsub_mul(v, a[c], xdb[c * CHOL_B + q]);   // Xd from LDS
+          for (int c = q; c < CHOL_B; ++c) v = zsub_mul(v, a[c], xc[c * CHOL_B + q]);   // Xd from LDS
           L[ri + q] = v;
         }
       }

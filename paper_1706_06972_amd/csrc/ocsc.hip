@@ -924,7 +924,7 @@ int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* ou
 // accumulation time (the fold of G and C may still be deferred).
 size_t chol_lds(int K) {
   const size_t n = (size_t)(K + CHOL_B - 1) / CHOL_B * CHOL_B;   // padded to whole column blocks
-  return (n * (n + 1) / 2 + CHOL_B * CHOL_B) * 16;
+  return (n * (n + 1) / 2 + 2 * CHOL_B * CHOL_B) * 16;
 }
 // two workgroups of 512 threads per CU when the factor takes at most half the LDS
 bool chol_small(int K) { return chol_lds(K) <= 80 * 1024; }
