@@ -759,17 +759,23 @@ __global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ 
   }
   float2 dc = make_float2(0.f, 0.f);
   const int rr = t >> 4, q = t & 15;
+  // element t + 256 m of a strip is row r, column cc of it, the same for
+  // every strip: the divisions are done once (packed as r * 512 + cc; r < 32,
+  // cc < K <= 256)
+  int rc[DS_ROWS];
+#pragma unroll
+  for (int m = 0; m < DS_ROWS; ++m) {
+    const int e = t + m * 256, r = e / K;
+    rc[m] = r * 512 + (e - r * K);
+  }
   // the next strip is fetched into registers while the current one is used
   float pf[DS_ROWS];
   auto fetch = [&](int a0) {
-    const int n = min(DS_ROWS, K - a0) * K;
+    const int nr = min(DS_ROWS, K - a0);
 #pragma unroll
     for (int m = 0; m < DS_ROWS; ++m) {
-      const int e = t + m * 256;
-      if (e < n) {
-        const int r = e / K, cc = e - r * K;
-        pf[m] = R[(size_t)(a0 + r) * ld + cc];
-      }
+      const int r = rc[m] >> 9, cc = rc[m] & 511;
+      if (r < nr) pf[m] = R[(size_t)(a0 + r) * ld + cc];
     }
   };
   fetch(0);
@@ -778,11 +784,8 @@ __global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ 
     const int nr = min(DS_ROWS, K - a0);
 #pragma unroll
     for (int m = 0; m < DS_ROWS; ++m) {
-      const int e = t + m * 256;
-      if (e < nr * K) {
-        const int r = e / K, cc = e - r * K;
-        strip[r * DS_PITCH + cc] = pf[m];
-      }
+      const int r = rc[m] >> 9, cc = rc[m] & 511;
+      if (r < nr) strip[r * DS_PITCH + cc] = pf[m];
     }
     __syncthreads();
     if (a0 + DS_ROWS < K) fetch(a0 + DS_ROWS);
