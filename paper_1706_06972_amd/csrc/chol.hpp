@@ -519,8 +519,12 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
   //    blocks (four loads for four products per m).  X is block diagonal
   //    with the identity padding, so the sums may run to N; only m = j0 meets
   //    the zero upper triangle (X_m,j0+1 for m = j0).
-  const int n2 = N / 2;
-  for (int t = tid; t < n2 * (n2 + 1) / 2; t += NT) {
+  const int n2 = N / 2, ntile = n2 * (n2 + 1) / 2;
+  // the sums get shorter along the tile list (m runs from j0 + 1 to N), so
+  // the rounds alternate direction and each thread's tiles even out
+  for (int rd = 0; rd * NT < ntile; ++rd) {
+    const int t = (rd & 1) ? (rd + 1) * NT - 1 - tid : rd * NT + tid;
+    if (t >= ntile) continue;
     int r = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);   // t = r (r + 1) / 2 + c, c <= r
     while (tri_idx(r + 1, 0) <= t) ++r;
     while (tri_idx(r, 0) > t) --r;
