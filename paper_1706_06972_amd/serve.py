@@ -46,16 +46,17 @@ class Request:
 
 
 def slot_bytes(K: int, n: int, real_bytes: int = 4, cholesky: bool = False) -> int:
-    """Device bytes one pending slot of an n x n context holds: the sample and
-    code spectra, the code-ADMM dual and transform workspace (and, in the
-    precision form, the frequency-major code spectra and a codes buffer)."""
+    """Device bytes one pending slot of an n x n context holds (contexts with
+    more than one slot): the sample and code spectra, the frequency-major copy
+    of the code spectra that the history fold reads, the code-ADMM dual and
+    transform workspace (and, in the precision form, a codes buffer)."""
     Pf, P = n * (n // 2 + 1), n * n
     spec = 2 * real_bytes
-    b = Pf * spec * 2 + 2 * K * Pf * spec + K * P * real_bytes
+    b = Pf * spec * 2 + 3 * K * Pf * spec + K * P * real_bytes
     if n > 128:
         b += K * Pf * spec
     if cholesky:
-        b += K * Pf * spec + K * P * real_bytes
+        b += K * P * real_bytes
     return b
 
 
