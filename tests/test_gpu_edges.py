@@ -20,7 +20,7 @@ import pytest
 
 import oracle.ocsc_oracle as O
 import synth
-from tests.gpu_util import rel, say, spectra, to_np
+from tests.gpu_util import rel, say, spectra, to_np, unpack_cinv
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -73,6 +73,34 @@ def test_largest_k_of_the_sherman_morrison_form(prec, K):
     say(f"  errors {worst}")
     assert np.count_nonzero(Uo) > 0
     assert all(v < TOL[prec] for v in worst.values()), worst
+
+
+@pytest.mark.parametrize("prec,K", [("f64", 92), ("f32", 128), ("f32", 100), ("f64", 16)])
+def test_minibatch_fold_at_the_largest_k(prec, K):
+    """Four samples coded together and folded in one sweep (blocks of three,
+    then one), at the largest K of each precision and at the compiled K."""
+    say(f"case minibatch fold {prec} K={K}")
+    from paper_1706_06972_amd.ocsc import OCSC
+    B = 4
+    xs = images(B, 32, 32, seed=9)
+    g = OCSC(K, 5, 5, 32, 32, 0.5, 1.0, precision=prec, max_batch=B)
+    o = O.OCSC(K, 5, 5, 32, 32, 0.5, 1.0)
+    D0 = synth.initial_dictionary(K, 5, 5, 0)
+    g.set_dictionary(D0)
+    o.set_dictionary(D0)
+    U = to_np(g.code_update(xs))
+    Uo = o.code_update(xs)
+    g.history_accumulate()
+    o.history_accumulate()
+    g.dict_update()
+    o.dict_update()
+    errs = {"codes": rel(U, Uo),
+            "G": rel(spectra(to_np(g.state("G")), (K,), 32, 32), o.G),
+            "C": rel(unpack_cinv(to_np(g.state("cinv")), K, 32, 32), o.C),
+            "D": rel(to_np(g.get_dictionary()), o.get_dictionary())}
+    say(f"  errors {errs}")
+    assert all(v < TOL[prec] for v in errs.values()), errs
+    g.close()
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
