@@ -20,6 +20,14 @@ __device__ __forceinline__ v4f mfma_bf16(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// -x for eight BF16 values (sign bits flipped; exact)
+__device__ __forceinline__ v8bf bf_neg(v8bf x) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  v4u u = __builtin_bit_cast(v4u, x);
+  u ^= 0x80008000u;
+  return __builtin_bit_cast(v8bf, u);
+}
+
 // NW waves per workgroup, NSPLIT workgroups per frequency p (blockIdx.x = p,
 // blockIdx.y = share of the tiles).  Zt[(p * ldt + b) * K + k] holds the nb
 // pending code spectra frequency-major; xh[b * Pf + p] the sample spectra.
@@ -55,9 +63,9 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
     tri[tt] = i;
     trj[tt] = i + t;
   }
-  v4f re[TPW], im1[TPW], im2[TPW];
+  v4f re[TPW], im[TPW];
 #pragma unroll
-  for (int tt = 0; tt < TPW; ++tt) re[tt] = im1[tt] = im2[tt] = v4f{0, 0, 0, 0};
+  for (int tt = 0; tt < TPW; ++tt) re[tt] = im[tt] = v4f{0, 0, 0, 0};
   float gr = 0.f, gi = 0.f;
   const int gk = tid % KP, gsl = tid / KP;   // this thread's filter and sample slice for G
   const float2* zp = Zt + (size_t)p * ldt * K;
@@ -155,13 +163,15 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
         re[tt] = mfma_bf16(ail, bih, re[tt]);
         // Im H_ij = sum_b zr_i zi_j - zi_i zr_j, formed transposed (row j,
         // column i: the j-block as operand A) so that the lower triangle of
-        // the R-form, which holds it, is written row by row
-        im1[tt] = mfma_bf16(bih, arh, im1[tt]);
-        im1[tt] = mfma_bf16(bil, arh, im1[tt]);
-        im1[tt] = mfma_bf16(bih, arl, im1[tt]);
-        im2[tt] = mfma_bf16(brh, aih, im2[tt]);
-        im2[tt] = mfma_bf16(brl, aih, im2[tt]);
-        im2[tt] = mfma_bf16(brh, ail, im2[tt]);
+        // the R-form, which holds it, is written row by row; the second sum
+        // enters with its A operand negated, so one accumulator holds both
+        im[tt] = mfma_bf16(bih, arh, im[tt]);
+        im[tt] = mfma_bf16(bil, arh, im[tt]);
+        im[tt] = mfma_bf16(bih, arl, im[tt]);
+        const v8bf nbrh = bf_neg(brh), nbrl = bf_neg(brl);
+        im[tt] = mfma_bf16(nbrh, aih, im[tt]);
+        im[tt] = mfma_bf16(nbrl, aih, im[tt]);
+        im[tt] = mfma_bf16(nbrh, ail, im[tt]);
       }
     }
   }
@@ -175,7 +185,7 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
       const int i = tri[tt] * 16 + 4 * lg + r, j = trj[tt] * 16 + li;   // Re H_ij at R[i][j], i <= j
       if (i < K && j < K && i <= j) R[i * ld + j] += re[tt][r];
       const int jt = trj[tt] * 16 + 4 * lg + r, it = tri[tt] * 16 + li;  // Im H_it,jt at R[jt][it], it < jt
-      if (it < K && jt < K && it < jt) R[jt * ld + it] += im1[tt][r] - im2[tt][r];
+      if (it < K && jt < K && it < jt) R[jt * ld + it] += im[tt][r];
     }
   }
   if (split == 0) {
