@@ -381,10 +381,19 @@ __host__ __device__ inline size_t sweep_plain_lds_bytes(int K, int fpb, int fs, 
 // the padding).  Guarded loads and stores would leave the compiler unable to
 // prove that the previous slot's loads into the same registers have landed,
 // and it would then wait for all of them before each new load.
+// C is read once per sweep, so its loads (and the fold's write-back, see
+// slot_writeback) carry the non-temporal hint: its lines are the first to
+// leave the caches, and the small vectors of the step (right-hand sides, d,
+// which the V-step reads next) stay there.
 template <int NV_MAX>
 __device__ __forceinline__ void slot_fetch(v4f (&reg)[NV_MAX], const v4f* __restrict__ src, int nvec, int tid) {
 #pragma unroll
-  for (int v = 0; v < NV_MAX; ++v) reg[v] = src[min(tid + v * 256, nvec - 1)];
+  for (int v = 0; v < NV_MAX; ++v) reg[v] = __builtin_nontemporal_load(&src[min(tid + v * 256, nvec - 1)]);
+}
+
+// the updated C of a slot back to HBM (nv 16-byte vectors)
+__device__ __forceinline__ void slot_writeback(v4f* __restrict__ dst, const v4f* src, int nv, int tid) {
+  for (int e = tid; e < nv; e += 256) __builtin_nontemporal_store(src[e], &dst[e]);
 }
 
 template <int NV_MAX>
@@ -580,9 +589,7 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
       }
       if constexpr (CT) herm_rank1_ct<T, KT, 256 / FPB>(R, vv, beta, lt);
       else herm_rank1<T>(R, K, ld, vv, beta, lt, tpg, ns);
-      v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
-      const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
-      for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
+      slot_writeback(reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs), reinterpret_cast<const v4f*>(Rall), nv, tid);
     } else if constexpr (MF) {
       // several samples, folded in sample order in blocks of FB (the
       // recursion of eq. C_update applied FB times per pass over C).  With
@@ -705,9 +712,7 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
         herm_rank_n<T, FB>(R, K, ld, U, beta, lt, tpg, ns);
       }
       if (ok && lt < K) G[(size_t)lt * Pf + p] = gacc;
-      v4f* dst = reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs);
-      const v4f* srcv = reinterpret_cast<const v4f*>(Rall);
-      for (int e = tid; e < nv; e += 256) dst[e] = srcv[e];
+      slot_writeback(reinterpret_cast<v4f*>(Cm + (size_t)sl * fpb * fs), reinterpret_cast<const v4f*>(Rall), nv, tid);
       if (rfold && ok && lt < K) {
         const cx<T> rn = cadd<T>(rfold[(size_t)lt * Pf + p], dsum);
         rfold[(size_t)lt * Pf + p] = rn;
