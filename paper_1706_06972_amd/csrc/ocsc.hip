@@ -462,8 +462,9 @@ int sweep_nvm_for(int K, int fpb, size_t sr) {
 template <typename T>
 int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dout, int cls) {
   LaunchTimer tm(c, cls);
-  // successive sweeps alternate direction, so the tail of one sweep is still
-  // in the Infinity Cache at the head of the next
+  // successive sweeps alternate direction (the tail of one sweep first in the
+  // next; with the non-temporal loads of C this no longer changes the time,
+  // and the direction changes no result)
   const int reverse = (int)(c->sweep_count & 1u);
   c->sweep_count++;
   if (c->dstream) {
