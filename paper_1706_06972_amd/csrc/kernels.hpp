@@ -387,11 +387,6 @@ __global__ void k_obj_final(const double* __restrict__ rpart, int nr, const doub
   }
 }
 
-template <typename T>
-__global__ void k_fill_zero(T* __restrict__ x, size_t n) {
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) x[e] = (T)0;
-}
-
 }  // namespace ocsc
 
 #pragma clang fp contract(fast)
