@@ -462,10 +462,11 @@ __device__ __forceinline__ void run_store(const cx<T>* rb, cx<T>* __restrict__ d
 // the right-hand side is instead the carried G + rho_d (F(V) - Theta), which
 // the fold advances by the same increments as G and writes back.
 // dout == nullptr: fold only.
-// MF: compiled for nfold > 1 only (the multi-sample fold's registers are then
-// not charged to the plain and one-sample sweeps, and the other way round).
+// MODE: 0 plain sweep (nfold = 0), 1 one-sample fold, 2 multi-sample fold;
+// each is its own kernel instance, so that no form carries the registers or
+// the slot order of another.
 // ---------------------------------------------------------------------------
-template <typename T, int KT, int FPB, bool MF>
+template <typename T, int KT, int FPB, int MODE>
 __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>* __restrict__ G,
                                                     const cx<T>* __restrict__ rhs,
                                                     const cx<T>* __restrict__ Zh,
@@ -478,6 +479,8 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
   // KT > 0: K and fpb fixed at compile time (the arguments then equal them);
   // KT = 0, -1: generic, slots of up to SWEEP_MAXV, SWEEP_MAXV_L vectors per thread
   constexpr bool CT = KT > 0;
+  constexpr bool MF = MODE == 2;
+  constexpr bool plain = MODE == 0;
   constexpr int VR = 16 / (int)sizeof(T);
   const int K = CT ? KT : K_;
   const int fpb = CT ? FPB : fpb_;
@@ -505,13 +508,20 @@ __global__ __launch_bounds__(256, 3) void k_dict_sweep(T* __restrict__ Cm, cx<T>
   const int nslots = (Pf + fpb - 1) / fpb;
   const int nwg = gridDim.x;
   const int run = xcd_block(blockIdx.x, nwg);
-  const int s_begin = run * slots_per_wg;
-  const int s_end = min(nslots, s_begin + slots_per_wg);
   const int nvec = (int)((size_t)fpb * fs * sizeof(T) / 16);
-  const bool plain = dout && nfold == 0;
+  // A plain sweep walks a contiguous run of slots (its right-hand sides come
+  // in as whole lines, see run_load).  A fold sweep takes its slots round by
+  // round instead, slot s * nwg + run in round s: the workgroups of one XCD
+  // then hold neighbouring frequencies at the same time and share the cache
+  // lines of the per-frequency spectra, G and d that a fold reads and writes.
+  const int s_begin = plain ? run * slots_per_wg : 0;
+  const int s_end = plain ? min(nslots, s_begin + slots_per_wg) : (run < nslots ? (nslots - 1 - run) / nwg + 1 : 0);
   v4f reg[NVM];
 
-  auto slot_of = [&](int s) { return reverse ? nslots - 1 - s : s; };
+  auto slot_of = [&](int s) {
+    const int i = plain ? s : s * nwg + run;
+    return reverse ? nslots - 1 - i : i;
+  };
   auto slot_vecs = [&](int sl) {
     return min(nvec, (int)(((size_t)min(fpb, Pf - sl * fpb) * fs * sizeof(T)) / 16));
   };

@@ -479,17 +479,19 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
     }
     return fail(c, OCSC_E_UNSUPPORTED, "the K > 128 form is FP32");
   }
-  const size_t smem = (dout && nfold == 0) ? c->plain_smem : c->sweep_smem;
-  const bool mf = nfold > 1;
-#define OCSC_SWEEP_MF(KT, FPB, MF)                                                                            \
-  TIMED_LAUNCH(tm, (k_dict_sweep<T, KT, FPB, MF>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,             \
+  if (nfold == 0 && !dout) return fail(c, OCSC_E_STATE, "internal: a sweep with neither fold nor D-step");
+  const size_t smem = nfold == 0 ? c->plain_smem : c->sweep_smem;
+  const int mode = nfold == 0 ? 0 : (nfold == 1 ? 1 : 2);
+#define OCSC_SWEEP_M(KT, FPB, M)                                                                              \
+  TIMED_LAUNCH(tm, (k_dict_sweep<T, KT, FPB, M>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,              \
                (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->Zt, c->maxB,  \
                (const cx<T>*)c->xh, nfold, (cx<T>*)rfold, (cx<T>*)dout, c->K, c->Pf, c->fpb, c->fs,            \
                c->slots_per_wg, reverse)
-#define OCSC_SWEEP(KT, FPB)                 \
-  do {                                      \
-    if (mf) OCSC_SWEEP_MF(KT, FPB, true);   \
-    else OCSC_SWEEP_MF(KT, FPB, false);     \
+#define OCSC_SWEEP(KT, FPB)                        \
+  do {                                             \
+    if (mode == 2) OCSC_SWEEP_M(KT, FPB, 2);       \
+    else if (mode == 1) OCSC_SWEEP_M(KT, FPB, 1);  \
+    else OCSC_SWEEP_M(KT, FPB, 0);                 \
   } while (0)
   bool done = false;
 #define X(TT, KT, FPB)                                                          \
@@ -506,7 +508,7 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
     else OCSC_SWEEP(0, 0);
   }
 #undef OCSC_SWEEP
-#undef OCSC_SWEEP_MF
+#undef OCSC_SWEEP_M
   LAUNCHED(c);
   tm.launched();
   return OCSC_OK;
@@ -1300,14 +1302,14 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
   if (!c->dstream && std::max(c->sweep_smem, c->plain_smem) > 64 * 1024) {
-    const void* fns[] = {(const void*)k_dict_sweep<double, 0, 0, false>, (const void*)k_dict_sweep<float, 0, 0, false>,
-                         (const void*)k_dict_sweep<double, -1, 0, false>, (const void*)k_dict_sweep<float, -1, 0, false>,
-                         (const void*)k_dict_sweep<double, 0, 0, true>, (const void*)k_dict_sweep<float, 0, 0, true>,
-                         (const void*)k_dict_sweep<double, -1, 0, true>, (const void*)k_dict_sweep<float, -1, 0, true>
-#define X(T, KT, FPB) , (const void*)k_dict_sweep<T, KT, FPB, false>, (const void*)k_dict_sweep<T, KT, FPB, true>
+#define M3(T, KT, FPB) \
+  (const void*)k_dict_sweep<T, KT, FPB, 0>, (const void*)k_dict_sweep<T, KT, FPB, 1>, (const void*)k_dict_sweep<T, KT, FPB, 2>
+    const void* fns[] = {M3(double, 0, 0), M3(float, 0, 0), M3(double, -1, 0), M3(float, -1, 0)
+#define X(T, KT, FPB) , M3(T, KT, FPB)
                          OCSC_SWEEP_SPECS(X)
 #undef X
     };
+#undef M3
     for (const void* fn : fns) {
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)std::max(c->sweep_smem, c->plain_smem));
