@@ -46,7 +46,7 @@ struct ocsc_ctx {
   int nvb = 0;     // V-step column blocks
   int fpb = 1;     // frequencies solved side by side by one D-step workgroup
   int fs = 0;      // reals per frequency of C (K rows of pitch K+1, 16-byte multiple)
-  int sweep_wgs = 0, slots_per_wg = 0;
+  int sweep_wgs = 0, slots_per_wg = 0, fold_wgs = 0;   // plain-sweep grid and run length; fold-sweep grid
   size_t sweep_smem = 0, plain_smem = 0, vapply_smem = 0;   // LDS of fold sweeps and of plain sweeps
   bool vstep_fused = false;   // one workgroup per filter (filters up to 16 x 16)
   bool big = false;           // two-pass plane transforms (a side above 128)
@@ -483,7 +483,8 @@ int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dou
   const size_t smem = nfold == 0 ? c->plain_smem : c->sweep_smem;
   const int mode = nfold == 0 ? 0 : (nfold == 1 ? 1 : 2);
 #define OCSC_SWEEP_M(KT, FPB, M)                                                                              \
-  TIMED_LAUNCH(tm, (k_dict_sweep<T, KT, FPB, M>), dim3(c->sweep_wgs), dim3(256), smem, c->stream,              \
+  TIMED_LAUNCH(tm, (k_dict_sweep<T, KT, FPB, M>), dim3(nfold ? c->fold_wgs : c->sweep_wgs), dim3(256), smem,   \
+               c->stream,                                                                                     \
                (T*)c->Cm, (cx<T>*)c->G, (const cx<T>*)rhs, (const cx<T>*)c->Zh, (const cx<T>*)c->Zt, c->maxB,  \
                (const cx<T>*)c->xh, nfold, (cx<T>*)rfold, (cx<T>*)dout, c->K, c->Pf, c->fpb, c->fs,            \
                c->slots_per_wg, reverse)
@@ -1243,15 +1244,21 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   c->fs = fs;
   c->sweep_smem = sweep_bytes(fpb);
   {
-    // One round of workgroups over the chip; each walks a run of slots.  A
-    // plain sweep also holds the run's right-hand sides in LDS, so the run
-    // length is capped by what fits at the chosen occupancy.
+    // One round of workgroups over the chip.  A fold sweep deals its slots
+    // out round by round to as many workgroups as fit at once.  A plain sweep
+    // gives each workgroup a run of slots and holds the run's right-hand
+    // sides in LDS; it runs at most two workgroups per CU with runs half as
+    // long again (K=100: 490 workgroups of 17 slots took 57 us per sweep
+    // against 64 us for 757 of 11), and the run length is capped by what
+    // fits in LDS.
     const int nslots = (c->Pf + fpb - 1) / fpb;
     const int nvm = sweep_nvm_for(K, fpb, sr);
     const size_t plain0 = sweep_plain_lds_bytes(K, fpb, fs, (int)sr, nvm, 0);
     const size_t per_slot = (size_t)fpb * K * 2 * sr;
-    int occ = (int)((160 * 1024) / (std::max(c->sweep_smem, plain0 + per_slot) + 64));   // + static LDS
-    occ = occ < 1 ? 1 : (occ > 8 ? 8 : occ);
+    const int occ_fold = std::max(1, std::min(8, (int)((160 * 1024) / (c->sweep_smem + 64))));   // + static LDS
+    c->fold_wgs = std::min(nslots, 256 * occ_fold);
+    int occ = (int)((160 * 1024) / (std::max(c->sweep_smem, plain0 + per_slot) + 64));
+    occ = occ < 1 ? 1 : (occ > 2 ? 2 : occ);
     const size_t budget = (size_t)(160 * 1024) / occ - 64;
     int spw = (nslots + 256 * occ - 1) / (256 * occ);
     const int spw_max = (int)((budget - plain0) / per_slot);
