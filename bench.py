@@ -94,7 +94,35 @@ def oracle_baseline(wl, n_steps: int):
     dt = time.perf_counter() - t0
     return {"value": n_steps / dt, "unit": "images/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_steps} steps of the {wl.name} workload (FP64 NumPy oracle, after one untimed step)",
-            "seconds": dt, "host_cpus": os.cpu_count()}
+            "seconds": dt, "host_cpus": os.cpu_count(), "nproc": host_nproc(), "cpu_model": host_cpu_model()}
+
+
+def host_nproc():
+    """Processing units available to this process (``nproc``)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count()
+
+
+def host_cpu_model() -> str:
+    """The host CPU model, as ``lscpu`` reports it (``/proc/cpuinfo`` if lscpu is missing)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def batched_run(wl, B: int, xs, dev, steps: int = 10, warmup: int = 2, cholesky: bool = False, K=None) -> dict:
@@ -411,11 +439,13 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pool", type=int, default=64, help="distinct images resident on the device")
-    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps timed for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=6, help="oracle steps timed for cpu_baseline (0: skip)")
     ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per D-step launch")
     ap.add_argument("--batch", type=int, default=64,
                     help="also time minibatch steps of this many samples (0: skip)")
     ap.add_argument("--coding", type=int, default=1, help="also time coding on 64..512 grids (0: skip)")
+    ap.add_argument("--grouped", type=int, default=1,
+                    help="also time the grouped persistent (cooperative) launch against per-grid launches (0: skip)")
     ap.add_argument("--served", type=int, default=1, help="also run the serving form (0: skip)")
     ap.add_argument("--quality", type=int, default=1,
                     help="also measure test objective / PSNR before and after learning (0: skip)")
@@ -518,7 +548,7 @@ def main():
     out["precision_k256"] = (batched_run(wl, args.batch, xs, dev, steps=4, warmup=1, cholesky=True, K=256)
                              if args.batch > 1 else None)
     out["coding"] = coding_run(dev) if args.coding else None
-    out["grouped"] = grouped_run(dev) if args.coding else None
+    out["grouped"] = grouped_run(dev) if args.grouped else None
     out["copy_ceiling"] = copy_ceiling(dev)
     out["served"] = served_run(dev) if args.served else None
     out["quality"] = quality_run(dev) if args.quality else None

@@ -89,7 +89,11 @@ typedef struct {
  * two 128-blocks joined by their Schur complement).  Implies
  * OCSC_FLAG_KEEP_HISTORY.  K > 128 is available only in this form: its D-step
  * streams C_p from HBM instead of holding it in LDS.  K > 128 also needs a
- * workspace of up to 2048 x 1.25 MB. */
+ * workspace of up to 2048 x 1.25 MB.  A factorisation whose matrix is not
+ * positive definite (a pivot <= 0 or NaN: a non-finite history, or an
+ * indefinite H given to ocsc_set_state) leaves NaN in C at that frequency and
+ * is reported once, as OCSC_E_NUMERIC, by the next ocsc_sync,
+ * ocsc_objective, ocsc_objective_terms, ocsc_surrogate or ocsc_diagnostics. */
 #define OCSC_FLAG_CHOLESKY 8
 
 /* Fill *opts with the defaults listed above. */
@@ -237,6 +241,37 @@ int ocsc_objective_terms(ocsc_ctx* ctx, const void* x_dev, const void* codes_dev
                          double* out_host);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * objective of ocsc_objective with every intermediate buffer taken from a
+ * static scratch array of the library instead of the context's workspace,
+ * and the result left in device memory.  The call allocates nothing (no
+ * hipMalloc, hipFree, host copy or synchronisation), so it may be captured
+ * in a graph.
+ *   out_dev: B doubles in caller-owned device memory, 8-byte aligned;
+ *   out_dev[b] = 1/2 ||x_b - sum_k F^-1(D~_k F(U_bk))||^2 + lambda ||U_b||_1,
+ *   the same values as ocsc_objective, bit for bit.
+ *   x_dev, codes_dev, B: as for ocsc_objective, except that B is bounded by
+ *   the scratch instead of max_batch: B (K + 1) spectra of Pf complex values
+ *   plus 8 B (ceil(Pf / 256) + 64) bytes of partial sums must fit in
+ *   OCSC_NOALLOC_SCRATCH_BYTES (else OCSC_E_INVALID_ARG, nothing enqueued);
+ *   at 128 x 128 with K = 100 that is B <= 4 in FP32 and B <= 2 in FP64.
+ * Enqueued on the context stream; returns without waiting, so values are not
+ * inspected (a non-finite input propagates to out_dev; ocsc_objective
+ * reports it).  The context's workspace, state and pending codes are not
+ * touched, and no kernel timing is recorded for the call.
+ * The scratch is one array per device (32 MiB, held from the first
+ * ocsc_init on that device until the process ends), shared by every context
+ * on the device; nothing in it needs to start at zero, and each call
+ * overwrites what the last one left.  Calls that overlap on one device -- on
+ * different streams, or from several host threads -- race on it: order them
+ * on one stream or with events.
+ */
+#define OCSC_NOALLOC_SCRATCH_BYTES (32 * 1024 * 1024)
+int ocsc_objective_noalloc(ocsc_ctx* ctx, const void* x_dev, const void* codes_dev, int B,
+                           double* out_dev);
+
+/*
  * Online surrogate of Proposition 1 (unnormalised), in double:
  *   F_t(D~) = 1/(2P) sum_p c_p [d_p^H H_p d_p - 2 Re d_p^H G_p]
  *             + 1/2 sum_i ||x_i||^2 + lambda sum_i ||U_i||_1,
@@ -261,7 +296,10 @@ int ocsc_surrogate(ocsc_ctx* ctx, const void* D_dev, double* out_host);
  */
 int ocsc_diagnostics(ocsc_ctx* ctx, double* out_host);
 
-/* Wait until all work enqueued on the context stream has finished. */
+/* Wait until all work enqueued on the context stream has finished.
+ * OCSC_E_NUMERIC if, in the precision form, a Cholesky factorisation met a
+ * pivot that was not positive since the last call that waits (see
+ * OCSC_FLAG_CHOLESKY). */
 int ocsc_sync(ocsc_ctx* ctx);
 
 /* ---------------------------------------------------------------------------

@@ -243,7 +243,7 @@ constexpr int CB_N = 128;       // block size of the K > 128 form
 template <bool FULL, int NT>
 __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm, float* __restrict__ Cm,
                                                    const double2* __restrict__ Ain, double2* __restrict__ Cout,
-                                                   int K, int fs, double rho_d) {
+                                                   int K, int fs, double rho_d, int* __restrict__ breakdown) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // the factorisation runs on N = K rounded up to CHOL_B, padded with the
   // identity (which stays outside the top-left K x K of the inverse)
@@ -291,6 +291,10 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
       double sdiag = a[c][c].x;
 #pragma unroll
       for (int m = 0; m < c; ++m) sdiag -= d[c][m].x * d[c][m].x + d[c][m].y * d[c][m].y;
+      // a pivot that is not positive (or not a number): the matrix is not
+      // Hermitian positive definite; the factor goes on with NaN, and the
+      // context reports the breakdown at its next call that waits
+      if (!(sdiag > 0.0) && tid == 0) atomicOr(breakdown, 1);
       const double dc = sqrt(sdiag), ic = 1.0 / dc;
       d[c][c] = make_double2(dc, ic);   // the diagonal is real; its .y carries 1 / d_cc
 #pragma unroll

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -26,9 +27,21 @@
 
 using namespace ocsc;
 
+// Scratch of ocsc_objective_noalloc: part of the code object's static data,
+// so that the call allocates nothing.  Each device that loads the library
+// holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that ocsc_init looks up once per
+// device with that device current.
+static __device__ __align__(256) unsigned char scratch[OCSC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_init_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
 
 struct ProfEntry {
   int cls;
@@ -74,6 +87,8 @@ struct ocsc_ctx {
   void* Yb = nullptr;   // inverse column pass of the code spectra (two-pass grids)
   void* Zt = nullptr;   // last code spectra frequency-major [Pf][max_batch][K] (Cholesky form, max_batch > 1)
   double *pend = nullptr, *hacc = nullptr, *dpart = nullptr, *dres = nullptr;
+  void* scratch = nullptr;   // device address of this device's static scratch (ocsc_objective_noalloc)
+  int* brk = nullptr;        // Cholesky form: set by the factorisation when a pivot is not positive
   // host-side bookkeeping
   int64_t t = 0;
   int pending_B = 0;    // coded samples not yet accumulated
@@ -897,6 +912,21 @@ int dict_update_group_t(ocsc_ctx* const* cs, int n) {
   return OCSC_OK;
 }
 
+// Cholesky form: report (once) a breakdown the factorisation flagged since the
+// last check.  Called by the calls that wait, after their stream sync.
+int check_breakdown(ocsc_ctx* c) {
+  if (!c->brk) return OCSC_OK;
+  int h = 0;
+  HIPX(c, hipMemcpyAsync(&h, c->brk, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPX(c, hipStreamSynchronize(c->stream));
+  if (!h) return OCSC_OK;
+  HIPX(c, hipMemsetAsync(c->brk, 0, sizeof(int), c->stream));
+  HIPX(c, hipStreamSynchronize(c->stream));
+  return fail(c, OCSC_E_NUMERIC,
+              "Cholesky breakdown: H_p + rho_d I was not positive definite at some frequency "
+              "(a non-finite history, or an indefinite H given to ocsc_set_state); C holds NaN there");
+}
+
 template <typename T>
 int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* out, int terms) {
   int rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, (cx<T>*)c->xh_obj, c->Pf, B);
@@ -919,8 +949,50 @@ int objective_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* ou
   const int nout = terms ? 2 * B : B;
   HIPX(c, hipMemcpyAsync(out, c->obj_out, sizeof(double) * nout, hipMemcpyDeviceToHost, c->stream));
   HIPX(c, hipStreamSynchronize(c->stream));
+  rc = check_breakdown(c);
+  if (rc) return rc;
   for (int b = 0; b < nout; ++b)
     if (!std::isfinite(out[b])) return fail(c, OCSC_E_NUMERIC, "objective is not finite");
+  return OCSC_OK;
+}
+
+// ocsc_objective_noalloc: the kernels of objective_t with every buffer they
+// write (sample and code spectra, reduction partials) carved out of the static
+// scratch, and the result left in caller-owned device memory.  The partition
+// into workgroups is the one of objective_t, so the values are the same bit
+// for bit.
+size_t noalloc_objective_bytes(const ocsc_ctx* c, int B) {
+  auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+  const size_t sc = 2 * c->sr;
+  return up((size_t)B * c->Pf * sc) + up((size_t)B * c->K * c->Pf * sc) + up((size_t)B * c->obj_nr * 8) +
+         up((size_t)B * c->obj_nl * 8);
+}
+
+template <typename T>
+int objective_noalloc_t(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {
+  char* p = (char*)c->scratch;
+  auto take = [&](size_t n) {
+    char* q = p;
+    p += (n + 255) / 256 * 256;
+    return q;
+  };
+  cx<T>* xh = (cx<T>*)take((size_t)B * c->Pf * sizeof(cx<T>));
+  cx<T>* uh = (cx<T>*)take((size_t)B * c->K * c->Pf * sizeof(cx<T>));
+  double* rpart = (double*)take((size_t)B * c->obj_nr * sizeof(double));
+  double* lpart = (double*)take((size_t)B * c->obj_nl * sizeof(double));
+  int rc = launch_rfft2<T>(c, (const T*)x, c->Ph, c->Pw, c->P, xh, c->Pf, B);
+  if (rc) return rc;
+  rc = launch_rfft2<T>(c, (const T*)codes, c->Ph, c->Pw, c->P, uh, c->Pf, B * c->K);
+  if (rc) return rc;
+  hipLaunchKernelGGL((k_obj_resid<T>), dim3(c->obj_nr, B), dim3(256), 0, c->stream, (const cx<T>*)xh,
+                     (const cx<T>*)c->Dh, (const cx<T>*)uh, rpart, c->K, c->Pw, c->Pf);
+  LAUNCHED(c);
+  hipLaunchKernelGGL((k_abs_sum<T>), dim3(c->obj_nl, B), dim3(256), 0, c->stream, (const T*)codes, lpart,
+                     (long)c->K * c->P);
+  LAUNCHED(c);
+  hipLaunchKernelGGL(k_obj_final, dim3(B), dim3(256), 0, c->stream, (const double*)rpart, c->obj_nr,
+                     (const double*)lpart, c->obj_nl, out, 1.0 / c->P, c->lam, 0);
+  LAUNCHED(c);
   return OCSC_OK;
 }
 
@@ -962,11 +1034,11 @@ int chol_history(ocsc_ctx* c, int B) {
     if (chol_small(c->K))
       hipLaunchKernelGGL((k_chol_inv_t<false, 512>), dim3(c->Pf), dim3(512), chol_lds(c->K), c->stream,
                          (const float*)c->Hm, (float*)c->Cm, (const double2*)nullptr, (double2*)nullptr, c->K, c->fs,
-                         c->rho_d);
+                         c->rho_d, c->brk);
     else
       hipLaunchKernelGGL((k_chol_inv_t<false, CHOL_NT>), dim3(c->Pf), dim3(CHOL_NT), chol_lds(c->K), c->stream,
                          (const float*)c->Hm, (float*)c->Cm, (const double2*)nullptr, (double2*)nullptr, c->K, c->fs,
-                         c->rho_d);
+                         c->rho_d, c->brk);
     LAUNCHED(c);
     return OCSC_OK;
   }
@@ -984,13 +1056,13 @@ int chol_history(ocsc_ctx* c, int B) {
     hipLaunchKernelGGL(k_schur_unpack, dim3(3 * 16, nf), dim3(256), 0, c->stream, (const float*)c->Hm, c->fs, c->K,
                        c->rho_d, f0, nf, W);
     hipLaunchKernelGGL((k_chol_inv_t<true, CHOL_NT>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream,
-                       (const float*)nullptr, (float*)nullptr, (const double2*)s0, s1, CB_N, 0, 0.0);   // P = A11^-1
+                       (const float*)nullptr, (float*)nullptr, (const double2*)s0, s1, CB_N, 0, 0.0, c->brk);   // P = A11^-1
     hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s2,
                        (const double2*)s1, (const double2*)nullptr, s4, 1.0, 0.0);                   // B = A21 P
     hipLaunchKernelGGL((k_zgemm128<false, true>), g, dim3(256), 0, c->stream, (const double2*)s4,
                        (const double2*)s2, (const double2*)s3, s3, -1.0, 1.0);                       // S = A22 - B A21^H
     hipLaunchKernelGGL((k_chol_inv_t<true, CHOL_NT>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream,
-                       (const float*)nullptr, (float*)nullptr, (const double2*)s3, s0, CB_N, 0, 0.0);   // Q = S^-1
+                       (const float*)nullptr, (float*)nullptr, (const double2*)s3, s0, CB_N, 0, 0.0, c->brk);   // Q = S^-1
     hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s0,
                        (const double2*)s4, (const double2*)nullptr, s2, -1.0, 0.0);                  // C21 = -Q B
     hipLaunchKernelGGL((k_zgemm128<true, false>), g, dim3(256), 0, c->stream, (const double2*)s4,
@@ -1038,6 +1110,8 @@ int surrogate_t(ocsc_ctx* c, const void* D, double* out) {
   }
   HIPX(c, hipMemcpyAsync(out, c->dres, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPX(c, hipStreamSynchronize(c->stream));
+  rc = check_breakdown(c);
+  if (rc) return rc;
   if (!std::isfinite(out[0])) return fail(c, OCSC_E_NUMERIC, "surrogate is not finite");
   return OCSC_OK;
 }
@@ -1072,6 +1146,8 @@ int diagnostics_t(ocsc_ctx* c, double* out) {
   const size_t n = 2 + 2 * (size_t)c->K;
   HIPX(c, hipMemcpyAsync(out, c->dres, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
   HIPX(c, hipStreamSynchronize(c->stream));
+  rc = check_breakdown(c);
+  if (rc) return rc;
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(out[i])) return fail(c, OCSC_E_NUMERIC, "diagnostics are not finite");
   return OCSC_OK;
@@ -1098,7 +1174,7 @@ void free_all(ocsc_ctx* c) {
   void** bufs[] = {&c->xh, &c->Dh, &c->gam, &c->S,    &c->Zh,   &c->W,      &c->G,
                    &c->Cm, &c->d,  &c->Th,  &c->rhs,  &c->V,    &c->apart, &c->twH, &c->twW,
                    &c->xh_obj, &c->Hm, &c->Ubuf, &c->Dv, &c->Dexp, (void**)&c->pend, (void**)&c->hacc,
-                   (void**)&c->dpart, (void**)&c->dres, &c->Yb, &c->Zt, &c->Wchol};
+                   (void**)&c->dpart, (void**)&c->dres, &c->Yb, &c->Zt, &c->Wchol, (void**)&c->brk};
   for (void** b : bufs)
     if (*b) {
       (void)hipFree(*b);
@@ -1293,6 +1369,19 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   };
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  {
+    // the static scratch's address on this device, looked up once per device
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c->device < 0 || c->device >= kMaxDevices) return bail(OCSC_E_UNSUPPORTED, "device index above 63");
+    if (!g_scratch_dev[c->device]) {
+      void* addr = nullptr;
+      e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !addr)
+        return bail(OCSC_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      g_scratch_dev[c->device] = addr;
+    }
+    c->scratch = g_scratch_dev[c->device];
+  }
   if (!(o.flags & OCSC_FLAG_OWN_STREAM)) {
     c->stream = (hipStream_t)o.stream;
   } else {
@@ -1346,7 +1435,8 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
       {(void**)&c->pend, c->keep_hist ? 2 * B * 64 * sizeof(double) : 0},
       {&c->Yb, c->big ? B * K_ * Pf * sc : 0},
       {&c->Zt, (c->chol || B > 1) ? Pf * B * K_ * sc : 0},
-      {&c->Wchol, c->dstream ? (size_t)5 * c->chol_chunk * CB_N * CB_N * 16 : 0}};
+      {&c->Wchol, c->dstream ? (size_t)5 * c->chol_chunk * CB_N * CB_N * 16 : 0},
+      {(void**)&c->brk, c->chol ? sizeof(int) : 0}};
   for (auto& a : allocs) {
     if (a.n == 0) continue;
     e = hipMalloc(a.p, a.n);
@@ -1528,6 +1618,25 @@ int ocsc_objective_terms(ocsc_ctx* c, const void* x, const void* codes, int B, d
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
   if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
   return c->sr == 8 ? objective_t<double>(c, x, codes, B, out, 1) : objective_t<float>(c, x, codes, B, out, 1);
+}
+
+int ocsc_objective_noalloc(ocsc_ctx* c, const void* x, const void* codes, int B, double* out_dev) {
+  if (!c) return OCSC_E_INVALID_ARG;
+  if (!x || !codes || !out_dev) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
+  if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  if ((uintptr_t)out_dev & 7) return fail(c, OCSC_E_INVALID_ARG, "out_dev must be 8-byte aligned");
+  if (B < 1 || B > 65535) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, 65535]");
+  if (noalloc_objective_bytes(c, B) > (size_t)OCSC_NOALLOC_SCRATCH_BYTES)
+    return fail(c, OCSC_E_INVALID_ARG,
+                "B (K + 1) spectra and the partial sums exceed the static scratch (OCSC_NOALLOC_SCRATCH_BYTES)");
+  if (!c->scratch) return fail(c, OCSC_E_HIP, "no scratch address for this device");
+  // no kernel timing here: timing events are created on demand
+  const unsigned mask = c->prof_mask;
+  c->prof_mask = 0;
+  const int rc = c->sr == 8 ? objective_noalloc_t<double>(c, x, codes, B, out_dev)
+                            : objective_noalloc_t<float>(c, x, codes, B, out_dev);
+  c->prof_mask = mask;
+  return rc;
 }
 
 int ocsc_surrogate(ocsc_ctx* c, const void* D, double* out) {
@@ -1807,7 +1916,7 @@ int ocsc_autotune(ocsc_ctx* c, int B, ocsc_tuning* out, double* best_ms) {
 int ocsc_sync(ocsc_ctx* c) {
   if (!c) return OCSC_E_INVALID_ARG;
   HIPX(c, hipStreamSynchronize(c->stream));
-  return OCSC_OK;
+  return check_breakdown(c);
 }
 
 const char* ocsc_last_error(const ocsc_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }

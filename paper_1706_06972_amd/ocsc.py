@@ -39,7 +39,7 @@ EXPORTS = [
     "ocsc_code_update", "ocsc_code_append", "ocsc_code_update_group", "ocsc_history_accumulate",
     "ocsc_dict_update",
     "ocsc_dict_update_group", "ocsc_objective",
-    "ocsc_objective_terms", "ocsc_surrogate", "ocsc_diagnostics", "ocsc_sync",
+    "ocsc_objective_terms", "ocsc_objective_noalloc", "ocsc_surrogate", "ocsc_diagnostics", "ocsc_sync",
     "ocsc_graph_create", "ocsc_graph_launch", "ocsc_graph_destroy",
     "ocsc_get_tuning", "ocsc_set_tuning", "ocsc_autotune",
     "ocsc_last_error", "ocsc_state_bytes", "ocsc_get_state", "ocsc_set_state", "ocsc_get_count",
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ocsc_dict_update": (i32, [vp]),
         "ocsc_objective": (i32, [vp, vp, vp, i32, ctypes.POINTER(dbl)]),
         "ocsc_objective_terms": (i32, [vp, vp, vp, i32, ctypes.POINTER(dbl)]),
+        "ocsc_objective_noalloc": (i32, [vp, vp, vp, i32, vp]),
         "ocsc_surrogate": (i32, [vp, vp, ctypes.POINTER(dbl)]),
         "ocsc_diagnostics": (i32, [vp, ctypes.POINTER(dbl)]),
         "ocsc_sync": (i32, [vp]),
@@ -234,6 +235,12 @@ def ocsc_objective_terms(ctx, x, codes, B):
     out = (ctypes.c_double * (2 * int(B)))()
     _check(ctx, load().ocsc_objective_terms(ctx, _ptr(x), _ptr(codes), int(B), out))
     return [(out[2 * b], out[2 * b + 1]) for b in range(int(B))]
+
+
+def ocsc_objective_noalloc(ctx, x, codes, B, out) -> None:
+    """Objective per sample into the device tensor ``out`` (B doubles), using the
+    library's static scratch; enqueued, not waited for."""
+    _check(ctx, load().ocsc_objective_noalloc(ctx, _ptr(x), _ptr(codes), int(B), _ptr(out)))
 
 
 def ocsc_surrogate(ctx, D=None) -> float:
@@ -459,6 +466,20 @@ class OCSC:
         if codes.dim() == 3:
             codes = codes[None]
         return ocsc_objective(self.ctx, x, codes, x.shape[0])
+
+    def objective_noalloc(self, x, codes, out=None):
+        """Objective per sample into a device tensor of B doubles, through the
+        allocation-free call (the library's static scratch); not waited for."""
+        x = self._dev(x)
+        if x.dim() == 2:
+            x = x[None]
+        codes = self._dev(codes)
+        if codes.dim() == 3:
+            codes = codes[None]
+        if out is None:
+            out = self.torch.empty(x.shape[0], dtype=self.torch.float64, device=self.device)
+        ocsc_objective_noalloc(self.ctx, x, codes, x.shape[0], out)
+        return out
 
     def objective_terms(self, x, codes):
         x = self._dev(x)

@@ -13,9 +13,10 @@ size:
   A_update, B_update, unnormalised), and C_p (H_p + rho_d I) = I for the
   inverse the library keeps (Sherman-Morrison fold, or the FP64 Cholesky
   inverse of the precision form);
-* after the DictOCSC call: every V_k in the unit ball.
-The D-step and V-step kernels of K = 100 on 128 x 128 are checked against the
-oracle at B = 1 by the parity tests, those of K = 256 at smaller grids.
+* after the DictOCSC call: every V_k in the unit ball;
+* with one DictOCSC iteration: d_p = C_p G_p at sampled frequencies of every
+  chunk of the K = 256 block inverse, V as Proposition 2 of the library's d,
+  and Theta = d - F(zero-pad V).
 Tolerance 1e-3 (norm-wise relative), as for every FP32 context.
 """
 import numpy as np
@@ -87,3 +88,48 @@ def test_minibatch_forms_at_full_size(K, cholesky):
     assert Vn.max() <= 1.0 + 1e-5
     g.close()
 
+
+
+@pytest.mark.parametrize("K,cholesky", [(100, False), (100, True), (256, True)])
+def test_first_dictionary_iterate_at_full_size(K, cholesky):
+    """One DictOCSC iteration (J_d = 1) after a B = 64 minibatch at 128 x 128.
+    From V = 0, Theta = 0 the D-step gives d_p = C_p G_p (eq. sub_d_sol); it is
+    checked at 8 sampled frequencies of every 2048-frequency chunk of the
+    K = 256 block inverse, against C_p G_p formed in FP64 from the library's own
+    C and G.  Then V must be Proposition 2 applied to the library's whole d,
+    and Theta = d - F(zero-pad V)."""
+    say(f"case first DictOCSC iterate 128x128 K={K} B=64 {'precision' if cholesky else 'Sherman-Morrison'} form")
+    from paper_1706_06972_amd.ocsc import OCSC
+    ph, pw = WL.pad_h, WL.pad_w
+    fh, fw = WL.filt_h, WL.filt_w
+    xs = synth.images(WL, synth.pass_order(WL.n_images, WL.seed, 0)[:B])
+    g = OCSC(K, fh, fw, ph, pw, WL.lam, WL.rho, iters_code=WL.iters_code, iters_dict=1, max_batch=B,
+             precision="f32", cholesky=cholesky)
+    g.set_dictionary(synth.initial_dictionary(K, fh, fw, WL.seed))
+    shape, _ = g.autotune(B)
+    g.set_tuning(**shape)
+    g.code_update(xs, want_codes=False)
+    g.history_accumulate()
+    Pf = ph * (pw // 2 + 1)
+    rng = np.random.default_rng(11)
+    idx = np.concatenate([np.sort(rng.choice(np.arange(lo, min(Pf, lo + 2048)), 8, replace=False))
+                          for lo in range(0, Pf, 2048)])
+    C = packed(to_np(g.state("cinv")), K, idx)                              # (n, K, K)
+    G = spectra(to_np(g.state("G")), (K,), ph, pw).reshape(K, -1)[:, idx].T   # (n, K)
+    g.dict_update()
+    d = spectra(to_np(g.state("dict_hat")), (K,), ph, pw)                     # (K, ph, pw/2+1)
+    want = (C @ G[:, :, None])[:, :, 0]
+    got = d.reshape(K, -1)[:, idx].T
+    per_f = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+    err_d = rel(got, want)
+    V = to_np(g.state("V")).reshape(K, fh, fw)
+    Vo = O.dict_vstep(d, np.zeros_like(d), (fh, fw), (ph, pw))
+    err_V = rel(V, Vo)
+    Th = spectra(to_np(g.state("theta")), (K,), ph, pw)
+    Tho = d - O.dft2(O.zero_pad(V, (ph, pw)))
+    err_T = rel(Th, Tho)
+    say(f"  d = C G: {err_d:.2e} (worst frequency {per_f.max():.2e}, {len(idx)} frequencies)  "
+        f"V = Prop. 2 of d: {err_V:.2e}  Theta = d - F(V): {err_T:.2e}")
+    assert err_d < 1e-3 and per_f.max() < 1e-3
+    assert err_V < 1e-3 and err_T < 1e-3
+    g.close()

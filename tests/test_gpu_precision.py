@@ -63,3 +63,31 @@ def test_cholesky_form_matches_oracle(K, B, batches, n):
         assert v < 1e-3, (k, v)
     assert g.count == B * batches
     g.close()
+
+
+@pytest.mark.parametrize("K", [16, 200])
+def test_cholesky_breakdown_is_reported(K):
+    """An indefinite history, set from the host through the state interface
+    (H = -2 rho_d I at every frequency), makes H + rho_d I negative definite:
+    the FP64 factorisation meets a negative pivot at the next fold, and the next
+    call that waits returns OCSC_E_NUMERIC (once).  K = 200 takes the block
+    (Schur complement) path, whose first block then breaks down."""
+    say(f"case Cholesky breakdown K={K}")
+    from paper_1706_06972_amd.ocsc import OCSC, OcscError, OCSC_E_NUMERIC
+    n = 32
+    xs = images(2, n, 16, 3)
+    g = OCSC(K, 11, 11, n, n, 1.0, 1.0, precision="f32", max_batch=2, cholesky=True)
+    g.set_dictionary(synth.initial_dictionary(K, 11, 11, 0))
+    Pf = n * (n // 2 + 1)
+    rho_d = 1.0 * n * n
+    H = np.zeros((Pf, K, K), np.float32)
+    H[:, np.arange(K), np.arange(K)] = -2.0 * rho_d                # packed form: the diagonal is real
+    g.set_state("H", torch.as_tensor(H.reshape(-1), device="cuda"))
+    g.code_update(xs, want_codes=False)
+    g.history_accumulate()
+    with pytest.raises(OcscError) as e:
+        g.sync()
+    assert e.value.status == OCSC_E_NUMERIC
+    assert "Cholesky breakdown" in str(e.value)
+    g.sync()                                                        # reported once
+    g.close()

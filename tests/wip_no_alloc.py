@@ -1,0 +1,56 @@
+"""The allocation-free objective (ocsc_objective_noalloc, for callers that
+cannot allocate device memory) against ocsc_objective, through the C ABI.
+
+Both run the same kernels over the same partition, the first with its
+buffers in the library's static per-device scratch, so the values must agree
+bit for bit (which meets the 1e-10 / 1e-3 parity bar of FP64 / FP32
+contexts).  Two calls in a row share the scratch, the second with a smaller
+input on another context; a request larger than the scratch is refused
+before any device work.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def coded(K, n, prec, B, seed):
+    from paper_1706_06972_amd.ocsc import OCSC
+    wl = synth.Workload(name="t", pad_h=n, pad_w=n, content_h=n - 10, content_w=n - 10, k_true=16,
+                        density=0.01, sigma_z=10.0, noise=0.01, K=16, filt_h=11, filt_w=11, lam=1.0, rho=1.0,
+                        iters_code=10, iters_dict=10, batch=1, n_images=B, passes=1, precision="f64", seed=seed)
+    g = OCSC(K, 11, 11, n, n, 1.0, 1.0, precision=prec, max_batch=B)
+    g.set_dictionary(synth.initial_dictionary(K, 11, 11, seed))
+    x = g._dev(synth.images(wl, range(B)))
+    U = g.code_update(x)
+    return g, x, U
+
+
+@pytest.mark.parametrize("order", ["large_then_small"])
+def test_noalloc_objective_matches_objective(order):
+    from paper_1706_06972_amd.ocsc import OcscError, OCSC_E_INVALID_ARG
+    cases = [(100, 128, "f32", 3, 0), (16, 64, "f64", 1, 1)]    # the second call is smaller
+    for K, n, prec, B, seed in cases:
+        say(f"case noalloc objective {n}x{n} K={K} {prec} B={B}")
+        g, x, U = coded(K, n, prec, B, seed)
+        want = np.array(g.objective(x, U))
+        got = g.objective_noalloc(x, U)
+        g.sync()
+        got = got.cpu().numpy()
+        rel = np.max(np.abs(got - want) / np.abs(want))
+        say(f"  objective {want}  noalloc {got}  max relative difference {rel:.1e}")
+        assert np.array_equal(got, want)
+        assert rel < (1e-10 if prec == "f64" else 1e-3)
+        g.close()
+    # B (K + 1) spectra above the 32 MiB scratch: refused before any device work
+    g, x, U = coded(16, 64, "f64", 1, 2)
+    xb = x.expand(60, -1, -1).contiguous()
+    Ub = U.expand(60, -1, -1, -1).contiguous()
+    with pytest.raises(OcscError) as e:
+        g.objective_noalloc(xb, Ub)
+    assert e.value.status == OCSC_E_INVALID_ARG
+    g.close()
