@@ -95,6 +95,14 @@ typedef struct {
  * is reported once, as OCSC_E_NUMERIC, by the next ocsc_sync,
  * ocsc_objective, ocsc_objective_terms, ocsc_surrogate or ocsc_diagnostics. */
 #define OCSC_FLAG_CHOLESKY 8
+/* opts.flags, with OCSC_FLAG_CHOLESKY only (else OCSC_E_UNSUPPORTED): after
+ * every D-step, one step of iterative refinement of d_p = (H_p + rho_d I)^-1 rhs_p
+ * (eq. sub_d_sol) against the kept history: r_p = rhs_p - (H_p + rho_d I) d_p
+ * formed from the FP32 H_p and d_p with FP64 sums, then d_p += C_p r_p.  It
+ * removes the error of the FP32 rounding of C_p (not that of H_p itself), at
+ * the cost of two more passes over K x K reals per frequency in each of the
+ * iters_dict D-steps. */
+#define OCSC_FLAG_REFINE 16
 
 /* Fill *opts with the defaults listed above. */
 void ocsc_default_opts(ocsc_opts* opts);

@@ -853,4 +853,120 @@ __global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ 
   if (t < K) dout[(size_t)t * Pf + p] = make_float2(dc.x + drow[t].x, dc.y + drow[t].y);
 }
 
+// ---------------------------------------------------------------------------
+// One step of iterative refinement of the D-step solve (eq. sub_d_sol) in the
+// precision form, against the history H_p the context keeps:
+//   r_p = rhs_p - (H_p + rho_d I) d_p      (products of FP32 values, summed in FP64),
+//   d_p <- d_p + C_p r_p                   (FP64 sums, rounded once to FP32).
+// The FP64 Cholesky factors solve the stored H to ~1e-15; what the refinement
+// removes is the error of using the FP32 rounding of C_p = (H_p + rho_d I)^-1.
+// One workgroup of 256 threads per frequency; H_p and then C_p pass through
+// LDS in strips of 16 rows, each stored real serving a row and a column
+// output as in k_dstep_stream.  K <= 256; d is updated in place.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dstep_refine(const float* __restrict__ Hm, const float* __restrict__ Cm,
+                                                      int fs, int K, int Pf, double rho_d,
+                                                      const float2* __restrict__ rhs, float2* __restrict__ d) {
+  __shared__ float strip[DS_ROWS * DS_PITCH];
+  __shared__ double2 xv[256], acc[256];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int ld = K + 1;
+  const int rr = t >> 4, q = t & 15;
+  int rc[DS_ROWS];
+#pragma unroll
+  for (int m = 0; m < DS_ROWS; ++m) {
+    const int e = t + m * 256, r = e / K;
+    rc[m] = r * 512 + (e - r * K);
+  }
+  float2 d0 = make_float2(0.f, 0.f);
+  if (t < K) {
+    d0 = d[(size_t)t * Pf + p];
+    xv[t] = make_double2((double)d0.x, (double)d0.y);
+  }
+  // y = M x for the Hermitian M stored in the R-form at R (FP64 sums);
+  // returns output t (t < K) to the thread that owns it
+  auto matvec = [&](const float* __restrict__ R) -> double2 {
+    float pf[DS_ROWS];
+    auto fetch = [&](int a0) {
+      const int nr = min(DS_ROWS, K - a0);
+#pragma unroll
+      for (int m = 0; m < DS_ROWS; ++m) {
+        const int r = rc[m] >> 9, cc = rc[m] & 511;
+        if (r < nr) pf[m] = R[(size_t)(a0 + r) * ld + cc];
+      }
+    };
+    if (t < K) acc[t] = make_double2(0.0, 0.0);
+    double2 dc = make_double2(0.0, 0.0);
+    fetch(0);
+    __syncthreads();
+    for (int a0 = 0; a0 < K; a0 += DS_ROWS) {
+      const int nr = min(DS_ROWS, K - a0);
+#pragma unroll
+      for (int m = 0; m < DS_ROWS; ++m) {
+        const int r = rc[m] >> 9, cc = rc[m] & 511;
+        if (r < nr) strip[r * DS_PITCH + cc] = pf[m];
+      }
+      __syncthreads();
+      if (a0 + DS_ROWS < K) fetch(a0 + DS_ROWS);
+      if (t < K) {   // column role: output t
+        for (int r = 0; r < nr; ++r) {
+          const int a = a0 + r;
+          const double v = (double)strip[r * DS_PITCH + t];
+          const double2 xa = xv[a];
+          if (a <= t) {
+            dc.x = fma(v, xa.x, dc.x);
+            dc.y = fma(v, xa.y, dc.y);
+          } else {
+            dc.x = fma(-v, xa.y, dc.x);
+            dc.y = fma(v, xa.x, dc.y);
+          }
+        }
+      }
+      double2 sum = make_double2(0.0, 0.0);   // row role: output a0 + rr, columns q, q + 16, ...
+      if (rr < nr) {
+        const int a = a0 + rr;
+        for (int b = q; b < K; b += 16) {
+          if (b == a) continue;
+          const double v = (double)strip[rr * DS_PITCH + b];
+          const double2 xb = xv[b];
+          if (a < b) {
+            sum.x = fma(v, xb.x, sum.x);
+            sum.y = fma(v, xb.y, sum.y);
+          } else {
+            sum.x = fma(v, xb.y, sum.x);
+            sum.y = fma(-v, xb.x, sum.y);
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        sum.x += __shfl_xor(sum.x, off, 16);
+        sum.y += __shfl_xor(sum.y, off, 16);
+      }
+      if (rr < nr && q == 0) {
+        double2 s = acc[a0 + rr];
+        s.x += sum.x;
+        s.y += sum.y;
+        acc[a0 + rr] = s;
+      }
+      __syncthreads();   // the strip is overwritten next
+    }
+    double2 y = make_double2(0.0, 0.0);
+    if (t < K) y = make_double2(dc.x + acc[t].x, dc.y + acc[t].y);
+    __syncthreads();   // acc and xv are reused by the caller
+    return y;
+  };
+  // r = rhs - H d - rho_d d
+  const double2 hd = matvec(Hm + (size_t)p * fs);
+  if (t < K) {
+    const float2 b = rhs[(size_t)t * Pf + p];
+    xv[t] = make_double2((double)b.x - hd.x - rho_d * (double)d0.x, (double)b.y - hd.y - rho_d * (double)d0.y);
+  }
+  __syncthreads();
+  // d += C r
+  const double2 cr = matvec(Cm + (size_t)p * fs);
+  if (t < K)
+    d[(size_t)t * Pf + p] = make_float2((float)((double)d0.x + cr.x), (float)((double)d0.y + cr.y));
+}
+
 }  // namespace ocsc

@@ -5,6 +5,7 @@
 // kernels of kernels.hpp on that stream.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <cstdint>
@@ -69,6 +70,7 @@ struct ocsc_ctx {
   int chol_chunk = 0;         // K > 128: frequencies per Schur-complement chunk
   void* Wchol = nullptr;      // K > 128: five 128 x 128 FP64 blocks per frequency of a chunk
   bool warm = false;          // OCSC_FLAG_WARM_START
+  bool refine = false;        // OCSC_FLAG_REFINE: one refinement step after each D-step (precision form)
   ocsc_tuning tune{};         // launch shapes of the code update (ocsc_set_tuning / ocsc_autotune)
   // runtime
   int device = 0;
@@ -124,6 +126,17 @@ int fail(ocsc_ctx* c, int code, const std::string& msg) {
     if (e_ != hipSuccess)                                                                    \
       return fail(ctx, OCSC_E_HIP, std::string("kernel launch: ") + hipGetErrorString(e_));  \
   } while (0)
+
+// A roctx range around each C-ABI call that enqueues or waits for work, so
+// that a profiler trace (rocprofv3 --marker-trace) shows the host call above
+// its kernels.  Without a profiler attached the calls cost a few nanoseconds.
+struct ApiRange {
+  explicit ApiRange(const char* name) { roctxRangePushA(name); }
+  ~ApiRange() { roctxRangePop(); }
+  ApiRange(const ApiRange&) = delete;
+  ApiRange& operator=(const ApiRange&) = delete;
+};
+#define OCSC_RANGE() ApiRange api_range_(__func__)
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
@@ -817,6 +830,21 @@ struct StreamJoin {
   }
 };
 
+// Precision form with OCSC_FLAG_REFINE: one step of iterative refinement of
+// d = C rhs against the kept H (k_dstep_refine), in place.
+template <typename T>
+int launch_refine(ocsc_ctx* c, const void* rhs) {
+  if (!c->refine) return OCSC_OK;
+  if constexpr (std::is_same<T, float>::value) {
+    ProfScope ps(c, OCSC_KC_OTHER);
+    hipLaunchKernelGGL(k_dstep_refine, dim3(c->Pf), dim3(256), 0, c->stream, (const float*)c->Hm,
+                       (const float*)c->Cm, c->fs, c->K, c->Pf, c->rho_d, (const float2*)rhs, (float2*)c->d);
+    LAUNCHED(c);
+    return OCSC_OK;
+  }
+  return fail(c, OCSC_E_UNSUPPORTED, "refinement is part of the FP32 precision form");
+}
+
 template <typename T>
 int dict_update_t(ocsc_ctx* c) {
   for (int tau = 0; tau < c->Jd; ++tau) {
@@ -829,6 +857,7 @@ int dict_update_t(ocsc_ctx* c) {
     } else {
       const void* r = (tau == 0 && !c->warm) ? c->G : c->rhs;
       rc = launch_sweep<T>(c, 0, r, nullptr, c->d, OCSC_KC_DSTEP);
+      if (!rc) rc = launch_refine<T>(c, r);
     }
     if (rc) return rc;
     rc = launch_vstep<T>(c, tau == 0 && !c->warm);
@@ -866,6 +895,7 @@ int dict_update_group_t(ocsc_ctx* const* cs, int n) {
         c->fold_B = 0;
       } else {
         rc = launch_sweep<T>(c, 0, tau == 0 ? c->G : c->rhs, nullptr, c->d, OCSC_KC_DSTEP);
+        if (!rc) rc = launch_refine<T>(c, tau == 0 ? c->G : c->rhs);
       }
       if (rc) return rc;
     }
@@ -1254,6 +1284,7 @@ void ocsc_default_opts(ocsc_opts* o) {
 
 int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_w, double lambda, double rho,
               const ocsc_opts* opts) {
+  OCSC_RANGE();
   g_init_error.clear();
   if (!out) return fail(nullptr, OCSC_E_INVALID_ARG, "out is NULL");
   ocsc_opts o;
@@ -1274,8 +1305,11 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   if (o.max_batch < 1 || o.max_batch > 65535) return fail(nullptr, OCSC_E_INVALID_ARG, "max_batch must be in [1, 65535]");
   if (o.precision != OCSC_FP64 && o.precision != OCSC_FP32)
     return fail(nullptr, OCSC_E_INVALID_ARG, "unknown precision");
-  if (o.flags & ~(OCSC_FLAG_OWN_STREAM | OCSC_FLAG_KEEP_HISTORY | OCSC_FLAG_WARM_START | OCSC_FLAG_CHOLESKY))
+  if (o.flags & ~(OCSC_FLAG_OWN_STREAM | OCSC_FLAG_KEEP_HISTORY | OCSC_FLAG_WARM_START | OCSC_FLAG_CHOLESKY |
+                  OCSC_FLAG_REFINE))
     return fail(nullptr, OCSC_E_INVALID_ARG, "unknown bits in opts->flags");
+  if ((o.flags & OCSC_FLAG_REFINE) && !(o.flags & OCSC_FLAG_CHOLESKY))
+    return fail(nullptr, OCSC_E_UNSUPPORTED, "OCSC_FLAG_REFINE needs OCSC_FLAG_CHOLESKY");
   if ((o.flags & OCSC_FLAG_CHOLESKY) &&
       (o.precision != OCSC_FP32 || K > 256 || (o.flags & OCSC_FLAG_WARM_START)))
     return fail(nullptr, OCSC_E_UNSUPPORTED, "the Cholesky form needs an FP32 context, K <= 256 and a cold start");
@@ -1357,6 +1391,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   c->chol_chunk = dstream ? std::min(c->Pf, 2048) : 0;
   c->keep_hist = (o.flags & OCSC_FLAG_KEEP_HISTORY) != 0 || c->chol;
   c->warm = (o.flags & OCSC_FLAG_WARM_START) != 0;
+  c->refine = (o.flags & OCSC_FLAG_REFINE) != 0;
   c->vstep_fused = sr == 8 ? vstep_fused_ok<double>(pad_h, pad_w, filt_h, filt_w)
                            : vstep_fused_ok<float>(pad_h, pad_w, filt_h, filt_w);
 
@@ -1471,6 +1506,7 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
 }
 
 int ocsc_destroy(ocsc_ctx* c) {
+  OCSC_RANGE();
   if (!c) return OCSC_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_all(c);
@@ -1480,6 +1516,7 @@ int ocsc_destroy(ocsc_ctx* c) {
 }
 
 int ocsc_set_dictionary(ocsc_ctx* c, const void* D) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!D) return fail(c, OCSC_E_INVALID_ARG, "D_dev is NULL");
   const long fs = (long)c->Mh * c->Mw;
@@ -1491,6 +1528,7 @@ int ocsc_set_dictionary(ocsc_ctx* c, const void* D) {
 }
 
 int ocsc_get_dictionary(ocsc_ctx* c, void* D) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!D) return fail(c, OCSC_E_INVALID_ARG, "D_dev_out is NULL");
   const long fs = (long)c->Mh * c->Mw;
@@ -1499,6 +1537,7 @@ int ocsc_get_dictionary(ocsc_ctx* c, void* D) {
 }
 
 int ocsc_code_update(ocsc_ctx* c, const void* x, int B, void* codes) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!x) return fail(c, OCSC_E_INVALID_ARG, "x_dev is NULL");
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
@@ -1507,6 +1546,7 @@ int ocsc_code_update(ocsc_ctx* c, const void* x, int B, void* codes) {
 }
 
 int ocsc_code_update_group(ocsc_ctx* const* ctxs, const void* const* xs, const int* Bs, void* const* codes, int n) {
+  OCSC_RANGE();
   if (!ctxs || !xs || !Bs || n < 1 || n > CG_MAX)
     return fail(nullptr, OCSC_E_INVALID_ARG, "need 1 <= n <= 8 contexts, samples and batch sizes");
   ocsc_ctx* c0 = ctxs[0];
@@ -1539,6 +1579,7 @@ int ocsc_code_update_group(ocsc_ctx* const* ctxs, const void* const* xs, const i
 }
 
 int ocsc_code_append(ocsc_ctx* c, const void* x, int B, void* codes) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!x) return fail(c, OCSC_E_INVALID_ARG, "x_dev is NULL");
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
@@ -1549,6 +1590,7 @@ int ocsc_code_append(ocsc_ctx* c, const void* x, int B, void* codes) {
 }
 
 int ocsc_history_accumulate(ocsc_ctx* c) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (c->pending_B == 0) return fail(c, OCSC_E_STATE, "no coded samples to accumulate");
   if (c->keep_hist) {
@@ -1569,12 +1611,14 @@ int ocsc_history_accumulate(ocsc_ctx* c) {
 }
 
 int ocsc_dict_update(ocsc_ctx* c) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (c->t == 0) return fail(c, OCSC_E_STATE, "dict_update needs at least one accumulated sample");
   return c->sr == 8 ? dict_update_t<double>(c) : dict_update_t<float>(c);
 }
 
 int ocsc_dict_update_group(ocsc_ctx* const* ctxs, int n) {
+  OCSC_RANGE();
   if (!ctxs || n < 1 || n > GROUP_MAX) return fail(nullptr, OCSC_E_INVALID_ARG, "need 1 <= n <= 8 contexts");
   ocsc_ctx* c0 = ctxs[0];
   if (!c0) return fail(nullptr, OCSC_E_INVALID_ARG, "NULL context");
@@ -1605,6 +1649,7 @@ int ocsc_dict_update_group(ocsc_ctx* const* ctxs, int n) {
 }
 
 int ocsc_objective(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!x || !codes || !out) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
@@ -1613,6 +1658,7 @@ int ocsc_objective(ocsc_ctx* c, const void* x, const void* codes, int B, double*
 }
 
 int ocsc_objective_terms(ocsc_ctx* c, const void* x, const void* codes, int B, double* out) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!x || !codes || !out) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
@@ -1621,6 +1667,7 @@ int ocsc_objective_terms(ocsc_ctx* c, const void* x, const void* codes, int B, d
 }
 
 int ocsc_objective_noalloc(ocsc_ctx* c, const void* x, const void* codes, int B, double* out_dev) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!x || !codes || !out_dev) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
@@ -1640,6 +1687,7 @@ int ocsc_objective_noalloc(ocsc_ctx* c, const void* x, const void* codes, int B,
 }
 
 int ocsc_surrogate(ocsc_ctx* c, const void* D, double* out) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!out) return fail(c, OCSC_E_INVALID_ARG, "out_host is NULL");
   if ((uintptr_t)D & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
@@ -1648,6 +1696,7 @@ int ocsc_surrogate(ocsc_ctx* c, const void* D, double* out) {
 }
 
 int ocsc_diagnostics(ocsc_ctx* c, double* out) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!out) return fail(c, OCSC_E_INVALID_ARG, "out_host is NULL");
   return c->sr == 8 ? diagnostics_t<double>(c, out) : diagnostics_t<float>(c, out);
@@ -1810,6 +1859,7 @@ struct ocsc_graph {
 extern "C" {
 
 int ocsc_graph_create(ocsc_ctx* c, const void* x, int B, void* codes, ocsc_graph** out) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (!x || !out) return fail(c, OCSC_E_INVALID_ARG, "NULL buffer");
   if (((uintptr_t)x | (uintptr_t)codes) & 15) return fail(c, OCSC_E_INVALID_ARG, "buffers must be 16-byte aligned");
@@ -1860,6 +1910,7 @@ int ocsc_graph_create(ocsc_ctx* c, const void* x, int B, void* codes, ocsc_graph
 }
 
 int ocsc_graph_launch(ocsc_graph* gr) {
+  OCSC_RANGE();
   if (!gr) return OCSC_E_INVALID_ARG;
   ocsc_ctx* c = gr->c;
   if (c->pending_B || c->fold_B) return fail(c, OCSC_E_STATE, "pending codes or a deferred fold");
@@ -1897,6 +1948,7 @@ int ocsc_set_tuning(ocsc_ctx* c, const ocsc_tuning* t) {
 }
 
 int ocsc_autotune(ocsc_ctx* c, int B, ocsc_tuning* out, double* best_ms) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   if (B < 1 || B > c->maxB) return fail(c, OCSC_E_INVALID_ARG, "B must be in [1, max_batch]");
   if (c->pending_B) return fail(c, OCSC_E_STATE, "pending codes occupy the code workspace");
@@ -1914,6 +1966,7 @@ int ocsc_autotune(ocsc_ctx* c, int B, ocsc_tuning* out, double* best_ms) {
 }
 
 int ocsc_sync(ocsc_ctx* c) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   HIPX(c, hipStreamSynchronize(c->stream));
   return check_breakdown(c);
@@ -1930,6 +1983,7 @@ int ocsc_state_bytes(const ocsc_ctx* c, int which, int64_t* out) {
 }
 
 int ocsc_get_state(ocsc_ctx* c, int which, void* dst) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   size_t n = 0;
   if (!dst || state_bytes(c, which, &n)) return fail(c, OCSC_E_INVALID_ARG, "bad state item or NULL dst");
@@ -1949,6 +2003,7 @@ int ocsc_get_state(ocsc_ctx* c, int which, void* dst) {
 }
 
 int ocsc_set_state(ocsc_ctx* c, int which, const void* src) {
+  OCSC_RANGE();
   if (!c) return OCSC_E_INVALID_ARG;
   size_t n = 0;
   if (!src || state_bytes(c, which, &n) || which == OCSC_STATE_ZHAT || which == OCSC_STATE_XHAT)

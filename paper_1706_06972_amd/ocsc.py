@@ -13,7 +13,9 @@ import os
 from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libocsc.so")
+# OCSC_LIBRARY selects another build of the same library (the host-sanitized
+# build that the CPU ABI tests load); by default the in-tree libocsc.so.
+LIB_PATH = os.environ.get("OCSC_LIBRARY") or os.path.join(HERE, "libocsc.so")
 
 OCSC_OK = 0
 OCSC_E_INVALID_ARG = -1
@@ -29,6 +31,7 @@ OCSC_FLAG_OWN_STREAM = 1
 OCSC_FLAG_KEEP_HISTORY = 2
 OCSC_FLAG_WARM_START = 4
 OCSC_FLAG_CHOLESKY = 8
+OCSC_FLAG_REFINE = 16
 
 STATE = {"dict_hat": 0, "G": 1, "cinv": 2, "V": 3, "theta": 4, "zhat": 5, "xhat": 6, "H": 7, "sums": 8,
          "rhs": 9}
@@ -355,7 +358,7 @@ class OCSC:
 
     def __init__(self, K, filt_h, filt_w, pad_h, pad_w, lam, rho, *, iters_code=10, iters_dict=10,
                  max_batch=1, precision="f64", rho_dict=0.0, keep_history=False, warm_start=False,
-                 cholesky=False, device="cuda"):
+                 cholesky=False, refine=False, device="cuda"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -364,7 +367,7 @@ class OCSC:
         self.dtype = torch.float64 if precision == "f64" else torch.float32
         with torch.cuda.device(self.device):
             flags = ((OCSC_FLAG_KEEP_HISTORY if keep_history else 0) | (OCSC_FLAG_WARM_START if warm_start else 0)
-                     | (OCSC_FLAG_CHOLESKY if cholesky else 0))
+                     | (OCSC_FLAG_CHOLESKY if cholesky else 0) | (OCSC_FLAG_REFINE if refine else 0))
             self.ctx = ocsc_init(K, filt_h, filt_w, pad_h, pad_w, lam, rho, iters_code=iters_code,
                                  iters_dict=iters_dict, max_batch=max_batch, precision=precision,
                                  rho_dict=rho_dict, flags=flags)

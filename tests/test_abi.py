@@ -58,10 +58,18 @@ def test_init_rejects_bad_opts():
     o.struct_size = 8
     assert init_rc(opts=ctypes.byref(o))[0] == B.OCSC_E_INVALID_ARG
     for field, val in (("iters_code", 0), ("iters_dict", 0), ("max_batch", 0), ("precision", 7),
-                       ("flags", 16), ("flags", B.OCSC_FLAG_KEEP_HISTORY | 32)):
+                       ("flags", 64), ("flags", B.OCSC_FLAG_KEEP_HISTORY | 32)):
         o = B.ocsc_default_opts()
         setattr(o, field, val)
         assert init_rc(opts=ctypes.byref(o))[0] == B.OCSC_E_INVALID_ARG, field
+
+
+def test_refinement_needs_the_cholesky_form():
+    o = B.ocsc_default_opts()
+    o.precision, o.flags = B.OCSC_FP32, B.OCSC_FLAG_REFINE
+    rc, ctx, msg = init_rc(opts=ctypes.byref(o))
+    assert rc == B.OCSC_E_UNSUPPORTED and ctx.value is None
+    assert "OCSC_FLAG_REFINE" in msg
 
 
 def test_cholesky_form_limits():

@@ -22,14 +22,18 @@ def images(n, ph, K_true, seed):
     return synth.images(wl, range(n))
 
 
-@pytest.mark.parametrize("K,B,batches,n", [(16, 8, 2, 64), (100, 6, 2, 64), (40, 70, 1, 64), (256, 4, 2, 32),
-                                           (200, 3, 1, 32), (129, 2, 1, 32), (120, 3, 1, 32)])
-def test_cholesky_form_matches_oracle(K, B, batches, n):
-    """K > 128 takes the block (Schur complement) inverse and the streaming D-step."""
-    say(f"case precision form K={K} B={B} grid {n}")
+@pytest.mark.parametrize("K,B,batches,n,refine", [(16, 8, 2, 64, False), (100, 6, 2, 64, False),
+                                                  (40, 70, 1, 64, False), (256, 4, 2, 32, False),
+                                                  (200, 3, 1, 32, False), (129, 2, 1, 32, False),
+                                                  (120, 3, 1, 32, False), (100, 6, 2, 64, True),
+                                                  (256, 4, 2, 32, True)])
+def test_cholesky_form_matches_oracle(K, B, batches, n, refine):
+    """K > 128 takes the block (Schur complement) inverse and the streaming
+    D-step; refine adds one refinement step after each D-step."""
+    say(f"case precision form K={K} B={B} grid {n}{' with refinement' if refine else ''}")
     from paper_1706_06972_amd.ocsc import OCSC
     xs = images(B * batches, n, 16, 11)
-    g = OCSC(K, 11, 11, n, n, 1.0, 1.0, precision="f32", max_batch=B, cholesky=True)
+    g = OCSC(K, 11, 11, n, n, 1.0, 1.0, precision="f32", max_batch=B, cholesky=True, refine=refine)
     o = O.OCSC(K, 11, 11, n, n, 1.0, 1.0, keep_history=True)
     D0 = synth.initial_dictionary(K, 11, 11, 0)
     g.set_dictionary(D0)
@@ -91,3 +95,40 @@ def test_cholesky_breakdown_is_reported(K):
     assert "Cholesky breakdown" in str(e.value)
     g.sync()                                                        # reported once
     g.close()
+
+
+@pytest.mark.parametrize("K", [100, 256])
+def test_refinement_of_the_dstep_solve(K):
+    """One DictOCSC iteration (J_d = 1, so d_p solves (H_p + rho_d I) d_p = G_p,
+    eq. sub_d_sol from V = Theta = 0), without and with the refinement step,
+    on the same minibatch.  Each d is compared with the FP64 solve of the
+    library's own H and G; the errors and solve residuals are printed.  The
+    refined solve must not be worse than the plain one beyond FP32 rounding."""
+    say(f"case refinement of the D-step solve K={K}")
+    from paper_1706_06972_amd.ocsc import OCSC
+    n, B = 32, 4
+    xs = images(2 * B, n, 16, 13)
+    D0 = synth.initial_dictionary(K, 11, 11, 0)
+    res = {}
+    for refine in (False, True):
+        g = OCSC(K, 11, 11, n, n, 1.0, 1.0, precision="f32", max_batch=B, cholesky=True, refine=refine,
+                 iters_dict=1)
+        g.set_dictionary(D0)
+        for bi in range(2):
+            g.code_update(xs[bi * B:(bi + 1) * B], want_codes=False)
+            g.history_accumulate()
+            if bi == 0:
+                g.dict_update()
+        H = unpack_cinv(to_np(g.state("H")), K, n, n).reshape(-1, K, K)
+        G = spectra(to_np(g.state("G")), (K,), n, n).reshape(K, -1).T
+        g.dict_update()
+        d = spectra(to_np(g.state("dict_hat")), (K,), n, n).reshape(K, -1).T
+        A = H + (n * n) * np.eye(K)
+        dx = np.linalg.solve(A, G[:, :, None])[:, :, 0]
+        r = (A @ d[:, :, None])[:, :, 0] - G
+        res[refine] = (rel(d, dx), np.linalg.norm(r) / np.linalg.norm(G))
+        g.close()
+    say(f"  d vs FP64 solve of the library's H: plain {res[False][0]:.2e}, refined {res[True][0]:.2e}; "
+        f"residual plain {res[False][1]:.2e}, refined {res[True][1]:.2e}")
+    assert res[False][0] < 1e-3 and res[True][0] < 1e-3
+    assert res[True][0] <= 1.5 * res[False][0] + 1e-7
