@@ -25,7 +25,7 @@ FLAGS = [
 # Host-side AddressSanitizer / UndefinedBehaviorSanitizer build of the same
 # source, for the C-ABI tests on the CPU (the device code is built as usual;
 # each -fsanitize applies to the host compilation only).
-LIB_SANITIZED = os.path.join(HERE, "libocsc_asan.so")
+LIB_SANITIZED = os.path.join(HERE, "_build_asan", "libocsc_asan.so")
 SANITIZE_FLAGS = [
     "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
     "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined",
@@ -42,6 +42,7 @@ def asan_runtime() -> str:
 
 
 def build_sanitized(verbose: bool = False) -> str:
+    os.makedirs(os.path.dirname(LIB_SANITIZED), exist_ok=True)
     tmp = LIB_SANITIZED + ".tmp"
     cmd = [HIPCC] + FLAGS + SANITIZE_FLAGS + SOURCES + ["-o", tmp]
     if verbose:

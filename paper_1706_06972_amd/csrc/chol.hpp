@@ -13,8 +13,6 @@ namespace ocsc {
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-constexpr int HERK_B = 64;            // samples per chunk (two k-steps of 32)
-constexpr int HERK_LD = HERK_B + 8;   // LDS row pitch (bf16) of the transposed parts
 
 __device__ __forceinline__ v4f mfma_bf16(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -29,7 +27,11 @@ __device__ __forceinline__ v8bf bf_neg(v8bf x) {
 }
 
 // NW waves per workgroup, NSPLIT workgroups per frequency p (blockIdx.x = p,
-// blockIdx.y = share of the tiles).  Zt[(p * ldt + b) * K + k] holds the nb
+// blockIdx.y = share of the tiles); CH samples per staged chunk (a multiple
+// of 32: one k-step of the products per 32).  Up to K = 112 with 8 waves the
+// registers are held to 128 per lane (chunks of 32 samples), so that two
+// workgroups share a CU and cover each other's load and write phases; with
+// the whole register file one workgroup per CU ran alone.  Zt[(p * ldt + b) * K + k] holds the nb
 // pending code spectra frequency-major; xh[b * Pf + p] the sample spectra.
 // H_p (R-form, rows of pitch K + 1 at Hm + p * fs) and G[k][p] are updated in
 // place.  The product tiles on and above the diagonal are spread over the
@@ -37,10 +39,12 @@ __device__ __forceinline__ v8bf bf_neg(v8bf x) {
 // v_mfma_f32_16x16x32_bf16: A[i][8g..8g+7] in lane i + 16 g,
 // B[8g..8g+7][j] in lane j + 16 g, D[i][j] in lane j + 16 (i / 4),
 // register i % 4.
-template <int KP, int NW, int NSPLIT>
-__global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict__ Zt, int ldt, int nb,
+template <int KP, int NW, int NSPLIT, int CH>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW <= 8 && KP <= 112 ? 4 : 1))) void k_herk_bf16(const float2* __restrict__ Zt, int ldt, int nb,
                                                       const float2* __restrict__ xh, int Pf, float* __restrict__ Hm,
                                                       int fs, float2* __restrict__ G, int K) {
+  constexpr int HERK_B = CH;            // samples per chunk
+  constexpr int HERK_LD = HERK_B + 8;   // LDS row pitch (bf16) of the transposed parts
   constexpr int NT = 64 * NW;
   constexpr int NTD = KP / 16;                    // tiles per dimension
   constexpr int NTILE = NTD * (NTD + 1) / 2;      // tiles on or above the diagonal
@@ -66,6 +70,7 @@ __global__ __launch_bounds__(64 * NW) void k_herk_bf16(const float2* __restrict_
   v4f re[TPW], im[TPW];
 #pragma unroll
   for (int tt = 0; tt < TPW; ++tt) re[tt] = im[tt] = v4f{0, 0, 0, 0};
+
   float gr = 0.f, gi = 0.f;
   const int gk = tid % KP, gsl = tid / KP;   // this thread's filter and sample slice for G
   const float2* zp = Zt + (size_t)p * ldt * K;

@@ -1044,14 +1044,14 @@ int chol_history(ocsc_ctx* c, int B) {
   switch (KP) {
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_herk_bf16<N, 8, 1>), dim3(c->Pf, 1), dim3(512), 0, c->stream, (const float2*)c->Zt,    \
+    hipLaunchKernelGGL((k_herk_bf16<N, 8, 1, 32>), dim3(c->Pf, 1), dim3(512), 0, c->stream, (const float2*)c->Zt, \
                        c->maxB, B, (const float2*)c->xh, c->Pf, (float*)c->Hm, c->fs, (float2*)c->G, c->K);     \
     break;
     X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128)
 #undef X
 #define X(N)                                                                                                  \
   case N:                                                                                                     \
-    hipLaunchKernelGGL((k_herk_bf16<N, 16, 2>), dim3(c->Pf, 2), dim3(1024), 0, c->stream, (const float2*)c->Zt, \
+    hipLaunchKernelGGL((k_herk_bf16<N, 16, 2, 64>), dim3(c->Pf, 2), dim3(1024), 0, c->stream, (const float2*)c->Zt, \
                        c->maxB, B, (const float2*)c->xh, c->Pf, (float*)c->Hm, c->fs, (float2*)c->G, c->K);     \
     break;
     X(144) X(160) X(176) X(192) X(208) X(224) X(240) X(256)
