@@ -235,13 +235,15 @@ def coding_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
 
 def grouped_run(dev, K: int = 100, iters: int = 10, reps: int = 5) -> dict:
     """Uneven sizes: one batch per grid coded (a) by per-grid launches in
-    turn, with autotuned shapes, and (b) by one persistent grouped launch
+    turn, with autotuned shapes, (b) the same launches captured once in a HIP
+    graph and replayed, and (c) by one persistent grouped launch
     (ocsc_code_update_group); full batches (the samples per launch of the
     coding run) and single samples per grid."""
     return {"full": _grouped(dev, CODING_GRIDS, K, iters, reps),
             "single": _grouped(dev, tuple((n, 1) for n, _ in CODING_GRIDS), K, iters, 4 * reps),
-            "note": ("K=100, FP32, J_z=10; separate: per-grid launch sequences in turn on one stream; grouped: "
-                     "every iteration of every grid in one cooperative launch")}
+            "note": ("K=100, FP32, J_z=10; separate: per-grid launch sequences in turn on one stream; graph: "
+                     "the same launches replayed from one HIP graph; grouped: every iteration of every grid in "
+                     "one cooperative launch")}
 
 
 def _grouped(dev, grids, K, iters, reps) -> dict:
@@ -250,16 +252,20 @@ def _grouped(dev, grids, K, iters, reps) -> dict:
     from paper_1706_06972_amd import ocsc as L
     D0 = synth.initial_dictionary(K, 11, 11, 0)
     models, xs = [], []
+    # every context on one side stream, so that their launches can be captured in one HIP graph
+    st = torch.cuda.Stream(device=dev)
     for n, B in grids:
         wl = synth.Workload(name=f"group{n}", pad_h=n, pad_w=n, content_h=n // 2, content_w=n // 2, k_true=K,
                             density=0.005, sigma_z=10.0, noise=0.01, K=K, filt_h=11, filt_w=11, lam=1.0, rho=1.0,
                             iters_code=iters, iters_dict=10, batch=B, n_images=B, passes=1, precision="f32", seed=n)
         xs.append(torch.as_tensor(synth.images(wl, range(B)), dtype=torch.float32, device=dev).contiguous())
-        g = L.OCSC(K, 11, 11, n, n, 1.0, 1.0, iters_code=iters, max_batch=B, precision="f32", device=dev)
+        with torch.cuda.stream(st):
+            g = L.OCSC(K, 11, 11, n, n, 1.0, 1.0, iters_code=iters, max_batch=B, precision="f32", device=dev)
         g.set_dictionary(D0)
         g.autotune(B)
         models.append(g)
     total = sum(B for _, B in grids)
+    torch.cuda.synchronize()
 
     def separate():
         for g, x in zip(models, xs):
@@ -268,8 +274,16 @@ def _grouped(dev, grids, K, iters, reps) -> dict:
     def grouped():
         L.ocsc_code_update_group([g.ctx for g in models], xs, [x.shape[0] for x in xs], None)
 
+    # the per-grid launch sequences of one mixed batch captured once as a HIP graph
+    separate()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=st):
+        separate()
+    torch.cuda.synchronize()
+
     out = {}
-    for name, fn in (("separate", separate), ("grouped", grouped)):
+    for name, fn in (("separate", separate), ("graph", graph.replay), ("grouped", grouped)):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -278,6 +292,7 @@ def _grouped(dev, grids, K, iters, reps) -> dict:
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         out[name] = {"images_per_s": total / dt, "ms_per_launch": 1000.0 * dt}
+    del graph
     for g in models:
         g.close()
     out["batch"] = {str(n): B for n, B in grids}
@@ -316,24 +331,33 @@ def graph_run(wl, xs, steps: int, warmup: int = 4, shape=None) -> dict:
             "steps": 2 * launches, "form": "the B=1 step above, replayed from HIP graphs"}
 
 
-def served_run(dev, K: int = 100) -> dict:
+def served_run(dev, K: int = 100, full: bool = False) -> dict:
     """Serving form (continuous batching, resident dictionary updated every
     256 requests, FP32): Poisson arrivals on a mix of 64/128/256/512 grids
     (shares 8:4:2:1, a 64 GB HBM budget) at a sustainable and at the
     configured 5,000/s offered rate, and a 128x128-only stream (the shape of
-    the B=1 workload above).  The first tenth of each run is excluded."""
+    the B=1 workload above).  The first tenth of each run is excluded.
+    full: the configured serving workload only -- 100,000 requests per rate,
+    the first 10,000 excluded, at 5,000/s and at 1,800/s (about the measured
+    capacity of the mix)."""
     import synth
     from paper_1706_06972_amd.serve import Server, poisson_requests, summarize
     D0 = synth.initial_dictionary(K, 11, 11, 0)
     out = {}
     grids, shares = (64, 128, 256, 512), (8, 4, 2, 1)
     srv = Server(K, 11, D0, grids=grids, shares=shares, update_every=256, budget=64e9)
-    for rate, n in ((1000.0, 2000), (5000.0, 3000)):
+    runs = ((5000.0, 100000), (1800.0, 100000)) if full else ((1000.0, 2000), (5000.0, 3000))
+    for rate, n in runs:
         reqs = poisson_requests(n, rate, grids, shares, seed=int(rate))
         m = srv.run(reqs)
         out[f"mix_{int(rate)}"] = summarize(reqs, m["wall_s"], m["dictionary_updates"], warmup=n // 10)
+        print(f"served mix at {rate:.0f}/s: {out[f'mix_{int(rate)}']}", file=sys.stderr, flush=True)
     out["mix_slots"] = srv.slots
     srv.close()
+    if full:
+        out["note"] = ("configured serving workload: 100,000 Poisson requests per offered rate, the first 10,000 "
+                       "excluded; latency = completion event - arrival (input copy from pinned host memory included)")
+        return out
     for chol in (False, True):
         # the 128x128 stream with the Sherman-Morrison fold, then in the precision form
         srv = Server(K, 11, D0, grids=(128,), shares=(1,), update_every=256, budget=64e9,
@@ -446,7 +470,8 @@ def main():
     ap.add_argument("--coding", type=int, default=1, help="also time coding on 64..512 grids (0: skip)")
     ap.add_argument("--grouped", type=int, default=1,
                     help="also time the grouped persistent (cooperative) launch against per-grid launches (0: skip)")
-    ap.add_argument("--served", type=int, default=1, help="also run the serving form (0: skip)")
+    ap.add_argument("--served", type=int, default=1,
+                    help="also run the serving form (0: skip; 2: only the configured 100,000-request mix runs)")
     ap.add_argument("--quality", type=int, default=1,
                     help="also measure test objective / PSNR before and after learning (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -550,7 +575,7 @@ def main():
     out["coding"] = coding_run(dev) if args.coding else None
     out["grouped"] = grouped_run(dev) if args.grouped else None
     out["copy_ceiling"] = copy_ceiling(dev)
-    out["served"] = served_run(dev) if args.served else None
+    out["served"] = served_run(dev, full=args.served == 2) if args.served else None
     out["quality"] = quality_run(dev) if args.quality else None
     if args.cpu_steps > 0:
         out["cpu_baseline"] = oracle_baseline(wl, args.cpu_steps)

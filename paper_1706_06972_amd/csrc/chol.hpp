@@ -589,6 +589,329 @@ __global__ __launch_bounds__(NT) void k_chol_inv_t(const float* __restrict__ Hm,
 }
 
 // ---------------------------------------------------------------------------
+// C_p = (H_p + rho_d I)^-1 in FP64 on the matrix cores, one workgroup of 8
+// waves per frequency, for N = K rounded up to 16 <= 128 (NB <= 8 blocks of
+// 16 x 16).  Used for the 128-blocks of the K > 128 form (FULL): 1.05 ms per
+// 2048 frequencies against 1.46 ms for k_chol_inv_t.  At K = 100 its 122 KB
+// of LDS leave one workgroup per CU, and k_chol_inv_t, two per CU, is
+// faster there (2.56 against 3.18 ms).  The lower triangle of blocks lives in LDS (each block 16 rows of
+// pitch 17 complex doubles, so that the 16 rows read by one operand load
+// fall in different banks).  Every block product is a 16 x 16 x 16 complex
+// product on v_mfma_f64_16x16x4_f64 (operand A[i][k] in lane i + 16 k,
+// B[k][j] in lane j + 16 k, result D[i][j] in lane j + 16 (i % 4), element
+// i / 4 -- the rows of a lane's four results are strided, unlike the FP32
+// form; checked by an in-bounds probe), three real products per complex one:
+//   P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi);  Re = P1 - P2, Im = P3 - P1 - P2.
+//   1. A = H + rho_d I (identity padding beyond K).
+//   2. Blocked right-looking Cholesky A = L L^H: per block column j, the
+//      diagonal block is factorised and inverted by one wave (W_jj = L_jj^-1,
+//      kept in place of L_jj), the panel becomes L_ij = A_ij W_jj^H, and the
+//      trailing blocks take A_ik -= L_ij L_kj^H.  Look-ahead: wave 0 first
+//      updates the next diagonal block and factorises it while the other waves
+//      update the rest of the trailing triangle.
+//   3. X = L^-1, right-looking per block column k: row k becomes
+//      X_kj = W_kk B_kj; then the rows below take B_ij -= L_ik X_kj (j < k)
+//      and, once those have read L_ik, B_ik = -L_ik W_kk (B holds the rows
+//      below).
+//   4. C = X^H X: C_ij = sum_{m >= j} X_mi^H X_mj for the blocks on and above
+//      the diagonal, written to the R-form (FP32) or, FULL, to a dense
+//      128 x 128 FP64 block (both triangles).
+// The diagonal blocks: in 4 x 4 steps, every lane of the wave factorises the
+// 4 x 4 diagonal piece in registers, the rows below solve against it, the
+// rest of the block takes the rank-4 update; then each of 16 lanes forms one
+// column of W_jj by forward substitution.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int CM_P = 17;            // LDS row pitch of a block (complex doubles)
+constexpr int CM_BS = 16 * CM_P;    // complex doubles per stored block
+constexpr int CM_NT = 512;          // 8 waves (up to 256 registers per lane)
+constexpr int CM_NW = CM_NT / 64;
+
+__host__ __device__ constexpr int cm_lblk(int i, int j) { return i * (i + 1) / 2 + j; }   // lower block, i >= j
+__host__ constexpr size_t cm_lds(int K) {
+  const int nb = (K + 15) / 16;
+  return (size_t)cm_lblk(nb, 0) * CM_BS * 16;
+}
+
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Intra-wave ordering of LDS accesses (the wave's lanes exchange data through LDS).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Accumulators of one 16 x 16 complex block: P1, P2, P3 of the three-product form.
+struct ZAcc {
+  v4d p1, p2, p3;
+};
+__device__ __forceinline__ void zacc_zero(ZAcc& z) { z.p1 = z.p2 = z.p3 = v4d{0, 0, 0, 0}; }
+
+// z += op(A) op(B) over k = 0..15 for blocks A, B in LDS; HA / HB: the
+// conjugate transpose of the stored block; NEG: subtract.
+template <bool HA, bool HB, bool NEG>
+__device__ __forceinline__ void zmma16(ZAcc& z, const double2* __restrict__ A, const double2* __restrict__ B,
+                                       int lane) {
+  const int i = lane & 15, kk = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    const int k = k0 + kk;
+    double2 a = HA ? A[k * CM_P + i] : A[i * CM_P + k];   // A[i][k]
+    double2 b = HB ? B[i * CM_P + k] : B[k * CM_P + i];   // B[k][j], j = lane & 15
+    if (HA) a.y = -a.y;
+    if (HB) b.y = -b.y;
+    if (NEG) {
+      a.x = -a.x;
+      a.y = -a.y;
+    }
+    z.p1 = mfma_f64(a.x, b.x, z.p1);
+    z.p2 = mfma_f64(a.y, b.y, z.p2);
+    z.p3 = mfma_f64(a.x + a.y, b.x + b.y, z.p3);
+  }
+}
+
+// element e of this lane's share of the block: row lane / 16 + 4 e, column lane % 16
+__device__ __forceinline__ double2 zacc_get(const ZAcc& z, int e) {
+  return make_double2(z.p1[e] - z.p2[e], z.p3[e] - z.p1[e] - z.p2[e]);
+}
+// a block held as (re, im) is loaded into the accumulators as P1 = re, P2 = 0, P3 = re + im
+__device__ __forceinline__ void zacc_load(ZAcc& z, const double2* __restrict__ D, int lane) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double2 v = D[((lane >> 4) + 4 * e) * CM_P + (lane & 15)];
+    z.p1[e] = v.x;
+    z.p2[e] = 0.0;
+    z.p3[e] = v.x + v.y;
+  }
+}
+__device__ __forceinline__ void zacc_store(const ZAcc& z, double2* __restrict__ D, int lane) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) D[((lane >> 4) + 4 * e) * CM_P + (lane & 15)] = zacc_get(z, e);
+}
+
+// Factorise the 16 x 16 diagonal block D (lower triangle, Hermitian positive
+// definite) and replace it by W = L^-1 (lower, zeros above).  One wave.
+__device__ __forceinline__ void cm_diag_block(double2* __restrict__ D, int lane, int* __restrict__ breakdown) {
+  // Cholesky in four steps of 4 columns
+#pragma unroll
+  for (int s = 0; s < 16; s += 4) {
+    double2 d[4][4];   // factor of the 4 x 4 diagonal piece, every lane alike; .y of d[c][c] = 1 / d_cc
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) d[r][c] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double sd = D[(s + c) * CM_P + s + c].x;
+#pragma unroll
+      for (int m = 0; m < c; ++m) sd -= d[c][m].x * d[c][m].x + d[c][m].y * d[c][m].y;
+      if (!(sd > 0.0) && lane == 0) atomicOr(breakdown, 1);
+      const double dc = sqrt(sd), ic = 1.0 / dc;
+      d[c][c] = make_double2(dc, ic);
+#pragma unroll
+      for (int r = c + 1; r < 4; ++r) {
+        double2 v = D[(s + r) * CM_P + s + c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) v = zsub_mulc(v, d[r][m], d[c][m]);
+        d[r][c] = make_double2(v.x * ic, v.y * ic);
+      }
+    }
+    // rows below the piece: l_r = a_r D^-H, one lane per row
+    const int r = s + 4 + lane;
+    double2 l[4];
+    if (lane < 12 - s) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double2 v = D[r * CM_P + s + c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) v = zsub_mulc(v, l[m], d[c][m]);
+        l[c] = make_double2(v.x * d[c][c].y, v.y * d[c][c].y);
+      }
+    }
+    wave_sync();   // every lane has read the piece and its row before they are overwritten
+    if (lane < 4) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c <= lane) {
+          // the lane's row of the factored piece (compile-time selection of d)
+          double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr)
+            if (rr == lane) v = (rr == c) ? make_double2(d[rr][rr].x, 0.0) : d[rr][c];
+          D[(s + lane) * CM_P + s + c] = v;
+        }
+    }
+    if (lane < 12 - s) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) D[r * CM_P + s + c] = l[c];
+    }
+    wave_sync();
+    // trailing lower triangle of rows and columns s + 4 .. 15: A_rc -= sum_m l_rm conj(l_cm)
+    const int n = 12 - s;
+    for (int e = lane; e < n * n; e += 64) {
+      const int rr = s + 4 + e / n, cc = s + 4 + e % n;
+      if (cc <= rr) {
+        double2 v = D[rr * CM_P + cc];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v = zsub_mulc(v, D[rr * CM_P + s + m], D[cc * CM_P + s + m]);
+        D[rr * CM_P + cc] = v;
+      }
+    }
+    wave_sync();
+  }
+  // W = L^-1 by forward substitution, lane c < 16 forming column c in
+  // registers (W_rc = (delta_rc - sum_{c <= m < r} L_rm W_mc) / L_rr; the L
+  // entries are the same for every lane)
+  const int c = lane & 15;
+  double2 w[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double2 v = make_double2(r == c ? 1.0 : 0.0, 0.0);
+#pragma unroll
+    for (int m = 0; m < r; ++m) v = zsub_mul(v, D[r * CM_P + m], w[m]);   // w[m] = 0 for m < c
+    const double ir = 1.0 / D[r * CM_P + r].x;
+    w[r] = (r >= c) ? make_double2(v.x * ir, v.y * ir) : make_double2(0.0, 0.0);
+  }
+  wave_sync();   // every lane has read L
+  if (lane < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) D[r * CM_P + c] = w[r];
+  }
+  wave_sync();
+}
+
+template <bool FULL>
+__global__ __launch_bounds__(CM_NT) void k_chol_inv_mfma(const float* __restrict__ Hm, float* __restrict__ Cm,
+                                                         const double2* __restrict__ Ain,
+                                                         double2* __restrict__ Cout, int K, int fs, double rho_d,
+                                                         int* __restrict__ breakdown) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2* Lb = reinterpret_cast<double2*>(smem_raw);
+  const int NB = (K + 15) / 16;
+  const int p = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ld = K + 1;
+  auto blk = [&](int i, int j) { return Lb + (size_t)cm_lblk(i, j) * CM_BS; };
+  // 1. A = H + rho_d I into the lower blocks (diagonal blocks: lower triangle)
+  const int nel = cm_lblk(NB, 0) * 256;
+  for (int t = tid; t < nel; t += CM_NT) {
+    const int b = t >> 8, e = t & 255;
+    int bi = 0;
+    while (cm_lblk(bi + 1, 0) <= b) ++bi;
+    const int bj = b - cm_lblk(bi, 0);
+    const int r = e >> 4, cc = e & 15;
+    const int i = bi * 16 + r, j = bj * 16 + cc;
+    double2 v;
+    if (i < j) {
+      v = make_double2(0.0, 0.0);   // upper part of a diagonal block
+    } else if (i >= K || j >= K) {
+      v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    } else if constexpr (FULL) {
+      v = Ain[(size_t)p * CB_N * CB_N + i * CB_N + j];
+    } else {
+      const float* R = Hm + (size_t)p * fs;
+      v = (i == j) ? make_double2((double)R[i * ld + i] + rho_d, 0.0)
+                   : make_double2((double)R[j * ld + i], -(double)R[i * ld + j]);
+    }
+    Lb[(size_t)b * CM_BS + r * CM_P + cc] = v;
+  }
+  __syncthreads();
+  // 2. blocked Cholesky; W_jj replaces L_jj
+  if (wave == 0) cm_diag_block(blk(0, 0), lane, breakdown);
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    // panel: L_ij = A_ij W_jj^H
+    for (int i = j + 1 + wave; i < NB; i += CM_NW) {
+      ZAcc z;
+      zacc_zero(z);
+      zmma16<false, true, false>(z, blk(i, j), blk(j, j), lane);
+      zacc_store(z, blk(i, j), lane);
+    }
+    __syncthreads();
+    if (j + 1 < NB) {
+      if (wave == 0) {
+        // the next diagonal block first, then its factor
+        ZAcc z;
+        zacc_load(z, blk(j + 1, j + 1), lane);
+        zmma16<false, true, true>(z, blk(j + 1, j), blk(j + 1, j), lane);
+        zacc_store(z, blk(j + 1, j + 1), lane);
+        wave_sync();
+        cm_diag_block(blk(j + 1, j + 1), lane, breakdown);
+      } else {
+        // the rest of the trailing triangle: blocks (i, k), j < k <= i, except (j + 1, j + 1)
+        const int n = NB - 1 - j;
+        for (int t = 1 + (wave - 1); t < n * (n + 1) / 2; t += CM_NW - 1) {
+          int ti = 0;
+          while (cm_lblk(ti + 1, 0) <= t) ++ti;
+          const int tk = t - cm_lblk(ti, 0);
+          const int i = j + 1 + ti, k = j + 1 + tk;
+          ZAcc z;
+          zacc_load(z, blk(i, k), lane);
+          zmma16<false, true, true>(z, blk(i, j), blk(k, j), lane);
+          zacc_store(z, blk(i, k), lane);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // 3. X = L^-1, right-looking per block column k (X_kk = W_kk already)
+  for (int k = 0; k < NB; ++k) {
+    for (int jj = wave; jj < k; jj += CM_NW) {   // X_kj = W_kk B_kj
+      ZAcc z;
+      zacc_zero(z);
+      zmma16<false, false, false>(z, blk(k, k), blk(k, jj), lane);
+      zacc_store(z, blk(k, jj), lane);
+    }
+    __syncthreads();
+    // B_ij -= L_ik X_kj for i > k, j < k (reads block (i, k))
+    const int nr = NB - 1 - k;
+    for (int t = wave; t < nr * k; t += CM_NW) {
+      const int i = k + 1 + t / k, jj = t % k;
+      ZAcc z;
+      zacc_load(z, blk(i, jj), lane);
+      zmma16<false, false, true>(z, blk(i, k), blk(k, jj), lane);
+      zacc_store(z, blk(i, jj), lane);
+    }
+    if (k > 0) __syncthreads();
+    // then B_ik = -L_ik W_kk overwrites block (i, k)
+    for (int i = k + 1 + wave; i < NB; i += CM_NW) {
+      ZAcc z;
+      zacc_zero(z);
+      zmma16<false, false, true>(z, blk(i, k), blk(k, k), lane);
+      wave_sync();   // every lane's reads of L_ik are done before it is overwritten
+      zacc_store(z, blk(i, k), lane);
+    }
+    __syncthreads();
+  }
+  // 4. C = X^H X, blocks (bi, bj) with bi <= bj
+  for (int t = wave; t < NB * (NB + 1) / 2; t += CM_NW) {
+    int bj = 0;
+    while (cm_lblk(bj + 1, 0) <= t) ++bj;
+    const int bi = t - cm_lblk(bj, 0);   // bi <= bj
+    ZAcc z;
+    zacc_zero(z);
+    for (int m = bj; m < NB; ++m) zmma16<true, false, false>(z, blk(m, bi), blk(m, bj), lane);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = bi * 16 + (lane >> 4) + 4 * e, jx = bj * 16 + (lane & 15);
+      if (i >= K || jx >= K || i > jx) continue;
+      const double2 v = zacc_get(z, e);
+      if constexpr (FULL) {
+        double2* Co = Cout + (size_t)p * CB_N * CB_N;
+        Co[i * CB_N + jx] = v;
+        Co[jx * CB_N + i] = make_double2(v.x, -v.y);
+      } else {
+        float* Co = Cm + (size_t)p * fs;
+        Co[i * ld + jx] = (float)v.x;
+        if (i < jx) Co[jx * ld + i] = (float)v.y;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K > 128 (up to 256): C_p = A^-1 for A = H_p + rho_d I from the FP64 block
 // inverses of two Cholesky factors and a Schur complement.  With the split
 // n1 = 128, n2 = K - 128 and every block stored as a full 128 x 128 FP64

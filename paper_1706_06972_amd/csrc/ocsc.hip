@@ -1061,6 +1061,10 @@ int chol_history(ocsc_ctx* c, int B) {
   }
   LAUNCHED(c);
   if (!c->dstream) {
+    // K <= 128: the VALU kernel; two workgroups share a CU.  (The matrix-core
+    // kernel, one workgroup per CU for its 122 KB of blocks at K = 100, took
+    // 3.18 ms per launch against 2.56 ms: its serial diagonal-block steps are
+    // not covered by a second workgroup.)
     if (chol_small(c->K))
       hipLaunchKernelGGL((k_chol_inv_t<false, 512>), dim3(c->Pf), dim3(512), chol_lds(c->K), c->stream,
                          (const float*)c->Hm, (float*)c->Cm, (const double2*)nullptr, (double2*)nullptr, c->K, c->fs,
@@ -1085,13 +1089,13 @@ int chol_history(ocsc_ctx* c, int B) {
     const dim3 g(2, 2, nf);
     hipLaunchKernelGGL(k_schur_unpack, dim3(3 * 16, nf), dim3(256), 0, c->stream, (const float*)c->Hm, c->fs, c->K,
                        c->rho_d, f0, nf, W);
-    hipLaunchKernelGGL((k_chol_inv_t<true, CHOL_NT>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream,
+    hipLaunchKernelGGL((k_chol_inv_mfma<true>), dim3(nf), dim3(CM_NT), cm_lds(CB_N), c->stream,
                        (const float*)nullptr, (float*)nullptr, (const double2*)s0, s1, CB_N, 0, 0.0, c->brk);   // P = A11^-1
     hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s2,
                        (const double2*)s1, (const double2*)nullptr, s4, 1.0, 0.0);                   // B = A21 P
     hipLaunchKernelGGL((k_zgemm128<false, true>), g, dim3(256), 0, c->stream, (const double2*)s4,
                        (const double2*)s2, (const double2*)s3, s3, -1.0, 1.0);                       // S = A22 - B A21^H
-    hipLaunchKernelGGL((k_chol_inv_t<true, CHOL_NT>), dim3(nf), dim3(CHOL_NT), chol_lds(CB_N), c->stream,
+    hipLaunchKernelGGL((k_chol_inv_mfma<true>), dim3(nf), dim3(CM_NT), cm_lds(CB_N), c->stream,
                        (const float*)nullptr, (float*)nullptr, (const double2*)s3, s0, CB_N, 0, 0.0, c->brk);   // Q = S^-1
     hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s0,
                        (const double2*)s4, (const double2*)nullptr, s2, -1.0, 0.0);                  // C21 = -Q B
@@ -1426,10 +1430,11 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
   }
   if (c->chol) {
     const int kb = c->dstream ? CB_N : K;   // the factorised block size
-    const void* fn = c->dstream ? (const void*)k_chol_inv_t<true, CHOL_NT>
+    const void* fn = c->dstream ? (const void*)k_chol_inv_mfma<true>
                                 : (chol_small(K) ? (const void*)k_chol_inv_t<false, 512>
                                                  : (const void*)k_chol_inv_t<false, CHOL_NT>);
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)chol_lds(kb));
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(c->dstream ? cm_lds(kb) : chol_lds(kb)));
     if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
   if (!c->dstream && std::max(c->sweep_smem, c->plain_smem) > 64 * 1024) {
