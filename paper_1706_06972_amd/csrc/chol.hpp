@@ -1091,10 +1091,34 @@ __global__ __launch_bounds__(256) void k_schur_pack(const double2* __restrict__ 
 // complex [K][Pf].
 // ---------------------------------------------------------------------------
 constexpr int DS_ROWS = 16, DS_PITCH = 260;
+constexpr int DS_V = (DS_ROWS * DS_PITCH / 4 + 255) / 256;   // 16-byte vectors per thread and strip
+
+// A strip of rows [a0, a0 + nr) of C_p is one contiguous, 16-byte aligned
+// run of nr (K + 1) reals (C_p starts at a multiple of 4 reals and 16 rows
+// of pitch K + 1 are 64 (K + 1) bytes); it is copied as 16-byte vectors and
+// keeps the pitch K + 1 in LDS (odd, so a column walk spreads over the banks).
+__device__ __forceinline__ void ds_fetch(v4f (&pf)[DS_V], const float* __restrict__ R, int a0, int nr, int ld,
+                                         int t) {
+  const int nv = (nr * ld + 3) / 4;
+  const v4f* src = reinterpret_cast<const v4f*>(R + (size_t)a0 * ld);
+#pragma unroll
+  for (int m = 0; m < DS_V; ++m) {
+    const int v = t + m * 256;
+    if (v < nv) pf[m] = src[v];
+  }
+}
+__device__ __forceinline__ void ds_stage(const v4f (&pf)[DS_V], float* strip, int nr, int ld, int t) {
+  const int nv = (nr * ld + 3) / 4;
+#pragma unroll
+  for (int m = 0; m < DS_V; ++m) {
+    const int v = t + m * 256;
+    if (v < nv) reinterpret_cast<v4f*>(strip)[v] = pf[m];
+  }
+}
 
 __global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ Cm, int fs, int K, int Pf,
                                                       const float2* __restrict__ rhs, float2* __restrict__ dout) {
-  __shared__ float strip[DS_ROWS * DS_PITCH];
+  __shared__ __align__(16) float strip[DS_ROWS * DS_PITCH];
   __shared__ float2 rv[256], drow[256];
   const int p = blockIdx.x, t = threadIdx.x;
   const int ld = K + 1;
@@ -1105,40 +1129,19 @@ __global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ 
   }
   float2 dc = make_float2(0.f, 0.f);
   const int rr = t >> 4, q = t & 15;
-  // element t + 256 m of a strip is row r, column cc of it, the same for
-  // every strip: the divisions are done once (packed as r * 512 + cc; r < 32,
-  // cc < K <= 256)
-  int rc[DS_ROWS];
-#pragma unroll
-  for (int m = 0; m < DS_ROWS; ++m) {
-    const int e = t + m * 256, r = e / K;
-    rc[m] = r * 512 + (e - r * K);
-  }
   // the next strip is fetched into registers while the current one is used
-  float pf[DS_ROWS];
-  auto fetch = [&](int a0) {
-    const int nr = min(DS_ROWS, K - a0);
-#pragma unroll
-    for (int m = 0; m < DS_ROWS; ++m) {
-      const int r = rc[m] >> 9, cc = rc[m] & 511;
-      if (r < nr) pf[m] = R[(size_t)(a0 + r) * ld + cc];
-    }
-  };
-  fetch(0);
+  v4f pf[DS_V];
+  ds_fetch(pf, R, 0, min(DS_ROWS, K), ld, t);
   __syncthreads();
   for (int a0 = 0; a0 < K; a0 += DS_ROWS) {
     const int nr = min(DS_ROWS, K - a0);
-#pragma unroll
-    for (int m = 0; m < DS_ROWS; ++m) {
-      const int r = rc[m] >> 9, cc = rc[m] & 511;
-      if (r < nr) strip[r * DS_PITCH + cc] = pf[m];
-    }
+    ds_stage(pf, strip, nr, ld, t);
     __syncthreads();
-    if (a0 + DS_ROWS < K) fetch(a0 + DS_ROWS);
+    if (a0 + DS_ROWS < K) ds_fetch(pf, R, a0 + DS_ROWS, min(DS_ROWS, K - a0 - DS_ROWS), ld, t);
     if (t < K) {   // column role: output t
       for (int r = 0; r < nr; ++r) {
         const int a = a0 + r;
-        const float v = strip[r * DS_PITCH + t];
+        const float v = strip[r * ld + t];
         const float2 ra = rv[a];
         if (a <= t) {
           dc.x = fma(v, ra.x, dc.x);
@@ -1154,7 +1157,7 @@ __global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ 
       const int a = a0 + rr;
       for (int b = q; b < K; b += 16) {
         if (b == a) continue;
-        const float v = strip[rr * DS_PITCH + b];
+        const float v = strip[rr * ld + b];
         const float2 rb = rv[b];
         if (a < b) {
           sum.x = fma(v, rb.x, sum.x);
@@ -1195,17 +1198,11 @@ __global__ __launch_bounds__(256) void k_dstep_stream(const float* __restrict__ 
 __global__ __launch_bounds__(256) void k_dstep_refine(const float* __restrict__ Hm, const float* __restrict__ Cm,
                                                       int fs, int K, int Pf, double rho_d,
                                                       const float2* __restrict__ rhs, float2* __restrict__ d) {
-  __shared__ float strip[DS_ROWS * DS_PITCH];
+  __shared__ __align__(16) float strip[DS_ROWS * DS_PITCH];
   __shared__ double2 xv[256], acc[256];
   const int p = blockIdx.x, t = threadIdx.x;
   const int ld = K + 1;
   const int rr = t >> 4, q = t & 15;
-  int rc[DS_ROWS];
-#pragma unroll
-  for (int m = 0; m < DS_ROWS; ++m) {
-    const int e = t + m * 256, r = e / K;
-    rc[m] = r * 512 + (e - r * K);
-  }
   float2 d0 = make_float2(0.f, 0.f);
   if (t < K) {
     d0 = d[(size_t)t * Pf + p];
@@ -1214,32 +1211,20 @@ __global__ __launch_bounds__(256) void k_dstep_refine(const float* __restrict__ 
   // y = M x for the Hermitian M stored in the R-form at R (FP64 sums);
   // returns output t (t < K) to the thread that owns it
   auto matvec = [&](const float* __restrict__ R) -> double2 {
-    float pf[DS_ROWS];
-    auto fetch = [&](int a0) {
-      const int nr = min(DS_ROWS, K - a0);
-#pragma unroll
-      for (int m = 0; m < DS_ROWS; ++m) {
-        const int r = rc[m] >> 9, cc = rc[m] & 511;
-        if (r < nr) pf[m] = R[(size_t)(a0 + r) * ld + cc];
-      }
-    };
+    v4f pf[DS_V];
     if (t < K) acc[t] = make_double2(0.0, 0.0);
     double2 dc = make_double2(0.0, 0.0);
-    fetch(0);
+    ds_fetch(pf, R, 0, min(DS_ROWS, K), ld, t);
     __syncthreads();
     for (int a0 = 0; a0 < K; a0 += DS_ROWS) {
       const int nr = min(DS_ROWS, K - a0);
-#pragma unroll
-      for (int m = 0; m < DS_ROWS; ++m) {
-        const int r = rc[m] >> 9, cc = rc[m] & 511;
-        if (r < nr) strip[r * DS_PITCH + cc] = pf[m];
-      }
+      ds_stage(pf, strip, nr, ld, t);
       __syncthreads();
-      if (a0 + DS_ROWS < K) fetch(a0 + DS_ROWS);
+      if (a0 + DS_ROWS < K) ds_fetch(pf, R, a0 + DS_ROWS, min(DS_ROWS, K - a0 - DS_ROWS), ld, t);
       if (t < K) {   // column role: output t
         for (int r = 0; r < nr; ++r) {
           const int a = a0 + r;
-          const double v = (double)strip[r * DS_PITCH + t];
+          const double v = (double)strip[r * ld + t];
           const double2 xa = xv[a];
           if (a <= t) {
             dc.x = fma(v, xa.x, dc.x);
@@ -1255,7 +1240,7 @@ __global__ __launch_bounds__(256) void k_dstep_refine(const float* __restrict__ 
         const int a = a0 + rr;
         for (int b = q; b < K; b += 16) {
           if (b == a) continue;
-          const double v = (double)strip[rr * DS_PITCH + b];
+          const double v = (double)strip[rr * ld + b];
           const double2 xb = xv[b];
           if (a < b) {
             sum.x = fma(v, xb.x, sum.x);
