@@ -80,19 +80,30 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW <= 8
     if (tid < HERK_B) xs[tid] = tid < cb ? xh[(size_t)(b0 + tid) * Pf + p] : make_float2(0.f, 0.f);
     // NW <= 8 (K <= 128): every load of the chunk is issued before the first
     // conversion, and the loads for G likewise (measured at K = 100: 875 ->
-    // 703 us per launch).  With 16 waves the extra registers spill, so the
-    // loads there stay one per step.
+    // 703 us per launch).  With 16 waves the registers allow four loads in
+    // flight per thread.
     if constexpr (NW > 8) {
-      for (int e = tid; e < HERK_B * KP; e += NT) {
-        const int b = e / KP, k = e - b * KP;   // consecutive threads read consecutive k
-        float2 z = make_float2(0.f, 0.f);
-        if (b < cb && k < K) z = zp[(size_t)(b0 + b) * K + k];
-        const __bf16 rh = (__bf16)z.x, ih = (__bf16)z.y;
-        const int o = k * HERK_LD + b;
-        zrh[o] = rh;
-        zrl[o] = (__bf16)(z.x - (float)rh);
-        zih[o] = ih;
-        zil[o] = (__bf16)(z.y - (float)ih);
+      constexpr int QL = 4;
+      for (int e0 = tid; e0 < HERK_B * KP; e0 += QL * NT) {
+        float2 zv[QL];
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {
+          const int e = e0 + q * NT, b = e / KP, k = e - b * KP;   // consecutive threads read consecutive k
+          zv[q] = (e < HERK_B * KP && b < cb && k < K) ? zp[(size_t)(b0 + b) * K + k] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {
+          const int e = e0 + q * NT, b = e / KP, k = e - b * KP;
+          if (e < HERK_B * KP) {
+            const float2 z = zv[q];
+            const __bf16 rh = (__bf16)z.x, ih = (__bf16)z.y;
+            const int o = k * HERK_LD + b;
+            zrh[o] = rh;
+            zrl[o] = (__bf16)(z.x - (float)rh);
+            zih[o] = ih;
+            zil[o] = (__bf16)(z.y - (float)ih);
+          }
+        }
       }
     } else {
       constexpr int SPT = (HERK_B * KP + NT - 1) / NT;
@@ -118,11 +129,23 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW <= 8
     }
     __syncthreads();
     if (NW > 8 && split == 0 && gsl < GS && gk < K) {   // G_p[k] += sum_b conj(z_bk) x_b (FP32), samples gsl, gsl + GS, ...
-      for (int b = gsl; b < cb; b += GS) {
-        const float2 z = zp[(size_t)(b0 + b) * K + gk];
-        const float2 x = xs[b];
-        gr += z.x * x.x + z.y * x.y;
-        gi += z.x * x.y - z.y * x.x;
+      constexpr int QL = 4;
+      for (int bb = gsl; bb < cb; bb += QL * GS) {
+        float2 zg[QL];
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {   // four loads in flight
+          const int b = bb + q * GS;
+          zg[q] = b < cb ? zp[(size_t)(b0 + b) * K + gk] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < QL; ++q) {
+          const int b = bb + q * GS;
+          if (b < cb) {
+            const float2 x = xs[b];
+            gr += zg[q].x * x.x + zg[q].y * x.y;
+            gi += zg[q].x * x.y - zg[q].y * x.x;
+          }
+        }
       }
     }
     if (NW <= 8 && split == 0 && gsl < GS && gk < K) {   // the same sums, loads issued together
@@ -934,6 +957,10 @@ __global__ __launch_bounds__(256) void k_schur_unpack(const float* __restrict__ 
                                                       int f0, int nf, double2* __restrict__ W) {
   __shared__ float t1[SU_T][SU_T + 1], t2[SU_T][SU_T + 1];   // t1[r][c] = R[a][b], t2[c][r] = R[b][a]
   const int f = blockIdx.y, blk = blockIdx.x / 16, tile = blockIdx.x % 16;
+  // A11 and A22: rows 0..63 x columns 64..127 are never read (the inverse
+  // reads the lower triangle, S = A22 - B A21^H the tiles on and below the
+  // diagonal of 64 x 64)
+  if (blk != 1 && tile / 4 < 2 && tile % 4 >= 2) return;
   const int slot = blk == 0 ? 0 : (blk == 1 ? 2 : 3);
   const int abase = blk == 0 ? 0 : CB_N, bbase = blk == 2 ? CB_N : 0;
   const int a0 = abase + (tile / 4) * SU_T, b0 = bbase + (tile % 4) * SU_T;
@@ -967,10 +994,12 @@ __global__ __launch_bounds__(256) void k_schur_unpack(const float* __restrict__ 
 // frequency per blockIdx.z, a 64 x 64 output tile per workgroup (blockIdx.x,
 // blockIdx.y), 256 threads with 4 x 4 outputs each; op = conjugate transpose
 // when HA / HB.  Cin may alias Cout (each output is read, then written, by
-// one thread).
+// one thread).  LOWER: the result is Hermitian and only its lower triangle is
+// used, so the tile above the diagonal is skipped (blockIdx.x = 0, 1, 2 for
+// tiles (0, 0), (1, 0), (1, 1)).
 constexpr int ZG_T = 64, ZG_K = 16;
 
-template <bool HA, bool HB>
+template <bool HA, bool HB, bool LOWER = false>
 __global__ __launch_bounds__(256) void k_zgemm128(const double2* __restrict__ A, const double2* __restrict__ B,
                                                   const double2* Cin, double2* Cout, double alpha, double beta) {
   __shared__ double2 as[ZG_K][ZG_T + 1];   // as[kk][i] = op(A)[i0 + i][k0 + kk]
@@ -978,7 +1007,8 @@ __global__ __launch_bounds__(256) void k_zgemm128(const double2* __restrict__ A,
   const size_t off = (size_t)blockIdx.z * CB_N * CB_N;
   const double2* a = A + off;
   const double2* b = B + off;
-  const int i0 = blockIdx.y * ZG_T, j0 = blockIdx.x * ZG_T;
+  const int i0 = LOWER ? (blockIdx.x > 0 ? ZG_T : 0) : blockIdx.y * ZG_T;
+  const int j0 = LOWER ? (blockIdx.x == 2 ? ZG_T : 0) : blockIdx.x * ZG_T;
   const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
   double2 acc[4][4];
 #pragma unroll
@@ -1039,11 +1069,12 @@ __global__ __launch_bounds__(256) void k_zgemm128(const double2* __restrict__ A,
     }
 }
 
-// C_p in R-form (FP32, rows of pitch K + 1) from C11 (slot 1), C21 (slot 2)
-// and C22 (slot 0) of frequencies [f0, f0 + nf): R[i][j] = Re C_ij for
-// j >= i, -Im C_ij for j < i.  Workgroup (blockIdx.x = 32 x 32 tile of R,
-// blockIdx.y = frequency); C_ij for i < 128 <= j is conj(C21[j-128][i]),
-// whose tile is transposed through LDS.
+// C_p in R-form (FP32, rows of pitch K + 1) from C11 (slot 1, its lower
+// triangle only), C21 (slot 2) and C22 (slot 0) of frequencies [f0, f0 + nf):
+// R[i][j] = Re C_ij for j >= i, -Im C_ij for j < i.  Workgroup (blockIdx.x =
+// 32 x 32 tile of R, blockIdx.y = frequency).  On and above the diagonal in
+// the first 128 rows, C_ij = conj(C21[j-128][i]) or conj(C11[j][i]): those
+// tiles are read transposed through LDS.
 __global__ __launch_bounds__(256) void k_schur_pack(const double2* __restrict__ W, int f0, int nf, int K, int fs,
                                                     float* __restrict__ Cm) {
   __shared__ double2 tt[SU_T][SU_T + 1];
@@ -1055,15 +1086,19 @@ __global__ __launch_bounds__(256) void k_schur_pack(const double2* __restrict__ 
   const double2* c11 = W + (1 * (size_t)nf + f) * bs;
   const double2* c21 = W + (2 * (size_t)nf + f) * bs;
   const double2* c22 = W + (0 * (size_t)nf + f) * bs;
-  if (i0 < CB_N && j0 >= CB_N) {
+  if (i0 < CB_N && j0 >= i0) {
+    // tt[r][c] = C[j0 + r][i0 + c]: row j0 + r - 128 of C21, or row j0 + r of C11
+    const double2* src = j0 >= CB_N ? c21 + (size_t)(j0 - CB_N) * CB_N : c11 + (size_t)j0 * CB_N;
     for (int e = threadIdx.x; e < SU_T * SU_T; e += 256) {
-      const int r = e / SU_T, c = e % SU_T;   // row j0 + r of C21, column i0 + c
-      tt[r][c] = (j0 + r < K) ? c21[(size_t)(j0 + r - CB_N) * CB_N + i0 + c] : make_double2(0.0, 0.0);
+      const int r = e / SU_T, c = e % SU_T;
+      tt[r][c] = (j0 + r < K) ? src[(size_t)r * CB_N + i0 + c] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < SU_T * SU_T; e += 256) {
       const int r = e / SU_T, c = e % SU_T, i = i0 + r, j = j0 + c;
-      if (i < K && j < K) Co[i * ld + j] = (float)tt[c][r].x;   // Re C_ij = Re C21[j-128][i]
+      if (i >= K || j >= K) continue;
+      // j >= i: Re C_ij = Re C_ji;  j < i (diagonal tiles, i0 = j0): -Im C_ij, with C_ij = tt[r][c]
+      Co[i * ld + j] = (float)(j >= i ? tt[c][r].x : -tt[r][c].y);
     }
     return;
   }
@@ -1071,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_schur_pack(const double2* __restrict__ 
     const int r = e / SU_T, c = e % SU_T, i = i0 + r, j = j0 + c;
     if (i >= K || j >= K) continue;
     double2 v;
-    if (i < CB_N && j < CB_N) v = c11[i * CB_N + j];
+    if (i < CB_N && j < CB_N) v = c11[i * CB_N + j];   // j < i here
     else if (i >= CB_N && j >= CB_N) v = c22[(i - CB_N) * CB_N + (j - CB_N)];
     else v = c21[(i - CB_N) * CB_N + j];   // i >= 128 > j
     Co[i * ld + j] = (float)(j >= i ? v.x : -v.y);

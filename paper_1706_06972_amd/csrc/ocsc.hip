@@ -1086,20 +1086,20 @@ int chol_history(ocsc_ctx* c, int B) {
     double2* s2 = W + 2 * (size_t)nf * bs;
     double2* s3 = W + 3 * (size_t)nf * bs;
     double2* s4 = W + 4 * (size_t)nf * bs;
-    const dim3 g(2, 2, nf);
+    const dim3 g(2, 2, nf), gl(3, 1, nf);   // gl: Hermitian results, lower tiles only
     hipLaunchKernelGGL(k_schur_unpack, dim3(3 * 16, nf), dim3(256), 0, c->stream, (const float*)c->Hm, c->fs, c->K,
                        c->rho_d, f0, nf, W);
     hipLaunchKernelGGL((k_chol_inv_mfma<true>), dim3(nf), dim3(CM_NT), cm_lds(CB_N), c->stream,
                        (const float*)nullptr, (float*)nullptr, (const double2*)s0, s1, CB_N, 0, 0.0, c->brk);   // P = A11^-1
     hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s2,
                        (const double2*)s1, (const double2*)nullptr, s4, 1.0, 0.0);                   // B = A21 P
-    hipLaunchKernelGGL((k_zgemm128<false, true>), g, dim3(256), 0, c->stream, (const double2*)s4,
+    hipLaunchKernelGGL((k_zgemm128<false, true, true>), gl, dim3(256), 0, c->stream, (const double2*)s4,
                        (const double2*)s2, (const double2*)s3, s3, -1.0, 1.0);                       // S = A22 - B A21^H
     hipLaunchKernelGGL((k_chol_inv_mfma<true>), dim3(nf), dim3(CM_NT), cm_lds(CB_N), c->stream,
                        (const float*)nullptr, (float*)nullptr, (const double2*)s3, s0, CB_N, 0, 0.0, c->brk);   // Q = S^-1
     hipLaunchKernelGGL((k_zgemm128<false, false>), g, dim3(256), 0, c->stream, (const double2*)s0,
                        (const double2*)s4, (const double2*)nullptr, s2, -1.0, 0.0);                  // C21 = -Q B
-    hipLaunchKernelGGL((k_zgemm128<true, false>), g, dim3(256), 0, c->stream, (const double2*)s4,
+    hipLaunchKernelGGL((k_zgemm128<true, false, true>), gl, dim3(256), 0, c->stream, (const double2*)s4,
                        (const double2*)s2, (const double2*)s1, s1, -1.0, 1.0);                       // C11 = P - B^H C21
     const int kt = (c->K + SU_T - 1) / SU_T;
     hipLaunchKernelGGL(k_schur_pack, dim3(kt * kt, nf), dim3(256), 0, c->stream, (const double2*)W, f0, nf, c->K,
