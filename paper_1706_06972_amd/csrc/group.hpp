@@ -112,9 +112,15 @@ __device__ __attribute__((noinline)) void cg_zstep(unsigned char* smem, const Co
 
 // At most 128 registers per lane (four waves per SIMD), so that two
 // workgroups share a CU when the largest plane's LDS allows it.
+// The arguments are copied once into LDS: indexed by a grid number only known
+// at run time, the by-value parameter would otherwise be copied into every
+// lane's private memory (1.2-1.9 KB of scratch per lane).
 template <typename T, int KPT>
-__global__ __launch_bounds__(CG_NT, 4) void k_code_group(CodeGroupArgs<T> g) {
+__global__ __launch_bounds__(CG_NT, 4) void k_code_group(CodeGroupArgs<T> ga) {
   extern __shared__ __align__(16) unsigned char cg_smem[];
+  __shared__ CodeGroupArgs<T> g;
+  if (threadIdx.x == 0) g = ga;
+  __syncthreads();
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int j = 0; j < g.Jz; ++j) {
     const int first = j == 0, last = j == g.Jz - 1;
