@@ -746,7 +746,7 @@ int code_group_t(ocsc_ctx* const* cs, const void* const* xs, const int* Bs, void
     g.p0[s] = (int)pl;
     g.r0[s] = (int)r;
     g.f0[s] = (int)f;
-    z += (long)((c->Pf + CG_ZF - 1) / CG_ZF) * B;
+    z += (long)((c->Pf + CG_ZF - 1) / CG_ZF) * ((B + CG_ZS - 1) / CG_ZS);
     size_t need;
     if (c->big) {
       g.any_big = 1;
