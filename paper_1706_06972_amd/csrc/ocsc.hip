@@ -23,6 +23,7 @@
 #include "bigplane.hpp"
 #include "chol.hpp"
 #include "diag.hpp"
+#include "fold.hpp"
 #include "group.hpp"
 #include "kernels.hpp"
 
@@ -486,10 +487,35 @@ int sweep_nvm_for(int K, int fpb, size_t sr) {
   return sweep_slot_bytes(K, fpb, sr) <= (size_t)256 * SWEEP_MAXV * 16 ? SWEEP_MAXV : SWEEP_MAXV_L;
 }
 
+// K rounded up to 16 for the matrix-core fold (FP32, K <= 128)
+#define OCSC_FOLD_KP(X) X(16) X(32) X(48) X(64) X(80) X(96) X(112) X(128)
+
 // One D-step sweep; nfold > 0 folds the kept spectra of nfold samples first.
 template <typename T>
 int launch_sweep(ocsc_ctx* c, int nfold, const void* rhs, void* rfold, void* dout, int cls) {
   LaunchTimer tm(c, cls);
+  if constexpr (std::is_same<T, float>::value) {
+    if (nfold >= 2 && !c->dstream) {
+      // several pending samples (FP32): blocks of sixteen on the matrix cores,
+      // then the first D-step as a plain sweep of the folded C
+      const size_t lds = fold_mfma_lds(c->K, c->fs);
+      bool done = false;
+#define X(KP)                                                                                             \
+  if (!done && (c->K + 15) / 16 * 16 == KP) {                                                             \
+    TIMED_LAUNCH(tm, k_fold_mfma<KP>, dim3(c->Pf), dim3(FM_NT), lds, c->stream, (float*)c->Cm, c->fs, c->K, \
+                 c->Pf, (float2*)c->G, (float2*)rfold, (const float2*)c->Zt, c->maxB, (const float2*)c->xh, \
+                 nfold);                                                                                  \
+    done = true;                                                                                          \
+  }
+      OCSC_FOLD_KP(X)
+#undef X
+      if (!done) return fail(c, OCSC_E_STATE, "internal: no fold kernel for this K");
+      LAUNCHED(c);
+      tm.launched();
+      if (!dout) return OCSC_OK;
+      return launch_sweep<T>(c, 0, rfold ? rfold : c->G, nullptr, dout, cls);
+    }
+  }
   // successive sweeps alternate direction (the tail of one sweep first in the
   // next; with the non-temporal loads of C this no longer changes the time,
   // and the direction changes no result)
@@ -1449,6 +1475,18 @@ int ocsc_init(ocsc_ctx** out, int K, int filt_h, int filt_w, int pad_h, int pad_
     for (const void* fn : fns) {
       e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)std::max(c->sweep_smem, c->plain_smem));
+      if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    }
+  }
+
+  if (!c->dstream && sr == 4 && c->maxB > 1) {
+    const void* fn = nullptr;
+#define X(KP) \
+    if ((K + 15) / 16 * 16 == KP) fn = (const void*)k_fold_mfma<KP>;
+    OCSC_FOLD_KP(X)
+#undef X
+    if (fn) {
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fold_mfma_lds(K, c->fs));
       if (e != hipSuccess) return bail(OCSC_E_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     }
   }
