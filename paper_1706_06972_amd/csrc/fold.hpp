@@ -11,9 +11,10 @@
 //      pitch K + 1) is staged in LDS;
 //   2. per block: U from the frequency-major copy of the code spectra, G_p
 //      (and the warm-start right-hand side) += u_b x_bp in sample order;
-//      Y = C U, M = U^H Y, S^-1 by Gauss-Jordan elimination (S is Hermitian
-//      positive definite, its eigenvalues are >= 1), W = Y S^-1, and
-//      C <- C - W Y^H on the 16 x 16 tiles on and above the diagonal;
+//      Y = C U, M = U^H Y, S^-1 by Gauss-Jordan elimination without pivoting
+//      (S is Hermitian positive definite, its eigenvalues are >= 1), W =
+//      Y S^-1, and C <- C - W Y^H on the 16 x 16 tiles on and above the
+//      diagonal;
 //   3. C_p is written back.
 // The products run on v_mfma_f32_16x16x4_f32 (operand A[i][kk] in lane
 // i + 16 kk, B[kk][j] in lane j + 16 kk, result D[i][j] in lane j + 16 (i / 4),
@@ -33,209 +34,305 @@ __device__ __forceinline__ v4f fm_mfma(float a, float b, v4f c) {
 }
 
 // LDS of k_fold_mfma in bytes: R (fs reals), U and Y (re, im; 16 rows of
-// KP + 1), S (16 x 16, re and im), the block's x (16 complex)
+// KP + 1), S (16 x 16, re and im), four partial products U^H Y (re, im), the
+// block's x (16 complex)
+// (at least the staging stores of C: whole rounds of 256 16-byte vectors)
 __host__ __device__ inline size_t fold_mfma_lds(int K, int fs) {
-  const int kpp = (K + 15) / 16 * 16 + 1;
-  return ((size_t)fs + 4 * (size_t)FM_B * kpp + 2 * 256 + 2 * FM_B) * sizeof(float);
+  const int kp = (K + 15) / 16 * 16, kpp = kp + 1;
+  const size_t need = ((size_t)fs + 4 * (size_t)FM_B * kpp + 2 * 256 + 4 * 2 * 256 + 2 * FM_B) * sizeof(float);
+  const size_t stage = (size_t)((kp * (kp + 1) / 4 + FM_NT - 1) / FM_NT) * FM_NT * 16;
+  return need > stage ? need : stage;
 }
 
-// C[r][c] from the R-form (zero outside K x K)
+// C[r][c] from the R-form (zero outside K x K), without branches: the two
+// loads read R[min][max] and R[max][min] (address 0 outside K x K)
 __device__ __forceinline__ void fm_centry(const float* R, int ld, int K, int r, int c, float& cr, float& ci) {
-  cr = 0.f;
-  ci = 0.f;
-  if (r < K && c < K) {
-    if (r < c) {
-      cr = R[r * ld + c];
-      ci = R[c * ld + r];
-    } else if (r > c) {
-      cr = R[c * ld + r];
-      ci = -R[r * ld + c];
-    } else {
-      cr = R[r * ld + r];
-    }
-  }
+  const bool up = r < c, ok = r < K && c < K;
+  const int lo = up ? r : c, hi = up ? c : r;
+  const float a = R[ok ? lo * ld + hi : 0], b = R[ok ? hi * ld + lo : 0];
+  cr = ok ? a : 0.f;
+  ci = (!ok || r == c) ? 0.f : (up ? b : -b);
+}
+
+// acc += (ar + i ai)(br + i bi) on the matrix cores (four real products)
+__device__ __forceinline__ void fm_cmac(v4f& re, v4f& im, float ar, float ai, float br, float bi) {
+  re = fm_mfma(ar, br, re);
+  re = fm_mfma(-ai, bi, re);
+  im = fm_mfma(ar, bi, im);
+  im = fm_mfma(ai, br, im);
 }
 
 // One frequency per workgroup (blockIdx.x = p).  Cm: R-forms of pitch fs;
 // G, rfold (optional): complex [K][Pf]; Zt[(p * ldt + b) * K + k]: the code
 // spectra of the nfold pending samples; xh[b * Pf + p]: their sample spectra.
+// Per block: the code spectra were fetched into registers during the previous
+// block (thread k holds row k of U); Y = C U with a wave's row tiles
+// interleaved; M = U^H Y as four partial sums (one per wave), added in a
+// fixed order; S^-1 by one wave in registers; W = Y S^-1; the update tiles
+// two at a time.
 template <int KP>
 __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, int fs, int K, int Pf,
                                                         float2* __restrict__ G, float2* __restrict__ rfold,
                                                         const float2* __restrict__ Zt, int ldt,
                                                         const float2* __restrict__ xh, int nfold) {
-  constexpr int NB = KP / 16;           // 16-row tiles of C
-  constexpr int KPP = KP + 1;           // pitch of U, Y, W
-  constexpr int NTI = NB * (NB + 1) / 2;  // tiles on and above the diagonal
+  constexpr int NB = KP / 16;             // 16-row tiles of C
+  constexpr int KPP = KP + 1;             // pitch of U, Y, W
+  constexpr int TPW = (NB + 3) / 4;       // row tiles per wave
+  constexpr int NTI = NB * (NB + 1) / 2;  // update tiles on and above the diagonal
   extern __shared__ __align__(16) float fm_smem[];
   float* R = fm_smem;
-  float* Ur = R + fs;                   // U, then W
+  float* Ur = R + fs;                     // U, then W
   float* Ui = Ur + FM_B * KPP;
   float* Yr = Ui + FM_B * KPP;
   float* Yi = Yr + FM_B * KPP;
-  float* Sr = Yi + FM_B * KPP;
+  float* Sr = Yi + FM_B * KPP;            // S, then S^-1
   float* Si = Sr + 256;
-  float2* xs = reinterpret_cast<float2*>(Si + 256);
+  float* Mp = Si + 256;                   // [4][2][256]: partial products U^H Y
+  float2* xs = reinterpret_cast<float2*>(Mp + 4 * 2 * 256);
   const int p = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int ld = K + 1;
+  const float2* zt = Zt + (size_t)p * ldt * K;
 
+  // this thread's row of U for the block at b0 (thread k < KP; zero past K or nfold)
+  float2 zn[FM_B];
+  float2 xn = make_float2(0.f, 0.f);
+  auto fetch = [&](int b0) {
+    if (tid < KP) {
+#pragma unroll
+      for (int q = 0; q < FM_B; ++q)
+        zn[q] = (tid < K && b0 + q < nfold) ? zt[(size_t)(b0 + q) * K + tid] : make_float2(0.f, 0.f);
+    }
+    if (tid < FM_B) xn = b0 + tid < nfold ? xh[(size_t)(b0 + tid) * Pf + p] : make_float2(0.f, 0.f);
+  };
+  fetch(0);
   {
+    // every load issued before the first store: indices past C_p are clamped
+    // to its last vector, and their stores land in the U / Y area (written
+    // before it is read)
+    constexpr int NVM = (KP * (KP + 1) / 4 + FM_NT - 1) / FM_NT;
+    const int nv = fs / 4;
     const v4f* src = reinterpret_cast<const v4f*>(Cm + (size_t)p * fs);
     v4f* dst = reinterpret_cast<v4f*>(R);
-    for (int v = tid; v < fs / 4; v += FM_NT) dst[v] = __builtin_nontemporal_load(src + v);
+    v4f cv[NVM];
+#pragma unroll
+    for (int m = 0; m < NVM; ++m) cv[m] = __builtin_nontemporal_load(src + min(tid + m * FM_NT, nv - 1));
+#pragma unroll
+    for (int m = 0; m < NVM; ++m) dst[tid + m * FM_NT] = cv[m];
   }
   float2 gacc = make_float2(0.f, 0.f), racc = make_float2(0.f, 0.f);
   if (tid < K) {
     gacc = G[(size_t)tid * Pf + p];
     if (rfold) racc = rfold[(size_t)tid * Pf + p];
   }
-  const float2* zt = Zt + (size_t)p * ldt * K;
 
   for (int b0 = 0; b0 < nfold; b0 += FM_B) {
-    __syncthreads();   // C staged or updated; U, Y and S free
-    if (tid < FM_B) xs[tid] = b0 + tid < nfold ? xh[(size_t)(b0 + tid) * Pf + p] : make_float2(0.f, 0.f);
-    for (int e = tid; e < FM_B * KP; e += FM_NT) {
-      const int q = e / KP, k = e - q * KP;   // consecutive threads: consecutive k of one sample
-      float2 z = make_float2(0.f, 0.f);
-      if (k < K && b0 + q < nfold) z = zt[(size_t)(b0 + q) * K + k];
-      Ur[q * KPP + k] = z.x;   // u = conj(z)
-      Ui[q * KPP + k] = -z.y;
+    __syncthreads();   // C staged or updated; U, Y, S and the partials free
+    if (tid < KP) {
+#pragma unroll
+      for (int q = 0; q < FM_B; ++q) {
+        Ur[q * KPP + tid] = zn[q].x;   // u = conj(z)
+        Ui[q * KPP + tid] = -zn[q].y;
+      }
     }
+    if (tid < FM_B) xs[tid] = xn;
     __syncthreads();
     if (tid < K) {   // G_p[k] (and the carried right-hand side) += u_bk x_bp, in sample order
-      for (int q = 0; q < FM_B && b0 + q < nfold; ++q) {
-        const float ur = Ur[q * KPP + tid], ui = Ui[q * KPP + tid];
-        const float2 x = xs[q];
-        const float dr = ur * x.x - ui * x.y, di = ur * x.y + ui * x.x;
-        gacc.x += dr;
-        gacc.y += di;
-        racc.x += dr;
-        racc.y += di;
+#pragma unroll
+      for (int q = 0; q < FM_B; ++q) {
+        if (b0 + q < nfold) {
+          const float ur = zn[q].x, ui = -zn[q].y;
+          const float2 x = xs[q];
+          const float dr = ur * x.x - ui * x.y, di = ur * x.y + ui * x.x;
+          gacc.x += dr;
+          gacc.y += di;
+          racc.x += dr;
+          racc.y += di;
+        }
       }
     }
-    // Y = C U: wave -> row tiles I
-    for (int I = wave; I < NB; I += 4) {
-      v4f yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-      const int r = I * 16 + li;
-#pragma unroll 4
+    if (b0 + FM_B < nfold) fetch(b0 + FM_B);   // in flight during this block
+    // Y = C U: the wave's row tiles I = wave, wave + 4, ... in one k loop
+    {
+      v4f yr[TPW], yi[TPW];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) yr[t] = yi[t] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
       for (int ks = 0; ks < KP / 4; ++ks) {
         const int c = ks * 4 + lk;
-        float cr, ci;
-        fm_centry(R, ld, K, r, c, cr, ci);                  // A[i][kk] = C[r][c]
         const float ur = Ur[li * KPP + c], ui = Ui[li * KPP + c];   // B[kk][j] = U[c][j]
-        yr = fm_mfma(cr, ur, yr);
-        yr = fm_mfma(-ci, ui, yr);
-        yi = fm_mfma(cr, ui, yi);
-        yi = fm_mfma(ci, ur, yi);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+          const int I = wave + 4 * t;
+          if (I < NB) {
+            float cr, ci;
+            fm_centry(R, ld, K, I * 16 + li, c, cr, ci);           // A[i][kk] = C[I*16+i][c]
+            fm_cmac(yr[t], yi[t], cr, ci, ur, ui);
+          }
+        }
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {   // D[i][j]: row I * 16 + 4 lk + e, sample li
-        Yr[li * KPP + I * 16 + 4 * lk + e] = yr[e];
-        Yi[li * KPP + I * 16 + 4 * lk + e] = yi[e];
+      for (int t = 0; t < TPW; ++t) {
+        const int I = wave + 4 * t;
+        if (I < NB) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {   // D[i][j]: row I * 16 + 4 lk + e, sample li
+            Yr[li * KPP + I * 16 + 4 * lk + e] = yr[t][e];
+            Yi[li * KPP + I * 16 + 4 * lk + e] = yi[t][e];
+          }
+        }
       }
     }
     __syncthreads();
-    // S = I + U^H Y on wave 0
-    if (wave == 0) {
+    // partial M_w = sum over the wave's row tiles of U_I^H Y_I
+    {
       v4f mr = {0.f, 0.f, 0.f, 0.f}, mi = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-      for (int ks = 0; ks < KP / 4; ++ks) {
-        const int c = ks * 4 + lk;
-        const float ar = Ur[li * KPP + c], ai = -Ui[li * KPP + c];   // A[a][kk] = conj(U[c][a])
-        const float br = Yr[li * KPP + c], bi = Yi[li * KPP + c];    // B[kk][b] = Y[c][b]
-        mr = fm_mfma(ar, br, mr);
-        mr = fm_mfma(-ai, bi, mr);
-        mi = fm_mfma(ar, bi, mi);
-        mi = fm_mfma(ai, br, mi);
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int I = wave + 4 * t;
+        if (I < NB) {
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int c = I * 16 + ks * 4 + lk;
+            fm_cmac(mr, mi, Ur[li * KPP + c], -Ui[li * KPP + c], Yr[li * KPP + c], Yi[li * KPP + c]);
+          }
+        }
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int a = 4 * lk + e;
-        Sr[a * 16 + li] = mr[e] + (a == li ? 1.f : 0.f);
-        Si[a * 16 + li] = mi[e];
+      for (int e = 0; e < 4; ++e) {   // M[a][b]: a = 4 lk + e, b = li
+        Mp[(wave * 2) * 256 + (4 * lk + e) * 16 + li] = mr[e];
+        Mp[(wave * 2 + 1) * 256 + (4 * lk + e) * 16 + li] = mi[e];
       }
     }
-    // S^-1 in place by Gauss-Jordan elimination, thread (i, j) = (tid / 16, tid % 16)
-    {
-      const int i = tid >> 4, j = tid & 15;
+    __syncthreads();
+    if (wave == 0) {
+      // S = I + sum of the partials (fixed order), then S^-1 by Gauss-Jordan
+      // elimination on this wave alone: lane (j, g) = (lane % 16, lane / 16)
+      // holds S[g + 4 m][j], m = 0..3, and each step takes the pivot row and
+      // column from the lanes that hold them (before the step's update)
+      float ar[4], ai[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int idx = (lk + 4 * m) * 16 + li;
+        float sr = (lk + 4 * m) == li ? 1.f : 0.f, si = 0.f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          sr += Mp[(w * 2) * 256 + idx];
+          si += Mp[(w * 2 + 1) * 256 + idx];
+        }
+        ar[m] = sr;
+        ai[m] = si;
+      }
+#pragma unroll
       for (int k = 0; k < 16; ++k) {
-        __syncthreads();
-        const float aikr = Sr[i * 16 + k], aiki = Si[i * 16 + k];
-        const float akjr = Sr[k * 16 + j], akji = Si[k * 16 + j];
-        const float akkr = Sr[k * 16 + k], akki = Si[k * 16 + k];
-        const float aijr = Sr[tid], aiji = Si[tid];
-        __syncthreads();
+        const int km = k >> 2, kg = k & 3;
+        const float akkr = __shfl(ar[km], k + 16 * kg, 64), akki = __shfl(ai[km], k + 16 * kg, 64);
+        const float akjr = __shfl(ar[km], li + 16 * kg, 64), akji = __shfl(ai[km], li + 16 * kg, 64);
+        float aikr[4], aiki[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          aikr[m] = __shfl(ar[m], k + 16 * lk, 64);
+          aiki[m] = __shfl(ai[m], k + 16 * lk, 64);
+        }
         const float den = akkr * akkr + akki * akki;
         const float ivr = akkr / den, ivi = -akki / den;   // 1 / a_kk
         const float tr = akjr * ivr - akji * ivi, ti = akjr * ivi + akji * ivr;   // a_kj / a_kk
-        float nr, ni;
-        if (i == k && j == k) {
-          nr = ivr;
-          ni = ivi;
-        } else if (i == k) {
-          nr = tr;
-          ni = ti;
-        } else if (j == k) {
-          nr = -(aikr * ivr - aiki * ivi);
-          ni = -(aikr * ivi + aiki * ivr);
-        } else {
-          nr = aijr - (aikr * tr - aiki * ti);
-          ni = aiji - (aikr * ti + aiki * tr);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int i = lk + 4 * m;
+          float nr, ni;
+          if (i == k && li == k) {
+            nr = ivr;
+            ni = ivi;
+          } else if (i == k) {
+            nr = tr;
+            ni = ti;
+          } else if (li == k) {
+            nr = -(aikr[m] * ivr - aiki[m] * ivi);
+            ni = -(aikr[m] * ivi + aiki[m] * ivr);
+          } else {
+            nr = ar[m] - (aikr[m] * tr - aiki[m] * ti);
+            ni = ai[m] - (aikr[m] * ti + aiki[m] * tr);
+          }
+          ar[m] = nr;
+          ai[m] = ni;
         }
-        Sr[tid] = nr;
-        Si[tid] = ni;
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        Sr[(lk + 4 * m) * 16 + li] = ar[m];
+        Si[(lk + 4 * m) * 16 + li] = ai[m];
       }
     }
-    __syncthreads();
+    __syncthreads();   // S^-1 in (Sr, Si)
     // W = Y S^-1 into U's place
-    for (int I = wave; I < NB; I += 4) {
-      v4f wr = {0.f, 0.f, 0.f, 0.f}, wi = {0.f, 0.f, 0.f, 0.f};
+    {
+      v4f wr[TPW], wi[TPW];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) wr[t] = wi[t] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int q = ks * 4 + lk;
-        const float ar = Yr[q * KPP + I * 16 + li], ai = Yi[q * KPP + I * 16 + li];   // A[i][kk] = Y[I*16+i][q]
-        const float br = Sr[q * 16 + li], bi = Si[q * 16 + li];                       // B[kk][j] = S^-1[q][j]
-        wr = fm_mfma(ar, br, wr);
-        wr = fm_mfma(-ai, bi, wr);
-        wi = fm_mfma(ar, bi, wi);
-        wi = fm_mfma(ai, br, wi);
+        const float br = Sr[q * 16 + li], bi = Si[q * 16 + li];   // B[kk][j] = S^-1[q][j]
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+          const int I = wave + 4 * t;
+          if (I < NB) fm_cmac(wr[t], wi[t], Yr[q * KPP + I * 16 + li], Yi[q * KPP + I * 16 + li], br, bi);
+        }
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        Ur[li * KPP + I * 16 + 4 * lk + e] = wr[e];
-        Ui[li * KPP + I * 16 + 4 * lk + e] = wi[e];
+      for (int t = 0; t < TPW; ++t) {
+        const int I = wave + 4 * t;
+        if (I < NB) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            Ur[li * KPP + I * 16 + 4 * lk + e] = wr[t][e];
+            Ui[li * KPP + I * 16 + 4 * lk + e] = wi[t][e];
+          }
+        }
       }
     }
     __syncthreads();
-    // C <- C - W Y^H on the tiles (I, J), I <= J
-    for (int t = wave; t < NTI; t += 4) {
-      int I = 0, tt = t;
-      while (tt >= NB - I) {
-        tt -= NB - I;
-        ++I;
+    // C <- C - W Y^H on the tiles (I, J), I <= J, two at a time
+    for (int t0 = wave; t0 < NTI; t0 += 8) {
+      int ti[2], tj[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        int I = 0, tt = min(t0 + 4 * h, NTI - 1);
+        while (tt >= NB - I) {
+          tt -= NB - I;
+          ++I;
+        }
+        ti[h] = I;
+        tj[h] = I + tt;
       }
-      const int J = I + tt;
-      v4f pr = {0.f, 0.f, 0.f, 0.f}, pi = {0.f, 0.f, 0.f, 0.f};
+      const bool two = t0 + 4 < NTI;
+      v4f pr[2], pim[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) pr[h] = pim[h] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int q = ks * 4 + lk;
-        const float ar = Ur[q * KPP + I * 16 + li], ai = Ui[q * KPP + I * 16 + li];    // A[i][kk] = W[I*16+i][q]
-        const float br = Yr[q * KPP + J * 16 + li], bi = -Yi[q * KPP + J * 16 + li];   // B[kk][j] = conj(Y[J*16+j][q])
-        pr = fm_mfma(ar, br, pr);
-        pr = fm_mfma(-ai, bi, pr);
-        pi = fm_mfma(ar, bi, pi);
-        pi = fm_mfma(ai, br, pi);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (h == 0 || two)   // A[i][kk] = W[I*16+i][q], B[kk][j] = conj(Y[J*16+j][q])
+            fm_cmac(pr[h], pim[h], Ur[q * KPP + ti[h] * 16 + li], Ui[q * KPP + ti[h] * 16 + li],
+                    Yr[q * KPP + tj[h] * 16 + li], -Yi[q * KPP + tj[h] * 16 + li]);
+        }
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = I * 16 + 4 * lk + e, c = J * 16 + li;
-        if (r < K && c < K) {
-          if (r < c) {
-            R[r * ld + c] -= pr[e];   // Re C_rc
-            R[c * ld + r] -= pi[e];   // Im C_rc
-          } else if (r == c) {
-            R[r * ld + r] -= pr[e];
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && !two) break;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = ti[h] * 16 + 4 * lk + e, c = tj[h] * 16 + li;
+          if (r < K && c < K) {
+            if (r < c) {
+              R[r * ld + c] -= pr[h][e];    // Re C_rc
+              R[c * ld + r] -= pim[h][e];   // Im C_rc
+            } else if (r == c) {
+              R[r * ld + r] -= pr[h][e];
+            }
           }
         }
       }
