@@ -68,8 +68,8 @@ __device__ __forceinline__ void fm_cmac(v4f& re, v4f& im, float ar, float ai, fl
 // Per block: the code spectra were fetched into registers during the previous
 // block (thread k holds row k of U); Y = C U with a wave's row tiles
 // interleaved; M = U^H Y as four partial sums (one per wave), added in a
-// fixed order; S^-1 by one wave in registers; W = Y S^-1; the update tiles
-// two at a time.
+// fixed order; S^-1 by one wave in registers (a column per lane); W = Y S^-1;
+// the update tiles two at a time.
 template <int KP>
 __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, int fs, int K, int Pf,
                                                         float2* __restrict__ G, float2* __restrict__ rfold,
@@ -207,61 +207,56 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
     __syncthreads();
     if (wave == 0) {
       // S = I + sum of the partials (fixed order), then S^-1 by Gauss-Jordan
-      // elimination on this wave alone: lane (j, g) = (lane % 16, lane / 16)
-      // holds S[g + 4 m][j], m = 0..3, and each step takes the pivot row and
-      // column from the lanes that hold them (before the step's update)
-      float ar[4], ai[4];
+      // elimination on this wave alone: lane j < 16 holds column j of S in
+      // registers; step k reads the pivot column from lane k (readlane, the
+      // same value for the whole wave) and its own element of the pivot row
+      float cr[16], ci[16];
+      const int j = li;   // lanes 16..63 repeat lanes 0..15
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int idx = (lk + 4 * m) * 16 + li;
-        float sr = (lk + 4 * m) == li ? 1.f : 0.f, si = 0.f;
+      for (int i = 0; i < 16; ++i) {
+        const int idx = i * 16 + j;
+        float sr = i == j ? 1.f : 0.f, si = 0.f;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
           sr += Mp[(w * 2) * 256 + idx];
           si += Mp[(w * 2 + 1) * 256 + idx];
         }
-        ar[m] = sr;
-        ai[m] = si;
+        cr[i] = sr;
+        ci[i] = si;
       }
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const int km = k >> 2, kg = k & 3;
-        const float akkr = __shfl(ar[km], k + 16 * kg, 64), akki = __shfl(ai[km], k + 16 * kg, 64);
-        const float akjr = __shfl(ar[km], li + 16 * kg, 64), akji = __shfl(ai[km], li + 16 * kg, 64);
-        float aikr[4], aiki[4];
+        float pr[16], pim[16];   // column k of the current matrix (from lane k)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          aikr[m] = __shfl(ar[m], k + 16 * lk, 64);
-          aiki[m] = __shfl(ai[m], k + 16 * lk, 64);
+        for (int i = 0; i < 16; ++i) {
+          pr[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cr[i]), k));
+          pim[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ci[i]), k));
         }
-        const float den = akkr * akkr + akki * akki;
-        const float ivr = akkr / den, ivi = -akki / den;   // 1 / a_kk
-        const float tr = akjr * ivr - akji * ivi, ti = akjr * ivi + akji * ivr;   // a_kj / a_kk
+        const float den = pr[k] * pr[k] + pim[k] * pim[k];
+        const float ivr = pr[k] / den, ivi = -pim[k] / den;   // 1 / a_kk
+        // a_kj / a_kk (this lane's element of the pivot row)
+        const float tr = cr[k] * ivr - ci[k] * ivi, ti = cr[k] * ivi + ci[k] * ivr;
+        const bool pivcol = j == k;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int i = lk + 4 * m;
-          float nr, ni;
-          if (i == k && li == k) {
-            nr = ivr;
-            ni = ivi;
-          } else if (i == k) {
-            nr = tr;
-            ni = ti;
-          } else if (li == k) {
-            nr = -(aikr[m] * ivr - aiki[m] * ivi);
-            ni = -(aikr[m] * ivi + aiki[m] * ivr);
+        for (int i = 0; i < 16; ++i) {
+          if (i == k) {
+            cr[i] = pivcol ? ivr : tr;
+            ci[i] = pivcol ? ivi : ti;
           } else {
-            nr = ar[m] - (aikr[m] * tr - aiki[m] * ti);
-            ni = ai[m] - (aikr[m] * ti + aiki[m] * tr);
+            // column k: -a_ik / a_kk;  elsewhere: a_ij - a_ik a_kj / a_kk
+            const float fr = pivcol ? ivr : tr, fi = pivcol ? ivi : ti;
+            const float qr = pr[i] * fr - pim[i] * fi, qi = pr[i] * fi + pim[i] * fr;
+            cr[i] = pivcol ? -qr : cr[i] - qr;
+            ci[i] = pivcol ? -qi : ci[i] - qi;
           }
-          ar[m] = nr;
-          ai[m] = ni;
         }
       }
+      if (lane < 16) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        Sr[(lk + 4 * m) * 16 + li] = ar[m];
-        Si[(lk + 4 * m) * 16 + li] = ai[m];
+        for (int i = 0; i < 16; ++i) {
+          Sr[i * 16 + j] = cr[i];
+          Si[i * 16 + j] = ci[i];
+        }
       }
     }
     __syncthreads();   // S^-1 in (Sr, Si)
