@@ -3,6 +3,8 @@ FP64 oracle and, where one exists, a closed form:
 
 * the largest K of the Sherman-Morrison form in each precision (C_p held in
   LDS: K = 92 in FP64, K = 128 in FP32);
+* FP32 minibatches folded sixteen samples at a time on the matrix cores,
+  with a ragged last block and K not a multiple of 16;
 * filters as large as the grid (the crop of the V-step keeps every tap);
 * lambda = 0 (no shrinkage: dense codes);
 * an all-zero sample: zero codes, an unchanged history, and the zero
@@ -100,6 +102,37 @@ def test_minibatch_fold_at_the_largest_k(prec, K):
             "D": rel(to_np(g.get_dictionary()), o.get_dictionary())}
     say(f"  errors {errs}")
     assert all(v < TOL[prec] for v in errs.values()), errs
+    g.close()
+
+
+@pytest.mark.parametrize("K,B", [(37, 37), (100, 33), (16, 48)])
+def test_minibatch_fold_in_blocks_of_sixteen(K, B):
+    """FP32: a minibatch of B samples folds sixteen at a time on the matrix
+    cores (whole blocks, then a ragged one; K not a multiple of 16 pads the
+    blocks), against the oracle's sample-by-sample recursion; then a second
+    minibatch on the updated dictionary."""
+    say(f"case matrix-core fold f32 K={K} B={B}")
+    from paper_1706_06972_amd.ocsc import OCSC
+    xs = images(2 * B, 32, 32, seed=11)
+    g = OCSC(K, 5, 5, 32, 32, 0.5, 1.0, precision="f32", max_batch=B)
+    o = O.OCSC(K, 5, 5, 32, 32, 0.5, 1.0)
+    D0 = synth.initial_dictionary(K, 5, 5, 1)
+    g.set_dictionary(D0)
+    o.set_dictionary(D0)
+    for step in range(2):
+        batch = xs[step * B:(step + 1) * B]
+        U = to_np(g.code_update(batch))
+        Uo = o.code_update(batch)
+        g.history_accumulate()
+        o.history_accumulate()
+        g.dict_update()
+        o.dict_update()
+        errs = {"codes": rel(U, Uo),
+                "G": rel(spectra(to_np(g.state("G")), (K,), 32, 32), o.G),
+                "C": rel(unpack_cinv(to_np(g.state("cinv")), K, 32, 32), o.C),
+                "D": rel(to_np(g.get_dictionary()), o.get_dictionary())}
+        say(f"  minibatch {step}: errors {errs}")
+        assert all(v < TOL["f32"] for v in errs.values()), errs
     g.close()
 
 
