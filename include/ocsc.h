@@ -331,11 +331,15 @@ int ocsc_graph_destroy(ocsc_graph* graph);
 /* ---------------------------------------------------------------------------
  * Launch shapes of the code update (the per-sample ADMM of eq. fcsc_code:
  * Z-step and plane kernel, 2 launches per code iteration) and their
- * autotuner.  Every valid shape computes the same values bit for bit (the
- * per-element arithmetic and the order of every sum are fixed); only the
- * speed differs, so a tuned context reproduces an untuned one exactly.
- *   plane_threads: threads per workgroup of the plane kernel, one plane per
- *                  workgroup: 256, 512 or 1024, at most pad_h * pad_w / 4.
+ * autotuner.  Every valid shape with two_pass 0 or 1 computes the same values
+ * bit for bit (the per-element arithmetic and the order of every sum are
+ * fixed); only the speed differs, so a tuned context reproduces an untuned
+ * one exactly.  The split plane step (two_pass 2) factors the column DFTs
+ * differently: its shapes agree bit for bit among themselves, and with the
+ * others to rounding.
+ *   plane_threads: threads per workgroup of the plane kernel, one plane (or
+ *                  half a plane, two_pass 2) per workgroup: 256, 512 or
+ *                  1024, at most pad_h * pad_w / 4.
  *                  Grids with a side above 128 use fixed two-pass kernels
  *                  and accept only 256.
  *   zstep_freqs:   frequencies per Z-step workgroup, 16, 32 or 64
@@ -356,7 +360,10 @@ int ocsc_graph_destroy(ocsc_graph* graph);
  *                  one-pass plane kernel) or 1 (the column and row passes,
  *                  more workgroups for small batches; the first selection
  *                  allocates a max_batch x K spectrum buffer, OCSC_E_OOM);
- *                  0 on other grids.
+ *                  0 on other grids.  On every one-pass grid also 2: each
+ *                  plane split by row parity over two workgroups (twice the
+ *                  workgroups, for batches that leave CUs idle); the last
+ *                  radix-2 step of the column DFTs then runs in the Z-step.
  * Defaults: plane_threads 1024 for 128 x 128 grids, else 256; 16; 1; 128; 8; 0;
  * 1 on two-pass grids, else 0.
  * ocsc_autotune times whole code updates for the group size.

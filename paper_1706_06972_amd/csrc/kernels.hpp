@@ -216,6 +216,146 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
 }
 
 // ---------------------------------------------------------------------------
+// The same step with each plane split over two workgroups by row parity
+// (workgroup e = 0, 1 takes rows r = 2m + e), for batches too small to fill
+// the chip with one workgroup per plane.  A column DFT of length PH is one
+// radix-2 step over two DFTs of length PH/2, on the even and the odd rows:
+//   forward  X[h] = E_0[h'] + w^h E_1[h'],  h' = h mod PH/2,  w = e^{-2 pi i/PH};
+//   inverse  rows 2m + e of the inverse column DFT of Y are the inverse DFTs
+//            of length PH/2 of Y[h'] + Y[h' + PH/2] (e = 0) and of
+//            (Y[h'] - Y[h' + PH/2]) conj(w^h') (e = 1).
+// Workgroup e forms its length-PH/2 spectrum from Zh on the way into LDS,
+// runs the half-height transforms, the U-step and the dual on its rows, and
+// writes E_e (the column DFTs of length PH/2 of its rows of U - W) to rows
+// [e PH/2, (e + 1) PH/2) of the plane's slot of S.  The Z-step forms
+// F(U - W) from E_0 and E_1 (zstep_body with SPLIT).
+// ---------------------------------------------------------------------------
+template <typename T, int PH, int PW, int NT>
+__device__ __forceinline__ void code_plane_split_body(cx<T>* buf, cx<T>* sH, cx<T>* sW, long q, int e,
+                                                      const cx<T>* __restrict__ Zh, T* __restrict__ W,
+                                                      cx<T>* __restrict__ S, T* __restrict__ Uout,
+                                                      const cx<T>* __restrict__ twH,
+                                                      const cx<T>* __restrict__ twW, T kappa, int first,
+                                                      int last) {
+  using G = PlaneGeom<PH, PW>;
+  constexpr int PHH = PH / 2;
+  constexpr int VR = 16 / (int)sizeof(T);    // reals per vector
+  constexpr int CV = VR / 2;                 // complex values per vector
+  static_assert((PHH * G::WC) % CV == 0, "half spectrum in whole vectors");
+  constexpr int NSV = PHH * G::WC / CV;      // vectors per half spectrum
+  constexpr int NRV = PHH * PW / VR;         // vectors per half plane
+  constexpr int CS = (NSV + NT - 1) / NT, CR = (NRV + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
+  // spectrum rows h' and h' + PH/2 of the plane, and the dual on this workgroup's rows
+  const v4f* zs = reinterpret_cast<const v4f*>(Zh + q * G::PF);
+  v4f lo[CS], hi[CS];
+#pragma unroll
+  for (int j = 0; j < CS; ++j) {
+    const int v = tid + j * NT;
+    if (NSV % NT == 0 || v < NSV) {
+      lo[j] = zs[v];
+      hi[j] = zs[v + NSV];
+    }
+  }
+  T* const Wq = W + q * G::P;
+  v4f wr[CR];
+#pragma unroll
+  for (int j = 0; j < CR; ++j) {
+    const int v = tid + j * NT;
+    if (NRV % NT == 0 || v < NRV) {
+      const int i = v * VR, m = i / PW;
+      wr[j] = first ? v4f{0, 0, 0, 0} : *reinterpret_cast<const v4f*>(Wq + (2 * m + e) * PW + i % PW);
+    }
+  }
+  __syncthreads();   // tables
+  v4f* d = reinterpret_cast<v4f*>(buf);
+#pragma unroll
+  for (int j = 0; j < CS; ++j) {
+    const int v = tid + j * NT;
+    if (NSV % NT == 0 || v < NSV) {
+      const cx<T>* a = reinterpret_cast<const cx<T>*>(&lo[j]);
+      const cx<T>* b = reinterpret_cast<const cx<T>*>(&hi[j]);
+      v4f o;
+      cx<T>* oc = reinterpret_cast<cx<T>*>(&o);
+#pragma unroll
+      for (int c = 0; c < CV; ++c)
+        oc[c] = e == 0 ? cadd<T>(a[c], b[c]) : cmulc<T>(csub<T>(a[c], b[c]), sH[(v * CV + c) / G::WC]);
+      d[v] = o;
+    }
+  }
+  __syncthreads();
+  irfft2_half_lds<PHH, PW, NT, T>(buf, sH, sW, tid);
+  const T scale = (T)1 / (T)G::P;
+#pragma unroll
+  for (int j = 0; j < CR; ++j) {
+    const int v = tid + j * NT;
+    if (NRV % NT == 0 || v < NRV) {
+      const int i = v * VR, m = i / PW, col = i % PW;
+      cx<T>* o = buf + m * G::LDW + (col >> 1);
+      T* w = reinterpret_cast<T*>(&wr[j]);
+      v4f uo;
+      T* u = reinterpret_cast<T*>(&uo);
+#pragma unroll
+      for (int h = 0; h < VR / 2; ++h) {
+        const cx<T> y = o[h];
+        const T v0 = fma(y.x, scale, w[2 * h]), v1 = fma(y.y, scale, w[2 * h + 1]);
+        const T u0 = copysign(fmax(fabs(v0) - kappa, (T)0), v0);
+        const T u1 = copysign(fmax(fabs(v1) - kappa, (T)0), v1);
+        u[2 * h] = u0;
+        u[2 * h + 1] = u1;
+        w[2 * h] = v0 - u0;
+        w[2 * h + 1] = v1 - u1;
+        o[h] = mk<T>(u0 - w[2 * h], u1 - w[2 * h + 1]);
+      }
+      const long off = (long)(2 * m + e) * PW + col;
+      if (last) {
+        if (Uout) *reinterpret_cast<v4f*>(Uout + q * G::P + off) = uo;
+      } else {
+        *reinterpret_cast<v4f*>(Wq + off) = wr[j];
+      }
+    }
+  }
+  if (last) return;
+  __syncthreads();
+  rfft2_half_lds<PHH, PW, NT, T>(buf, sH, sW, tid);
+  v4f* so = reinterpret_cast<v4f*>(S + q * G::PF + (long)e * PHH * G::WC);
+#pragma unroll
+  for (int j = 0; j < CS; ++j) {
+    const int v = tid + j * NT;
+    if (NSV % NT == 0 || v < NSV) so[v] = d[v];
+  }
+}
+
+// Block b of 2 n -> (plane q, parity e).  The two workgroups of a plane are
+// eight blocks apart, so they run on the same XCD and the second read of the
+// plane's spectrum can come from its L2.  A bijection on [0, 2n).
+__device__ __forceinline__ void split_block(int b, int n, int& q, int& e) {
+  const int full = n >> 3;
+  if (b < full * 16) {
+    q = (b >> 4) * 8 + (b & 7);
+    e = (b >> 3) & 1;
+  } else {
+    const int t = b - full * 16, r = n - full * 8;
+    q = full * 8 + t % r;
+    e = t / r;
+  }
+}
+
+template <typename T, int PH, int PW, int NT>
+__global__ __launch_bounds__(NT) void k_code_plane_split(const cx<T>* __restrict__ Zh, T* __restrict__ W,
+                                                         cx<T>* __restrict__ S, T* __restrict__ Uout,
+                                                         const cx<T>* __restrict__ twH,
+                                                         const cx<T>* __restrict__ twW, T kappa, int first,
+                                                         int last, int nplanes) {
+  __shared__ __align__(16) cx<T> buf[(PH / 2) * PlaneGeom<PH, PW>::LDW];
+  __shared__ cx<T> sH[PH], sW[PW];
+  int q, e;
+  split_block((int)blockIdx.x, nplanes, q, e);
+  code_plane_split_body<T, PH, PW, NT>(buf, sH, sW, (long)q, e, Zh, W, S, Uout, twH, twW, kappa, first, last);
+}
+
+// ---------------------------------------------------------------------------
 // Code update, frequency half of one ADMM iteration (the Z-step).  At each
 // frequency p with a = Dh[:, p], s = S[:, p]:
 //   z = s + conj(a) * gam_p * (x_p - a^T s),   gam_p = 1 / (rho + ||a||^2),
@@ -228,18 +368,29 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
 // order for every ZF and SB (per thread over j, then over the 16 threads of a
 // frequency in kq order), so every launch shape gives the same bits.
 // first: s = 0.
+// SPLIT: S holds, per plane, the half-height column DFTs E_0 and E_1 of the
+// split plane step (rows [0, PH/2) and [PH/2, PH)), and s = E_0[h'] + w^h
+// E_1[h'] is formed here (twH[h] = w^h = e^{-2 pi i h/PH}, WC stored columns).
+// A workgroup then serves ZF/2 frequencies of the upper half and the ZF/2
+// frequencies PH/2 rows below them, which read the same E values.
 // ---------------------------------------------------------------------------
 // The body serves frequency block bx of sample block by with the LDS
 // reduction buffer red (16 * (ZF + 1) complex).
-template <typename T, int KPT, int ZF, int SB>
+template <typename T, int KPT, int ZF, int SB, bool SPLIT = false>
 __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by, const cx<T>* __restrict__ Dh,
                                            const T* __restrict__ gam, const cx<T>* __restrict__ xh,
                                            const cx<T>* __restrict__ S, cx<T>* __restrict__ Zh, int K, int Pf,
-                                           int B, int first, cx<T>* __restrict__ Zt, int ldt, int bt0) {
+                                           int B, int first, cx<T>* __restrict__ Zt, int ldt, int bt0,
+                                           const cx<T>* __restrict__ twH = nullptr, int WC = 1) {
   // Zt (optional): the same values frequency-major, Zt[(p * ldt + bt0 + b) * K + k]
   const int f = threadIdx.x % ZF, kq = threadIdx.x / ZF;
-  const int p = bx * ZF + f;
-  const bool ok = p < Pf;
+  constexpr int ZH = ZF / 2;
+  const int half = Pf / 2;
+  const int jh = bx * ZH + f % ZH;   // SPLIT: index within a half spectrum
+  const int p = SPLIT ? jh + (f >= ZH ? half : 0) : bx * ZF + f;
+  const bool ok = SPLIT ? jh < half : p < Pf;
+  cx<T> tw = mk<T>(0, 0);
+  if (SPLIT && ok) tw = twH[p / WC];
   cx<T> a[KPT];
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
@@ -254,7 +405,12 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int k = kq + j * 16;
-      s[j] = (ok && k < K && !first) ? S[((size_t)b * K + k) * Pf + p] : mk<T>(0, 0);
+      if (SPLIT) {
+        const cx<T>* e0 = S + ((size_t)b * K + k) * Pf + jh;
+        s[j] = (ok && k < K && !first) ? cadd<T>(e0[0], cmul<T>(e0[half], tw)) : mk<T>(0, 0);
+      } else {
+        s[j] = (ok && k < K && !first) ? S[((size_t)b * K + k) * Pf + p] : mk<T>(0, 0);
+      }
       acc = cadd<T>(acc, cmul<T>(a[j], s[j]));
     }
     red[kq][f] = acc;
@@ -282,15 +438,17 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
   }
 }
 
-template <typename T, int KPT, int ZF, int SB>
+template <typename T, int KPT, int ZF, int SB, bool SPLIT>
 __global__ __launch_bounds__(16 * ZF) void k_code_zstep(const cx<T>* __restrict__ Dh,
                                                         const T* __restrict__ gam,
                                                         const cx<T>* __restrict__ xh,
                                                         const cx<T>* __restrict__ S,
                                                         cx<T>* __restrict__ Zh, int K, int Pf, int B,
-                                                        int first, cx<T>* __restrict__ Zt, int ldt, int bt0) {
+                                                        int first, cx<T>* __restrict__ Zt, int ldt, int bt0,
+                                                        const cx<T>* __restrict__ twH, int WC) {
   __shared__ cx<T> red[16][ZF + 1];
-  zstep_body<T, KPT, ZF, SB>(red, blockIdx.x, blockIdx.y, Dh, gam, xh, S, Zh, K, Pf, B, first, Zt, ldt, bt0);
+  zstep_body<T, KPT, ZF, SB, SPLIT>(red, blockIdx.x, blockIdx.y, Dh, gam, xh, S, Zh, K, Pf, B, first, Zt, ldt,
+                                    bt0, twH, WC);
 }
 
 // gam_p = 1 / (rho + sum_k |Dh[k][p]|^2): 64 frequencies per workgroup, the

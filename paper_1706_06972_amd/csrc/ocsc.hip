@@ -370,12 +370,41 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
   // samples [off, off + nplanes / K) of the code workspace
   cx<T>* const Zh = (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf;
   cx<T>* const S = (cx<T>*)c->S + (size_t)off * c->K * c->Pf;
-  cx<T>* const Yb = c->tune.two_pass ? (cx<T>*)c->Yb + (size_t)off * c->K * c->Pf : nullptr;
+  cx<T>* const Yb = c->tune.two_pass == 1 ? (cx<T>*)c->Yb + (size_t)off * c->K * c->Pf : nullptr;
   T* const W = (T*)c->W + (size_t)off * c->K * c->P;
   ProfScope ps(c, OCSC_KC_CODEPLANE);
   const cx<T>* tH = (const cx<T>*)c->twH;
   const cx<T>* tW = (const cx<T>*)c->twW;
   const T kappa = (T)(c->lam / c->rho);
+  if (c->tune.two_pass == 2) {
+    // each plane split by row parity over two workgroups (the Z-step forms the spectrum)
+    const int nt = c->tune.plane_threads;
+    bool done = false;
+    switch (c->Ph * 1000 + c->Pw) {
+#define OCSC_SPLIT_NT(A, B, NT)                                                                          \
+  if constexpr (plane_nt_ok(A, B, NT)) {                                                                 \
+    if (nt == NT) {                                                                                      \
+      hipLaunchKernelGGL((k_code_plane_split<T, A, B, NT>), dim3(2 * nplanes), dim3(NT), 0, c->stream,   \
+                         (const cx<T>*)Zh, W, S, Uout, tH, tW, kappa, first, last, nplanes);             \
+      done = true;                                                                                       \
+    }                                                                                                    \
+  }
+#define X(A, B)              \
+  case A * 1000 + B:         \
+    OCSC_SPLIT_NT(A, B, 256)  \
+    OCSC_SPLIT_NT(A, B, 512)  \
+    OCSC_SPLIT_NT(A, B, 1024) \
+    break;
+      OCSC_SIZE_CASES(X)
+#undef X
+#undef OCSC_SPLIT_NT
+      default:
+        break;
+    }
+    if (!done) return fail(c, OCSC_E_UNSUPPORTED, "no split code-plane kernel for this grid and workgroup size");
+    LAUNCHED(c);
+    return OCSC_OK;
+  }
   if (c->tune.two_pass) {
     // column inverse of Zh into Y, row pass (U-step, dual, rows of F(U - W)) into S, column pass on S
     bool done = false;
@@ -424,11 +453,21 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
 
 template <typename T, int KPT, int ZF, int SB>
 void zstep_kernel(ocsc_ctx* c, int off, int B, int first, cx<T>* Zt) {
+  const cx<T>* xh = (const cx<T>*)c->xh + (size_t)off * c->Pf;
+  const cx<T>* S = (const cx<T>*)c->S + (size_t)off * c->K * c->Pf;
+  cx<T>* Zh = (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf;
+  if (c->tune.two_pass == 2) {
+    // S holds the half-height column DFTs of the split plane step
+    const dim3 grid((c->Pf / 2 + ZF / 2 - 1) / (ZF / 2), (B + SB - 1) / SB);
+    hipLaunchKernelGGL((k_code_zstep<T, KPT, ZF, SB, true>), grid, dim3(16 * ZF), 0, c->stream,
+                       (const cx<T>*)c->Dh, (const T*)c->gam, xh, S, Zh, c->K, c->Pf, B, first, Zt, c->maxB, off,
+                       (const cx<T>*)c->twH, c->Wc);
+    return;
+  }
   const dim3 grid((c->Pf + ZF - 1) / ZF, (B + SB - 1) / SB);
-  hipLaunchKernelGGL((k_code_zstep<T, KPT, ZF, SB>), grid, dim3(16 * ZF), 0, c->stream, (const cx<T>*)c->Dh,
-                     (const T*)c->gam, (const cx<T>*)c->xh + (size_t)off * c->Pf,
-                     (const cx<T>*)c->S + (size_t)off * c->K * c->Pf, (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf,
-                     c->K, c->Pf, B, first, Zt, c->maxB, off);
+  hipLaunchKernelGGL((k_code_zstep<T, KPT, ZF, SB, false>), grid, dim3(16 * ZF), 0, c->stream, (const cx<T>*)c->Dh,
+                     (const T*)c->gam, xh, S, Zh, c->K, c->Pf, B, first, Zt, c->maxB, off, (const cx<T>*)nullptr,
+                     c->Wc);
 }
 
 template <typename T, int KPT>
@@ -1759,7 +1798,8 @@ bool tuning_valid(const ocsc_ctx* c, const ocsc_tuning& t) {
   const bool rb = t.row_block == 4 || t.row_block == 8 || t.row_block == 16;
   const bool ch = t.chunk_samples == 0 || t.chunk_samples == 1 || t.chunk_samples == 2 || t.chunk_samples == 4 ||
                   t.chunk_samples == 8 || t.chunk_samples == 16;
-  const bool tp = c->big ? t.two_pass == 1 : (t.two_pass == 0 || (t.two_pass == 1 && two_pass_capable(c->Ph, c->Pw)));
+  const bool tp = c->big ? t.two_pass == 1
+                         : (t.two_pass == 0 || t.two_pass == 2 || (t.two_pass == 1 && two_pass_capable(c->Ph, c->Pw)));
   return pt && zf && sb && cb && rb && ch && tp;
 }
 
@@ -1821,22 +1861,29 @@ int autotune_t(ocsc_ctx* c, int B, double* best_ms) {
   ocsc_tuning best = start;
   double best_z = 1e30, best_p = 1e30;
   constexpr int REPS = 3;
-  for (int zf : {16, 32, 64}) {
-    for (int sb : {1, 2, 4}) {
-      c->tune.zstep_freqs = zf;
-      c->tune.zstep_samples = sb;
-      double ms = 0;
-      rc = time_launches(c, ev, [&] { return launch_zstep<T>(c, 0, B, 0, false); }, REPS, &ms);
-      if (rc) break;
-      if (ms < best_z) {
-        best_z = ms;
-        best.zstep_freqs = zf;
-        best.zstep_samples = sb;
+  // Z-step tiles; tp = 2: the Z-step of the split plane step (it forms its
+  // input from two half-height spectra)
+  auto tune_zstep = [&](int tp, ocsc_tuning& into, double& ms_best) {
+    for (int zf : {16, 32, 64}) {
+      for (int sb : {1, 2, 4}) {
+        c->tune = start;
+        c->tune.two_pass = tp;
+        c->tune.zstep_freqs = zf;
+        c->tune.zstep_samples = sb;
+        double ms = 0;
+        rc = time_launches(c, ev, [&] { return launch_zstep<T>(c, 0, B, 0, false); }, REPS, &ms);
+        if (rc) return;
+        if (ms < ms_best) {
+          ms_best = ms;
+          into.zstep_freqs = zf;
+          into.zstep_samples = sb;
+        }
       }
     }
-    if (rc) break;
-  }
+  };
+  tune_zstep(c->big ? 1 : 0, best, best_z);
   c->tune = start;
+  if (c->tune.two_pass == 2) c->tune.two_pass = 0;
   // plane step: workgroup size of the one-pass kernel, or column block x row
   // block of the two-pass kernels (two-pass grids, and 64 x 64 / 128 x 128
   // grids as an alternative)
@@ -1866,6 +1913,33 @@ int autotune_t(ocsc_ctx* c, int B, double* best_ms) {
           }
         }
       }
+    }
+  }
+  // split planes (one-pass grids), with the Z-step tile chosen for them: kept
+  // if the Z-step and plane step together beat the unsplit pair
+  if (!c->big && !rc) {
+    ocsc_tuning split = best;
+    split.two_pass = 2;
+    double sz = 1e30, sp = 1e30;
+    tune_zstep(2, split, sz);
+    for (int nt : {256, 512, 1024}) {
+      if (rc) break;
+      ocsc_tuning t = split;
+      t.plane_threads = nt;
+      if (!tuning_valid(c, t)) continue;
+      c->tune = t;
+      double ms = 0;
+      rc = time_launches(c, ev, [&] { return launch_code_plane<T>(c, 0, B * c->K, nullptr, 0, 0); }, REPS, &ms);
+      if (rc) break;
+      if (ms < sp) {
+        sp = ms;
+        split.plane_threads = nt;
+      }
+    }
+    if (!rc && sz + sp < best_z + best_p) {
+      best = split;
+      best_z = sz;
+      best_p = sp;
     }
   }
   // sample groups: whole code updates (all iterations) with the chosen kernel shapes
@@ -1982,7 +2056,7 @@ int ocsc_set_tuning(ocsc_ctx* c, const ocsc_tuning* t) {
   if (!c) return OCSC_E_INVALID_ARG;
   if (!t) return fail(c, OCSC_E_INVALID_ARG, "tuning is NULL");
   if (!tuning_valid(c, *t)) return fail(c, OCSC_E_INVALID_ARG, "unsupported launch shape");
-  if (t->two_pass) {
+  if (t->two_pass == 1) {
     const int rc = ensure_column_buffer(c);
     if (rc) return rc;
   }

@@ -17,7 +17,8 @@ Design (host loop over the C calls; every arithmetic step runs in the library):
 * The pending slots per grid (the device state a request occupies until its
   history is folded) are sized so that all contexts fit the HBM budget.
 * Each grid's code-update launch shapes are autotuned at start-up for a full
-  launch (``ocsc_autotune``); every shape gives the same bits.
+  launch (``ocsc_autotune``).  A context keeps its shape for every launch
+  size, so a request's codes do not depend on what it was batched with.
 * ``cholesky=True`` serves in the precision form: each fold adds the pending
   samples to the history on the matrix cores and rebuilds C from FP64
   Cholesky factors, instead of folding sample after sample.
@@ -120,7 +121,7 @@ class Server:
                 m = OCSC(K, filt, filt, n, n, lam, rho, iters_code=iters_code, iters_dict=iters_dict,
                          max_batch=self.slots[n], precision="f32", cholesky=cholesky, device=self.device)
                 m.set_dictionary(D0)
-                if autotune:   # launch shapes for full launches of this grid (same bits for every shape)
+                if autotune:   # launch shapes for full launches of this grid, kept for every launch size
                     m.autotune(min(max_launch[n], self.slots[n]))
             g = _Grid(n, m, st, self.slots[n], max_launch[n])
             g.xbuf = torch.empty((g.max_launch, n, n), dtype=torch.float32, pin_memory=True)
