@@ -244,22 +244,6 @@ __device__ void irfft2_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int t
   rows_c2r_lds<PH, PW, NT, T>(buf, twW, tid);
 }
 
-// The same on PHH = PH/2 rows (one row parity of a PH x PW plane): column
-// DFTs of length PHH, with twH the length-PH table read at stride 2.
-template <int PHH, int PW, int NT, typename T>
-__device__ void rfft2_half_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
-  constexpr int WC = PW / 2 + 1;
-  rows_r2c_lds<PHH, PW, NT, T>(buf, twW, tid);
-  fft_lines<PHH, WC, 1, WC, 2, true, false, NT, T>(buf, twH, tid);
-}
-
-template <int PHH, int PW, int NT, typename T>
-__device__ void irfft2_half_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
-  constexpr int WC = PW / 2 + 1;
-  fft_lines<PHH, WC, 1, WC, 2, true, true, NT, T>(buf, twH, tid);
-  rows_c2r_lds<PHH, PW, NT, T>(buf, twW, tid);
-}
-
 }  // namespace ocsc
 
 #pragma clang fp contract(fast)

@@ -230,6 +230,22 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
 // [e PH/2, (e + 1) PH/2) of the plane's slot of S.  The Z-step forms
 // F(U - W) from E_0 and E_1 (zstep_body with SPLIT).
 // ---------------------------------------------------------------------------
+// 2-D transforms of one row parity of a PH x PW plane (PHH = PH/2 rows):
+// column DFTs of length PHH, with twH the length-PH table read at stride 2.
+template <int PHH, int PW, int NT, typename T>
+__device__ void rfft2_half_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
+  constexpr int WC = PW / 2 + 1;
+  rows_r2c_lds<PHH, PW, NT, T>(buf, twW, tid);
+  fft_lines<PHH, WC, 1, WC, 2, true, false, NT, T>(buf, twH, tid);
+}
+
+template <int PHH, int PW, int NT, typename T>
+__device__ void irfft2_half_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
+  constexpr int WC = PW / 2 + 1;
+  fft_lines<PHH, WC, 1, WC, 2, true, true, NT, T>(buf, twH, tid);
+  rows_c2r_lds<PHH, PW, NT, T>(buf, twW, tid);
+}
+
 template <typename T, int PH, int PW, int NT>
 __device__ __forceinline__ void code_plane_split_body(cx<T>* buf, cx<T>* sH, cx<T>* sW, long q, int e,
                                                       const cx<T>* __restrict__ Zh, T* __restrict__ W,
