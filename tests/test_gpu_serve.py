@@ -1,8 +1,9 @@
 """Serving form: continuous batching over several grid sizes with a shared,
 online-updated dictionary.
 
-* Each request's codes are the same alone and in the mix (bitwise: a sample's
-  arithmetic does not depend on the others in its batch).
+* Each request's codes are the same alone and in the mix, with the same launch
+  shape (bitwise: a sample's arithmetic does not depend on the others in its
+  batch).
 * A served run with dictionary updates, replayed event by event on the FP64
   oracle (same batches, same fold points, same shared updates), agrees within
   the FP32 bound (norm-wise relative 1e-3 per quantity).
@@ -32,8 +33,9 @@ def test_same_alone_and_in_the_mix():
     assert m["requests"] == 60 and m["dictionary_updates"] == 0
     assert any(len(ev[2]) > 1 for ev in srv.log if ev[0] == "code"), "no batching happened"
     alone = {n: OCSC(K, filt, filt, n, n, 0.5, 1.0, precision="f32") for n in grids}
-    for g in alone.values():
+    for n, g in alone.items():
         g.set_dictionary(D0)
+        g.set_tuning(**srv.grids[n].model.tuning)   # the launch shape the server tuned (split planes round differently)
     for r in reqs:
         U = alone[r.grid].code_update(r.image)[0]
         assert torch.equal(U, r.codes), r.rid
