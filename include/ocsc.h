@@ -338,10 +338,10 @@ int ocsc_graph_destroy(ocsc_graph* graph);
  * differently: its shapes agree bit for bit among themselves, and with the
  * others to rounding.
  *   plane_threads: threads per workgroup of the plane kernel, one plane (or
- *                  half a plane, two_pass 2) per workgroup: 256, 512 or
- *                  1024, at most pad_h * pad_w / 4.
- *                  Grids with a side above 128 use fixed two-pass kernels
- *                  and accept only 256.
+ *                  one row residue of a plane, two_pass 2) per workgroup:
+ *                  256, 512 or 1024, at most pad_h * pad_w / 4.  Grids with
+ *                  a side above 128 use fixed two-pass kernels and accept
+ *                  only 256 there (two_pass 1).
  *   zstep_freqs:   frequencies per Z-step workgroup, 16, 32 or 64
  *                  (16 * zstep_freqs threads).
  *   zstep_samples: samples per Z-step workgroup, 1, 2 or 4 (the dictionary
@@ -360,10 +360,12 @@ int ocsc_graph_destroy(ocsc_graph* graph);
  *                  one-pass plane kernel) or 1 (the column and row passes,
  *                  more workgroups for small batches; the first selection
  *                  allocates a max_batch x K spectrum buffer, OCSC_E_OOM);
- *                  0 on other grids.  On every one-pass grid also 2: each
- *                  plane split by row parity over two workgroups (twice the
- *                  workgroups, for batches that leave CUs idle); the last
- *                  radix-2 step of the column DFTs then runs in the Z-step.
+ *                  0 on other grids.  On every grid also 2: each plane
+ *                  split by row residue over F workgroups (F = 2 on grids up
+ *                  to 128, for batches that leave CUs idle; on 256 and 512
+ *                  grids 2 to 16, so that one residue's rows fit in LDS and
+ *                  the plane step is one kernel instead of three); the last
+ *                  radix-F step of the column DFTs then runs in the Z-step.
  * Defaults: plane_threads 1024 for 128 x 128 grids, else 256; 16; 1; 128; 8; 0;
  * 1 on two-pass grids, else 0.
  * ocsc_autotune times whole code updates for the group size.

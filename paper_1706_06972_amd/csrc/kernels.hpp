@@ -216,34 +216,53 @@ __global__ __launch_bounds__(NT) void k_code_plane(const cx<T>* __restrict__ Zh,
 }
 
 // ---------------------------------------------------------------------------
-// The same step with each plane split over two workgroups by row parity
-// (workgroup e = 0, 1 takes rows r = 2m + e), for batches too small to fill
-// the chip with one workgroup per plane.  A column DFT of length PH is one
-// radix-2 step over two DFTs of length PH/2, on the even and the odd rows:
-//   forward  X[h] = E_0[h'] + w^h E_1[h'],  h' = h mod PH/2,  w = e^{-2 pi i/PH};
-//   inverse  rows 2m + e of the inverse column DFT of Y are the inverse DFTs
-//            of length PH/2 of Y[h'] + Y[h' + PH/2] (e = 0) and of
-//            (Y[h'] - Y[h' + PH/2]) conj(w^h') (e = 1).
-// Workgroup e forms its length-PH/2 spectrum from Zh on the way into LDS,
-// runs the half-height transforms, the U-step and the dual on its rows, and
-// writes E_e (the column DFTs of length PH/2 of its rows of U - W) to rows
-// [e PH/2, (e + 1) PH/2) of the plane's slot of S.  The Z-step forms
-// F(U - W) from E_0 and E_1 (zstep_body with SPLIT).
+// The same step with each plane split over F workgroups by row residue
+// (workgroup e = 0 .. F-1 takes rows r = F m + e): for batches too small to
+// fill the chip with one workgroup per plane (F = 2), and for planes too
+// large for one workgroup's LDS (256 and 512 grids: F = 2 to 16, so that a
+// slice of PH/F rows fits).  A column DFT of length PH is one radix-F step
+// over F DFTs of length PH/F on the rows of each residue (decimation in time):
+//   forward  X[h] = sum_e w^{h e} E_e[h mod PH/F],  w = e^{-2 pi i/PH};
+//   inverse  rows F m + e of the inverse column DFT of Y are the inverse
+//            DFTs of length PH/F of
+//            conj(w^{h' e}) sum_j Y[h' + j PH/F] e^{+2 pi i j e/F}.
+// Workgroup e forms its length-PH/F spectrum from Zh on the way into LDS,
+// runs the transforms of its PH/F rows, the U-step and the dual on them, and
+// writes E_e (the column DFTs of length PH/F of its rows of U - W) to rows
+// [e PH/F, (e + 1) PH/F) of the plane's slot of S.  The Z-step forms
+// F(U - W) from E_0 .. E_{F-1} (zstep_body with SPLIT).
 // ---------------------------------------------------------------------------
-// 2-D transforms of one row parity of a PH x PW plane (PHH = PH/2 rows):
-// column DFTs of length PHH, with twH the length-PH table read at stride 2.
-template <int PHH, int PW, int NT, typename T>
-__device__ void rfft2_half_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
-  constexpr int WC = PW / 2 + 1;
-  rows_r2c_lds<PHH, PW, NT, T>(buf, twW, tid);
-  fft_lines<PHH, WC, 1, WC, 2, true, false, NT, T>(buf, twH, tid);
+// Row residues per plane: 2 on one-pass grids, else the fewest whose slice
+// (and the twiddle tables) fits in 150 KB of LDS.
+__host__ __device__ constexpr int split_rows(int real_bytes, int ph, int pw) {
+  int f = 2;
+  if (ph > 128 || pw > 128)
+    while (f < 16 && (long)(ph / f) * (pw / 2 + 1) * 2 * real_bytes + (long)(ph + pw) * 2 * real_bytes > 150 * 1024)
+      f *= 2;
+  return f;
 }
 
-template <int PHH, int PW, int NT, typename T>
-__device__ void irfft2_half_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
+// 2-D transforms of one row residue of a PH x PW plane (PHS = PH/F rows):
+// column DFTs of length PHS, with twH the length-PH table read at stride F.
+template <int PHS, int F, int PW, int NT, typename T>
+__device__ void rfft2_slice_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
   constexpr int WC = PW / 2 + 1;
-  fft_lines<PHH, WC, 1, WC, 2, true, true, NT, T>(buf, twH, tid);
-  rows_c2r_lds<PHH, PW, NT, T>(buf, twW, tid);
+  rows_r2c_lds<PHS, PW, NT, T>(buf, twW, tid);
+  fft_lines<PHS, WC, 1, WC, F, true, false, NT, T>(buf, twH, tid);
+}
+
+template <int PHS, int F, int PW, int NT, typename T>
+__device__ void irfft2_slice_lds(cx<T>* buf, const cx<T>* twH, const cx<T>* twW, int tid) {
+  constexpr int WC = PW / 2 + 1;
+  fft_lines<PHS, WC, 1, WC, F, true, true, NT, T>(buf, twH, tid);
+  rows_c2r_lds<PHS, PW, NT, T>(buf, twW, tid);
+}
+
+// v * e^{+2 pi i k/16}, 0 <= k < 16 (exact for k a multiple of 4)
+template <typename T>
+__device__ __forceinline__ cx<T> rot16_inv(cx<T> v, int k) {
+  const cx<T> r = rot16<true, T>(v, k & 7);
+  return k < 8 ? r : mk<T>(-r.x, -r.y);
 }
 
 template <typename T, int PH, int PW, int NT>
@@ -254,26 +273,34 @@ __device__ __forceinline__ void code_plane_split_body(cx<T>* buf, cx<T>* sH, cx<
                                                       const cx<T>* __restrict__ twW, T kappa, int first,
                                                       int last) {
   using G = PlaneGeom<PH, PW>;
-  constexpr int PHH = PH / 2;
+  constexpr int F = split_rows((int)sizeof(T), PH, PW);
+  constexpr int PHS = PH / F;
   constexpr int VR = 16 / (int)sizeof(T);    // reals per vector
   constexpr int CV = VR / 2;                 // complex values per vector
-  static_assert((PHH * G::WC) % CV == 0, "half spectrum in whole vectors");
-  constexpr int NSV = PHH * G::WC / CV;      // vectors per half spectrum
-  constexpr int NRV = PHH * PW / VR;         // vectors per half plane
+  static_assert((PHS * G::WC) % CV == 0, "slice spectrum in whole vectors");
+  constexpr int NSV = PHS * G::WC / CV;      // vectors per slice spectrum
+  constexpr int NRV = PHS * PW / VR;         // vectors per slice of the real plane
   constexpr int CS = (NSV + NT - 1) / NT, CR = (NRV + NT - 1) / NT;
+  constexpr int U0 = 16 / F > 0 ? 16 / F : 1;
+  constexpr int U = CS < U0 ? CS : U0;       // vectors per thread per round of spectrum loads
+  constexpr int NR = (CS + U - 1) / U;       // rounds
   const int tid = threadIdx.x;
   load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
-  // spectrum rows h' and h' + PH/2 of the plane, and the dual on this workgroup's rows
+  // spectrum rows h' + j PH/F (j < F) of the plane, U vectors per thread at a time
   const v4f* zs = reinterpret_cast<const v4f*>(Zh + q * G::PF);
-  v4f lo[CS], hi[CS];
+  v4f zin[U][F];
+  auto fetch = [&](int r) {
 #pragma unroll
-  for (int j = 0; j < CS; ++j) {
-    const int v = tid + j * NT;
-    if (NSV % NT == 0 || v < NSV) {
-      lo[j] = zs[v];
-      hi[j] = zs[v + NSV];
+    for (int u = 0; u < U; ++u) {
+      const int v = (r * U + u) * NT + tid;
+      if (v < NSV) {
+#pragma unroll
+        for (int j = 0; j < F; ++j) zin[u][j] = zs[v + j * NSV];
+      }
     }
-  }
+  };
+  fetch(0);
+  // the dual on this workgroup's rows
   T* const Wq = W + q * G::P;
   v4f wr[CR];
 #pragma unroll
@@ -281,27 +308,34 @@ __device__ __forceinline__ void code_plane_split_body(cx<T>* buf, cx<T>* sH, cx<
     const int v = tid + j * NT;
     if (NRV % NT == 0 || v < NRV) {
       const int i = v * VR, m = i / PW;
-      wr[j] = first ? v4f{0, 0, 0, 0} : *reinterpret_cast<const v4f*>(Wq + (2 * m + e) * PW + i % PW);
+      wr[j] = first ? v4f{0, 0, 0, 0} : *reinterpret_cast<const v4f*>(Wq + (F * m + e) * PW + i % PW);
     }
   }
   __syncthreads();   // tables
   v4f* d = reinterpret_cast<v4f*>(buf);
+#pragma unroll 1
+  for (int r = 0; r < NR; ++r) {
 #pragma unroll
-  for (int j = 0; j < CS; ++j) {
-    const int v = tid + j * NT;
-    if (NSV % NT == 0 || v < NSV) {
-      const cx<T>* a = reinterpret_cast<const cx<T>*>(&lo[j]);
-      const cx<T>* b = reinterpret_cast<const cx<T>*>(&hi[j]);
-      v4f o;
-      cx<T>* oc = reinterpret_cast<cx<T>*>(&o);
+    for (int u = 0; u < U; ++u) {
+      const int v = (r * U + u) * NT + tid;
+      if (v < NSV) {
+        v4f o;
+        cx<T>* oc = reinterpret_cast<cx<T>*>(&o);
 #pragma unroll
-      for (int c = 0; c < CV; ++c)
-        oc[c] = e == 0 ? cadd<T>(a[c], b[c]) : cmulc<T>(csub<T>(a[c], b[c]), sH[(v * CV + c) / G::WC]);
-      d[v] = o;
+        for (int c = 0; c < CV; ++c) {
+          cx<T> acc = reinterpret_cast<const cx<T>*>(&zin[u][0])[c];
+#pragma unroll
+          for (int j = 1; j < F; ++j)
+            acc = cadd<T>(acc, rot16_inv<T>(reinterpret_cast<const cx<T>*>(&zin[u][j])[c], (j * e * (16 / F)) & 15));
+          oc[c] = e == 0 ? acc : cmulc<T>(acc, sH[(((v * CV + c) / G::WC) * e) % PH]);
+        }
+        d[v] = o;
+      }
     }
+    if (r + 1 < NR) fetch(r + 1);
   }
   __syncthreads();
-  irfft2_half_lds<PHH, PW, NT, T>(buf, sH, sW, tid);
+  irfft2_slice_lds<PHS, F, PW, NT, T>(buf, sH, sW, tid);
   const T scale = (T)1 / (T)G::P;
 #pragma unroll
   for (int j = 0; j < CR; ++j) {
@@ -324,7 +358,7 @@ __device__ __forceinline__ void code_plane_split_body(cx<T>* buf, cx<T>* sH, cx<
         w[2 * h + 1] = v1 - u1;
         o[h] = mk<T>(u0 - w[2 * h], u1 - w[2 * h + 1]);
       }
-      const long off = (long)(2 * m + e) * PW + col;
+      const long off = (long)(F * m + e) * PW + col;
       if (last) {
         if (Uout) *reinterpret_cast<v4f*>(Uout + q * G::P + off) = uo;
       } else {
@@ -334,25 +368,21 @@ __device__ __forceinline__ void code_plane_split_body(cx<T>* buf, cx<T>* sH, cx<
   }
   if (last) return;
   __syncthreads();
-  rfft2_half_lds<PHH, PW, NT, T>(buf, sH, sW, tid);
-  v4f* so = reinterpret_cast<v4f*>(S + q * G::PF + (long)e * PHH * G::WC);
-#pragma unroll
-  for (int j = 0; j < CS; ++j) {
-    const int v = tid + j * NT;
-    if (NSV % NT == 0 || v < NSV) so[v] = d[v];
-  }
+  rfft2_slice_lds<PHS, F, PW, NT, T>(buf, sH, sW, tid);
+  v4f* so = reinterpret_cast<v4f*>(S + q * G::PF + (long)e * PHS * G::WC);
+  for (int v = tid; v < NSV; v += NT) so[v] = d[v];
 }
 
-// Block b of 2 n -> (plane q, parity e).  The two workgroups of a plane are
-// eight blocks apart, so they run on the same XCD and the second read of the
-// plane's spectrum can come from its L2.  A bijection on [0, 2n).
-__device__ __forceinline__ void split_block(int b, int n, int& q, int& e) {
+// Block b of F n -> (plane q, residue e).  The F workgroups of a plane are
+// eight blocks apart, so they run on the same XCD and the repeated reads of
+// the plane's spectrum can come from its L2.  A bijection on [0, F n).
+__device__ __forceinline__ void split_block(int b, int n, int F, int& q, int& e) {
   const int full = n >> 3;
-  if (b < full * 16) {
-    q = (b >> 4) * 8 + (b & 7);
-    e = (b >> 3) & 1;
+  if (b < full * 8 * F) {
+    q = (b / (8 * F)) * 8 + (b & 7);
+    e = (b >> 3) % F;
   } else {
-    const int t = b - full * 16, r = n - full * 8;
+    const int t = b - full * 8 * F, r = n - full * 8;
     q = full * 8 + t % r;
     e = t / r;
   }
@@ -364,10 +394,11 @@ __global__ __launch_bounds__(NT) void k_code_plane_split(const cx<T>* __restrict
                                                          const cx<T>* __restrict__ twH,
                                                          const cx<T>* __restrict__ twW, T kappa, int first,
                                                          int last, int nplanes) {
-  __shared__ __align__(16) cx<T> buf[(PH / 2) * PlaneGeom<PH, PW>::LDW];
+  constexpr int F = split_rows((int)sizeof(T), PH, PW);
+  __shared__ __align__(16) cx<T> buf[(PH / F) * PlaneGeom<PH, PW>::LDW];
   __shared__ cx<T> sH[PH], sW[PW];
   int q, e;
-  split_block((int)blockIdx.x, nplanes, q, e);
+  split_block((int)blockIdx.x, nplanes, F, q, e);
   code_plane_split_body<T, PH, PW, NT>(buf, sH, sW, (long)q, e, Zh, W, S, Uout, twH, twW, kappa, first, last);
 }
 
@@ -384,11 +415,11 @@ __global__ __launch_bounds__(NT) void k_code_plane_split(const cx<T>* __restrict
 // order for every ZF and SB (per thread over j, then over the 16 threads of a
 // frequency in kq order), so every launch shape gives the same bits.
 // first: s = 0.
-// SPLIT: S holds, per plane, the half-height column DFTs E_0 and E_1 of the
-// split plane step (rows [0, PH/2) and [PH/2, PH)), and s = E_0[h'] + w^h
-// E_1[h'] is formed here (twH[h] = w^h = e^{-2 pi i h/PH}, WC stored columns).
-// A workgroup then serves ZF/2 frequencies of the upper half and the ZF/2
-// frequencies PH/2 rows below them, which read the same E values.
+// SPLIT: S holds, per plane, the column DFTs E_0 .. E_{F-1} of the split
+// plane step (rows [e PH/F, (e + 1) PH/F)), and s = sum_e w^{h e} E_e[h']
+// (h' = h mod PH/F) is formed here (twH[i] = e^{-2 pi i i/PH}, WC stored
+// columns).  A workgroup then serves ZF/F frequencies in each of the F row
+// blocks, at the same h' and column, which read the same E values.
 // ---------------------------------------------------------------------------
 // The body serves frequency block bx of sample block by with the LDS
 // reduction buffer red (16 * (ZF + 1) complex).
@@ -397,16 +428,15 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
                                            const T* __restrict__ gam, const cx<T>* __restrict__ xh,
                                            const cx<T>* __restrict__ S, cx<T>* __restrict__ Zh, int K, int Pf,
                                            int B, int first, cx<T>* __restrict__ Zt, int ldt, int bt0,
-                                           const cx<T>* __restrict__ twH = nullptr, int WC = 1) {
+                                           const cx<T>* __restrict__ twH = nullptr, int WC = 1, int F = 1) {
   // Zt (optional): the same values frequency-major, Zt[(p * ldt + bt0 + b) * K + k]
   const int f = threadIdx.x % ZF, kq = threadIdx.x / ZF;
-  constexpr int ZH = ZF / 2;
-  const int half = Pf / 2;
-  const int jh = bx * ZH + f % ZH;   // SPLIT: index within a half spectrum
-  const int p = SPLIT ? jh + (f >= ZH ? half : 0) : bx * ZF + f;
-  const bool ok = SPLIT ? jh < half : p < Pf;
-  cx<T> tw = mk<T>(0, 0);
-  if (SPLIT && ok) tw = twH[p / WC];
+  const int zb = ZF / F;              // SPLIT: frequencies per row block
+  const int part = Pf / F;            // SPLIT: values per E_e
+  const int jh = bx * zb + f % zb;    // SPLIT: index within E_e
+  const int p = SPLIT ? jh + (f / zb) * part : bx * ZF + f;
+  const bool ok = SPLIT ? jh < part : p < Pf;
+  const int ph = Pf / WC, h = p / WC;
   cx<T> a[KPT];
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
@@ -423,7 +453,12 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
       const int k = kq + j * 16;
       if (SPLIT) {
         const cx<T>* e0 = S + ((size_t)b * K + k) * Pf + jh;
-        s[j] = (ok && k < K && !first) ? cadd<T>(e0[0], cmul<T>(e0[half], tw)) : mk<T>(0, 0);
+        cx<T> v = mk<T>(0, 0);
+        if (ok && k < K && !first) {
+          v = e0[0];
+          for (int r = 1; r < F; ++r) v = cadd<T>(v, cmul<T>(e0[(size_t)r * part], twH[(h * r) % ph]));
+        }
+        s[j] = v;
       } else {
         s[j] = (ok && k < K && !first) ? S[((size_t)b * K + k) * Pf + p] : mk<T>(0, 0);
       }
@@ -461,10 +496,10 @@ __global__ __launch_bounds__(16 * ZF) void k_code_zstep(const cx<T>* __restrict_
                                                         const cx<T>* __restrict__ S,
                                                         cx<T>* __restrict__ Zh, int K, int Pf, int B,
                                                         int first, cx<T>* __restrict__ Zt, int ldt, int bt0,
-                                                        const cx<T>* __restrict__ twH, int WC) {
+                                                        const cx<T>* __restrict__ twH, int WC, int F) {
   __shared__ cx<T> red[16][ZF + 1];
   zstep_body<T, KPT, ZF, SB, SPLIT>(red, blockIdx.x, blockIdx.y, Dh, gam, xh, S, Zh, K, Pf, B, first, Zt, ldt,
-                                    bt0, twH, WC);
+                                    bt0, twH, WC, F);
 }
 
 // gam_p = 1 / (rho + sum_k |Dh[k][p]|^2): 64 frequencies per workgroup, the

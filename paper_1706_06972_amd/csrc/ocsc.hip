@@ -384,7 +384,8 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
 #define OCSC_SPLIT_NT(A, B, NT)                                                                          \
   if constexpr (plane_nt_ok(A, B, NT)) {                                                                 \
     if (nt == NT) {                                                                                      \
-      hipLaunchKernelGGL((k_code_plane_split<T, A, B, NT>), dim3(2 * nplanes), dim3(NT), 0, c->stream,   \
+      hipLaunchKernelGGL((k_code_plane_split<T, A, B, NT>), dim3(split_rows((int)sizeof(T), A, B) * nplanes), \
+                         dim3(NT), 0, c->stream,                                                         \
                          (const cx<T>*)Zh, W, S, Uout, tH, tW, kappa, first, last, nplanes);             \
       done = true;                                                                                       \
     }                                                                                                    \
@@ -396,6 +397,7 @@ int launch_code_plane(ocsc_ctx* c, int off, int nplanes, T* Uout, int first, int
     OCSC_SPLIT_NT(A, B, 1024) \
     break;
       OCSC_SIZE_CASES(X)
+      OCSC_BIG_CASES(X)
 #undef X
 #undef OCSC_SPLIT_NT
       default:
@@ -457,17 +459,18 @@ void zstep_kernel(ocsc_ctx* c, int off, int B, int first, cx<T>* Zt) {
   const cx<T>* S = (const cx<T>*)c->S + (size_t)off * c->K * c->Pf;
   cx<T>* Zh = (cx<T>*)c->Zh + (size_t)off * c->K * c->Pf;
   if (c->tune.two_pass == 2) {
-    // S holds the half-height column DFTs of the split plane step
-    const dim3 grid((c->Pf / 2 + ZF / 2 - 1) / (ZF / 2), (B + SB - 1) / SB);
+    // S holds the column DFTs of the row residues of the split plane step
+    const int F = split_rows(c->sr, c->Ph, c->Pw), zb = ZF / F;
+    const dim3 grid((c->Pf / F + zb - 1) / zb, (B + SB - 1) / SB);
     hipLaunchKernelGGL((k_code_zstep<T, KPT, ZF, SB, true>), grid, dim3(16 * ZF), 0, c->stream,
                        (const cx<T>*)c->Dh, (const T*)c->gam, xh, S, Zh, c->K, c->Pf, B, first, Zt, c->maxB, off,
-                       (const cx<T>*)c->twH, c->Wc);
+                       (const cx<T>*)c->twH, c->Wc, F);
     return;
   }
   const dim3 grid((c->Pf + ZF - 1) / ZF, (B + SB - 1) / SB);
   hipLaunchKernelGGL((k_code_zstep<T, KPT, ZF, SB, false>), grid, dim3(16 * ZF), 0, c->stream, (const cx<T>*)c->Dh,
                      (const T*)c->gam, xh, S, Zh, c->K, c->Pf, B, first, Zt, c->maxB, off, (const cx<T>*)nullptr,
-                     c->Wc);
+                     c->Wc, 1);
 }
 
 template <typename T, int KPT>
@@ -1790,7 +1793,7 @@ int ocsc_diagnostics(ocsc_ctx* c, double* out) {
 namespace {
 
 bool tuning_valid(const ocsc_ctx* c, const ocsc_tuning& t) {
-  const bool pt = c->big ? t.plane_threads == 256 : plane_nt_ok(c->Ph, c->Pw, t.plane_threads);
+  const bool pt = (c->big && t.two_pass != 2) ? t.plane_threads == 256 : plane_nt_ok(c->Ph, c->Pw, t.plane_threads);
   const bool zf = t.zstep_freqs == 16 || t.zstep_freqs == 32 || t.zstep_freqs == 64;
   const bool sb = t.zstep_samples == 1 || t.zstep_samples == 2 || t.zstep_samples == 4;
   const bool cb = (t.col_bytes == 128 || t.col_bytes == 256 || t.col_bytes == 512) &&
@@ -1798,7 +1801,7 @@ bool tuning_valid(const ocsc_ctx* c, const ocsc_tuning& t) {
   const bool rb = t.row_block == 4 || t.row_block == 8 || t.row_block == 16;
   const bool ch = t.chunk_samples == 0 || t.chunk_samples == 1 || t.chunk_samples == 2 || t.chunk_samples == 4 ||
                   t.chunk_samples == 8 || t.chunk_samples == 16;
-  const bool tp = c->big ? t.two_pass == 1
+  const bool tp = c->big ? (t.two_pass == 1 || t.two_pass == 2)
                          : (t.two_pass == 0 || t.two_pass == 2 || (t.two_pass == 1 && two_pass_capable(c->Ph, c->Pw)));
   return pt && zf && sb && cb && rb && ch && tp;
 }
@@ -1883,7 +1886,7 @@ int autotune_t(ocsc_ctx* c, int B, double* best_ms) {
   };
   tune_zstep(c->big ? 1 : 0, best, best_z);
   c->tune = start;
-  if (c->tune.two_pass == 2) c->tune.two_pass = 0;
+  if (c->tune.two_pass == 2) c->tune.two_pass = c->big ? 1 : 0;
   // plane step: workgroup size of the one-pass kernel, or column block x row
   // block of the two-pass kernels (two-pass grids, and 64 x 64 / 128 x 128
   // grids as an alternative)
@@ -1895,7 +1898,7 @@ int autotune_t(ocsc_ctx* c, int B, double* best_ms) {
           if (rc) break;
           // a one-pass shape varies the workgroup size only, a two-pass one the blocks only
           if (tp == 0 && (cby != start.col_bytes || rb != start.row_block)) continue;
-          if (tp == 1 && nt != start.plane_threads) continue;
+          if (tp == 1 && nt != 256) continue;
           c->tune.two_pass = tp;
           c->tune.plane_threads = nt;
           c->tune.col_bytes = cby;
@@ -1915,9 +1918,9 @@ int autotune_t(ocsc_ctx* c, int B, double* best_ms) {
       }
     }
   }
-  // split planes (one-pass grids), with the Z-step tile chosen for them: kept
-  // if the Z-step and plane step together beat the unsplit pair
-  if (!c->big && !rc) {
+  // split planes, with the Z-step tile chosen for them: kept if the Z-step
+  // and plane step together beat the unsplit pair
+  if (!rc) {
     ocsc_tuning split = best;
     split.two_pass = 2;
     double sz = 1e30, sp = 1e30;

@@ -1,13 +1,15 @@
 """The split plane step (launch shape two_pass = 2) against the FP64 oracle,
 through the C ABI.
 
-With two_pass = 2 each plane of the code update runs on two workgroups, one
-per row parity, and the last radix-2 step of its column DFTs runs in the
-Z-step (eq. fcsc_code: the U-step and the dual on the rows of one parity; the
-spectrum of U - W formed from the two half-height column DFTs).  Whole
+With two_pass = 2 each plane of the code update runs on F workgroups, one
+per row residue (F = 2 on grids up to 128; 2 to 16 on 256 and 512 grids, so
+that a residue's rows fit in LDS), and the last radix-F step of its column
+DFTs runs in the Z-step (eq. fcsc_code: the U-step and the dual on the rows
+of one residue; the spectrum of U - W formed from the F column DFTs).  Whole
 learning steps (code update, history, DictOCSC) are compared with the oracle
 per quantity at the suite's tolerances (norm-wise 1e-10 FP64, 1e-3 FP32):
-one-pass grids of every height, single samples and a ragged minibatch, and
+grids of every height up to 512 (F = 2, 4, 8 and 16), single samples and
+ragged minibatches, and
 the 128x128, K = 100 FP32 workload at B = 1.
 """
 import numpy as np
@@ -37,6 +39,12 @@ def images(n, ph, pw, seed):
     ("f64", 128, 128, 7, (1, 1), 1024),
     ("f32", 32, 64, 9, (2, 1), 256),
     ("f32", 128, 128, 12, (1, 3), 512),
+    ("f32", 256, 256, 4, (1, 2), 512),
+    ("f64", 256, 256, 3, (1, 1), 512),
+    ("f32", 256, 512, 2, (2, 1), 1024),
+    ("f64", 512, 256, 2, (1, 1), 512),
+    ("f32", 512, 512, 3, (1, 1), 512),
+    ("f64", 512, 512, 2, (1, 1), 1024),
 ])
 def test_split_planes_match_oracle(prec, ph, pw, K, batches, nt):
     say(f"case split planes {prec} {ph}x{pw} K={K} batches={batches} threads={nt}")
