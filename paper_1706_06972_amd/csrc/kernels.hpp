@@ -498,8 +498,11 @@ __global__ __launch_bounds__(16 * ZF) void k_code_zstep(const cx<T>* __restrict_
                                                         int first, cx<T>* __restrict__ Zt, int ldt, int bt0,
                                                         const cx<T>* __restrict__ twH, int WC, int F) {
   __shared__ cx<T> red[16][ZF + 1];
-  zstep_body<T, KPT, ZF, SB, SPLIT>(red, blockIdx.x, blockIdx.y, Dh, gam, xh, S, Zh, K, Pf, B, first, Zt, ldt,
-                                    bt0, twH, WC, F);
+  // SPLIT: a block's runs in each E_e can be shorter than a cache line, so
+  // neighbouring blocks go to the same XCD and share its L2
+  const int bx = SPLIT ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  zstep_body<T, KPT, ZF, SB, SPLIT>(red, bx, blockIdx.y, Dh, gam, xh, S, Zh, K, Pf, B, first, Zt, ldt, bt0, twH,
+                                    WC, F);
 }
 
 // gam_p = 1 / (rho + sum_k |Dh[k][p]|^2): 64 frequencies per workgroup, the
