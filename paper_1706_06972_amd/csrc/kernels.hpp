@@ -437,6 +437,7 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
   const int p = SPLIT ? jh + (f / zb) * part : bx * ZF + f;
   const bool ok = SPLIT ? jh < part : p < Pf;
   const int ph = Pf / WC, h = p / WC;
+  const cx<T> tw1 = (SPLIT && ok) ? twH[h] : mk<T>(0, 0);   // w^h
   cx<T> a[KPT];
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
@@ -455,8 +456,12 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
         const cx<T>* e0 = S + ((size_t)b * K + k) * Pf + jh;
         cx<T> v = mk<T>(0, 0);
         if (ok && k < K && !first) {
-          v = e0[0];
-          for (int r = 1; r < F; ++r) v = cadd<T>(v, cmul<T>(e0[(size_t)r * part], twH[(h * r) % ph]));
+          v = cadd<T>(e0[0], cmul<T>(e0[part], tw1));
+          for (int r = 2, i = h; r < F; ++r) {   // i = h r mod PH
+            i += h;
+            if (i >= ph) i -= ph;
+            v = cadd<T>(v, cmul<T>(e0[(size_t)r * part], twH[i]));
+          }
         }
         s[j] = v;
       } else {
