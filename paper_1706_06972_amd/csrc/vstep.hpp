@@ -364,6 +364,8 @@ __global__ __launch_bounds__(1024) void k_vstep_mfma(const float2* __restrict__ 
   using Gm = VGeo<PH, PW>;
   constexpr int WC = Gm::WC, PF = Gm::PF, NVT = Gm::NVT, WPT = Gm::WPT, SPW = Gm::SPW, TPW = Gm::TPW;
   constexpr int NT = 1024;
+  static_assert(PH <= NT && PW <= NT, "one twiddle of each table per thread");
+  static_assert(WPT * NVT >= 8, "part holds the 16 partial alpha products");
   constexpr int FPT = (PF + NT - 1) / NT;
   constexpr int NYQ = PW / 2;
   __shared__ __align__(16) float2 xs[PF];               // X[u][v]
@@ -377,17 +379,11 @@ __global__ __launch_bounds__(1024) void k_vstep_mfma(const float2* __restrict__ 
   const int li = lane & 15, lk = lane >> 4;
   const size_t base = (size_t)k * PF;
 
-  // G for this wave's output tiles and the Nyquist column, fetched now, used at the end
-  float2 gq[TPW][4];
-#pragma unroll
-  for (int tt = 0; tt < TPW; ++tt) {
-    const int tile = min(wave + 16 * tt, Gm::NTILE - 1);
-    const int ut = tile / NVT, vt = tile - ut * NVT;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) gq[tt][j] = G[base + (size_t)(ut * 16 + 4 * lk + j) * WC + vt * 16 + li];
-  }
-  const float2 gny = G[base + (size_t)min(tid, PH - 1) * WC + NYQ];
+  // X = d + Theta first; then G for this wave's output tiles and the Nyquist
+  // column, which is used at the end and arrives during the products
+  float2 gq[TPW][4], gny;
   {
+    const float2 th = twH[min(tid, PH - 1)], tw = twW[min(tid, PW - 1)];
     float2 dq[FPT], tq[FPT];
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
@@ -395,8 +391,16 @@ __global__ __launch_bounds__(1024) void k_vstep_mfma(const float2* __restrict__ 
       dq[j] = d[base + e];
       tq[j] = first ? make_float2(0.f, 0.f) : Th[base + e];
     }
-    for (int i = tid; i < PH; i += NT) sH[i] = twH[i];
-    for (int i = tid; i < PW; i += NT) sW[i] = twW[i];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+      const int tile = min(wave + 16 * tt, Gm::NTILE - 1);
+      const int ut = tile / NVT, vt = tile - ut * NVT;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gq[tt][j] = G[base + (size_t)(ut * 16 + 4 * lk + j) * WC + vt * 16 + li];
+    }
+    gny = G[base + (size_t)min(tid, PH - 1) * WC + NYQ];
+    if (tid < PH) sH[tid] = th;
+    if (tid < PW) sW[tid] = tw;
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
       const int e = tid + j * NT;
@@ -454,27 +458,41 @@ __global__ __launch_bounds__(1024) void k_vstep_mfma(const float2* __restrict__ 
   }
   __syncthreads();
 
-  // ---- alpha: eight lanes per tap, each over every eighth column
+  // ---- alpha on the matrix cores, as the real product (16 x 2 WC)(2 WC x 16):
+  //   A[m][2v + c] = (Re, Im)[c] t[m][v],  B[2v + c][n] = c_v (Re, Im)[c] e^{-2 pi i v n / PW}
+  // (c_v = 1 at v = 0 and v = PW/2, else 2; the sum is Re(t conj(w)) over v).  Its k-steps
+  // are dealt out to the 16 waves; their partial 16 x 16 products are added in wave order.
+  {
+    constexpr int KSA = (2 * WC + 3) / 4;
+    v4f acc = {0, 0, 0, 0};
+    for (int s = wave; s < KSA; s += 16) {
+      const int kk = 4 * s + lk, v = kk >> 1;
+      float a = 0.f, b = 0.f;
+      if (v < WC) {
+        const float2 tv = ts[li * WC + v];
+        const float2 w = sW[(v * li) & (PW - 1)];
+        const float cv = (v == 0 || 2 * v == PW) ? 1.f : 2.f;
+        a = (kk & 1) ? tv.y : tv.x;
+        b = cv * ((kk & 1) ? w.y : w.x);
+      }
+      acc = mfma4(a, b, acc);
+    }
+    float* pa = reinterpret_cast<float*>(part) + wave * 256;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) pa[(4 * lk + j) * 16 + li] = acc[j];   // D[4 lk + j][li]
+  }
+  __syncthreads();
   const float invP = 1.f / (float)(PH * PW);
   float ss = 0.f;
-  for (int task = tid; task < 8 * Mh * Mw; task += NT) {
-    const int o = task >> 3, c = task & 7;
+  for (int o = tid; o < Mh * Mw; o += NT) {
     const int m = o / Mw, n = o - m * Mw;
+    const float* pa = reinterpret_cast<const float*>(part) + m * 16 + n;
     float acc = 0.f;
-    for (int v = c; v < WC; v += 8) {
-      const float2 tv = ts[m * WC + v];
-      const float2 w = sW[(v * n) & (PW - 1)];
-      const float cv = (v == 0 || 2 * v == PW) ? 1.f : 2.f;
-      acc += cv * (tv.x * w.x + tv.y * w.y);   // Re(t * conj(w))
-    }
-    acc += __shfl_xor(acc, 4, 64);
-    acc += __shfl_xor(acc, 2, 64);
-    acc += __shfl_xor(acc, 1, 64);
+#pragma unroll
+    for (int w = 0; w < 16; ++w) acc += pa[w * 256];
     acc *= invP;
-    if (c == 0) {
-      al[o] = acc;
-      ss += acc * acc;
-    }
+    al[o] = acc;
+    ss += acc * acc;
   }
   for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
   if (lane == 0) red[wave] = ss;
