@@ -412,20 +412,21 @@ __global__ __launch_bounds__(1024) void k_vstep_mfma(const float2* __restrict__ 
   // ---- t = W X on the matrix cores: wave -> (column tile vt, slice of u)
   if (wave < WPT * NVT) {
     const int vt = wave / WPT, sl = wave - vt * WPT;
-    v4f dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+    // three real products per complex one: p1 = Re W Re X, p2 = Im W Im X,
+    // p3 = (Re W + Im W)(Re X + Im X); Re t = p1 - p2, Im t = p3 - p1 - p2
+    v4f p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll 4
     for (int s = 0; s < SPW; ++s) {
       const int u = (sl * SPW + s) * 4 + lk;
       const float2 w = sH[(u * li) & (PH - 1)];         // e^{-2 pi i u m/PH}, m = li; W is its conjugate
       const float2 x = xs[u * WC + vt * 16 + li];
-      dr = mfma4(w.x, x.x, dr);                          // Re W Re X
-      dr = mfma4(w.y, x.y, dr);                          // - Im W Im X, Im W = -w.y
-      di = mfma4(w.x, x.y, di);                          // Re W Im X
-      di = mfma4(-w.y, x.x, di);                         // Im W Re X
+      p1 = mfma4(w.x, x.x, p1);
+      p2 = mfma4(-w.y, x.y, p2);                         // Im W = -w.y
+      p3 = mfma4(w.x - w.y, x.x + x.y, p3);
     }
     float2* pp = part + (size_t)wave * 256;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) pp[(4 * lk + j) * 16 + li] = make_float2(dr[j], di[j]);
+    for (int j = 0; j < 4; ++j) pp[(4 * lk + j) * 16 + li] = make_float2(p1[j] - p2[j], p3[j] - p1[j] - p2[j]);
   }
   // Nyquist column of t on the VALU: wave m sums over u
   if (wave < 16) {
@@ -531,25 +532,26 @@ __global__ __launch_bounds__(1024) void k_vstep_mfma(const float2* __restrict__ 
     if (tile < Gm::NTILE) {
       const int ut = tile / NVT, vt = tile - ut * NVT;
       const int u = ut * 16 + li;
-      v4f fr = {0, 0, 0, 0}, fi = {0, 0, 0, 0};
+      // three real products per complex one, as for t
+      v4f p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int m = s * 4 + lk;
         const float2 w = sH[(u * m) & (PH - 1)];         // W'[u][m]
         const float2 x = ts[m * WC + vt * 16 + li];     // r[m][v]
-        fr = mfma4(w.x, x.x, fr);
-        fr = mfma4(-w.y, x.y, fr);
-        fi = mfma4(w.x, x.y, fi);
-        fi = mfma4(w.y, x.x, fi);
+        p1 = mfma4(w.x, x.x, p1);
+        p2 = mfma4(w.y, x.y, p2);
+        p3 = mfma4(w.x + w.y, x.x + x.y, p3);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int uo = ut * 16 + 4 * lk + j, v = vt * 16 + li;
         const int e = uo * WC + v;
+        const float fr = p1[j] - p2[j], fi = p3[j] - p1[j] - p2[j];
         const float2 xv = xs[e];
-        const float2 th = make_float2(xv.x - fr[j], xv.y - fi[j]);
+        const float2 th = make_float2(xv.x - fr, xv.y - fi);
         Th[base + e] = th;
-        rhs[base + e] = make_float2(gq[tt][j].x + rho_d * (fr[j] - th.x), gq[tt][j].y + rho_d * (fi[j] - th.y));
+        rhs[base + e] = make_float2(gq[tt][j].x + rho_d * (fr - th.x), gq[tt][j].y + rho_d * (fi - th.y));
       }
     }
   }
