@@ -18,7 +18,7 @@
 //   3. C_p is written back.
 // The products run on v_mfma_f32_16x16x4_f32 (operand A[i][kk] in lane
 // i + 16 kk, B[kk][j] in lane j + 16 kk, result D[i][j] in lane j + 16 (i / 4),
-// register i % 4), four real products per complex one.  U, Y and W are held
+// register i % 4), three real products per complex one.  U, Y and W are held
 // sample-major, [16][K rounded up to 16, plus 1], so that the 16 rows or
 // samples one operand load touches fall in different banks.
 #pragma once
@@ -54,13 +54,19 @@ __device__ __forceinline__ void fm_centry(const float* R, int ld, int K, int r, 
   ci = (!ok || r == c) ? 0.f : (up ? b : -b);
 }
 
-// acc += (ar + i ai)(br + i bi) on the matrix cores (four real products)
-__device__ __forceinline__ void fm_cmac(v4f& re, v4f& im, float ar, float ai, float br, float bi) {
-  re = fm_mfma(ar, br, re);
-  re = fm_mfma(-ai, bi, re);
-  im = fm_mfma(ar, bi, im);
-  im = fm_mfma(ai, br, im);
+// A complex product accumulated as three real ones: p1 += ar br, p2 += ai bi,
+// p3 += (ar + ai)(br + bi); then Re = p1 - p2, Im = p3 - p1 - p2.
+struct FmAcc {
+  v4f p1, p2, p3;
+};
+__device__ __forceinline__ FmAcc fm_zero() { return FmAcc{{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}}; }
+__device__ __forceinline__ void fm_cmac(FmAcc& a, float ar, float ai, float br, float bi) {
+  a.p1 = fm_mfma(ar, br, a.p1);
+  a.p2 = fm_mfma(ai, bi, a.p2);
+  a.p3 = fm_mfma(ar + ai, br + bi, a.p3);
 }
+__device__ __forceinline__ float fm_re(const FmAcc& a, int e) { return a.p1[e] - a.p2[e]; }
+__device__ __forceinline__ float fm_im(const FmAcc& a, int e) { return a.p3[e] - a.p1[e] - a.p2[e]; }
 
 // One frequency per workgroup (blockIdx.x = p).  Cm: R-forms of pitch fs;
 // G, rfold (optional): complex [K][Pf]; Zt[(p * ldt + b) * K + k]: the code
@@ -154,9 +160,9 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
     if (b0 + FM_B < nfold) fetch(b0 + FM_B);   // in flight during this block
     // Y = C U: the wave's row tiles I = wave, wave + 4, ... in one k loop
     {
-      v4f yr[TPW], yi[TPW];
+      FmAcc ya[TPW];
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) yr[t] = yi[t] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < TPW; ++t) ya[t] = fm_zero();
 #pragma unroll 2
       for (int ks = 0; ks < KP / 4; ++ks) {
         const int c = ks * 4 + lk;
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
           if (I < NB) {
             float cr, ci;
             fm_centry(R, ld, K, I * 16 + li, c, cr, ci);           // A[i][kk] = C[I*16+i][c]
-            fm_cmac(yr[t], yi[t], cr, ci, ur, ui);
+            fm_cmac(ya[t], cr, ci, ur, ui);
           }
         }
       }
@@ -177,8 +183,8 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
         if (I < NB) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {   // D[i][j]: row I * 16 + 4 lk + e, sample li
-            Yr[li * KPP + I * 16 + 4 * lk + e] = yr[t][e];
-            Yi[li * KPP + I * 16 + 4 * lk + e] = yi[t][e];
+            Yr[li * KPP + I * 16 + 4 * lk + e] = fm_re(ya[t], e);
+            Yi[li * KPP + I * 16 + 4 * lk + e] = fm_im(ya[t], e);
           }
         }
       }
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
     __syncthreads();
     // partial M_w = sum over the wave's row tiles of U_I^H Y_I
     {
-      v4f mr = {0.f, 0.f, 0.f, 0.f}, mi = {0.f, 0.f, 0.f, 0.f};
+      FmAcc ma = fm_zero();
 #pragma unroll
       for (int t = 0; t < TPW; ++t) {
         const int I = wave + 4 * t;
@@ -194,14 +200,14 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
             const int c = I * 16 + ks * 4 + lk;
-            fm_cmac(mr, mi, Ur[li * KPP + c], -Ui[li * KPP + c], Yr[li * KPP + c], Yi[li * KPP + c]);
+            fm_cmac(ma, Ur[li * KPP + c], -Ui[li * KPP + c], Yr[li * KPP + c], Yi[li * KPP + c]);
           }
         }
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {   // M[a][b]: a = 4 lk + e, b = li
-        Mp[(wave * 2) * 256 + (4 * lk + e) * 16 + li] = mr[e];
-        Mp[(wave * 2 + 1) * 256 + (4 * lk + e) * 16 + li] = mi[e];
+        Mp[(wave * 2) * 256 + (4 * lk + e) * 16 + li] = fm_re(ma, e);
+        Mp[(wave * 2 + 1) * 256 + (4 * lk + e) * 16 + li] = fm_im(ma, e);
       }
     }
     __syncthreads();
@@ -262,9 +268,9 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
     __syncthreads();   // S^-1 in (Sr, Si)
     // W = Y S^-1 into U's place
     {
-      v4f wr[TPW], wi[TPW];
+      FmAcc wa[TPW];
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) wr[t] = wi[t] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < TPW; ++t) wa[t] = fm_zero();
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int q = ks * 4 + lk;
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
 #pragma unroll
         for (int t = 0; t < TPW; ++t) {
           const int I = wave + 4 * t;
-          if (I < NB) fm_cmac(wr[t], wi[t], Yr[q * KPP + I * 16 + li], Yi[q * KPP + I * 16 + li], br, bi);
+          if (I < NB) fm_cmac(wa[t], Yr[q * KPP + I * 16 + li], Yi[q * KPP + I * 16 + li], br, bi);
         }
       }
 #pragma unroll
@@ -281,8 +287,8 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
         if (I < NB) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            Ur[li * KPP + I * 16 + 4 * lk + e] = wr[t][e];
-            Ui[li * KPP + I * 16 + 4 * lk + e] = wi[t][e];
+            Ur[li * KPP + I * 16 + 4 * lk + e] = fm_re(wa[t], e);
+            Ui[li * KPP + I * 16 + 4 * lk + e] = fm_im(wa[t], e);
           }
         }
       }
@@ -302,16 +308,16 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
         tj[h] = I + tt;
       }
       const bool two = t0 + 4 < NTI;
-      v4f pr[2], pim[2];
+      FmAcc pa[2];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) pr[h] = pim[h] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int h = 0; h < 2; ++h) pa[h] = fm_zero();
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int q = ks * 4 + lk;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           if (h == 0 || two)   // A[i][kk] = W[I*16+i][q], B[kk][j] = conj(Y[J*16+j][q])
-            fm_cmac(pr[h], pim[h], Ur[q * KPP + ti[h] * 16 + li], Ui[q * KPP + ti[h] * 16 + li],
+            fm_cmac(pa[h], Ur[q * KPP + ti[h] * 16 + li], Ui[q * KPP + ti[h] * 16 + li],
                     Yr[q * KPP + tj[h] * 16 + li], -Yi[q * KPP + tj[h] * 16 + li]);
         }
       }
@@ -323,10 +329,10 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
           const int r = ti[h] * 16 + 4 * lk + e, c = tj[h] * 16 + li;
           if (r < K && c < K) {
             if (r < c) {
-              R[r * ld + c] -= pr[h][e];    // Re C_rc
-              R[c * ld + r] -= pim[h][e];   // Im C_rc
+              R[r * ld + c] -= fm_re(pa[h], e);    // Re C_rc
+              R[c * ld + r] -= fm_im(pa[h], e);    // Im C_rc
             } else if (r == c) {
-              R[r * ld + r] -= pr[h][e];
+              R[r * ld + r] -= fm_re(pa[h], e);
             }
           }
         }
