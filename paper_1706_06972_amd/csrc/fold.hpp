@@ -213,56 +213,65 @@ __global__ __launch_bounds__(FM_NT, 2) void k_fold_mfma(float* __restrict__ Cm, 
     __syncthreads();
     if (wave == 0) {
       // S = I + sum of the partials (fixed order), then S^-1 by Gauss-Jordan
-      // elimination on this wave alone: lane j < 16 holds column j of S in
-      // registers; step k reads the pivot column from lane k (readlane, the
-      // same value for the whole wave) and its own element of the pivot row
-      float cr[16], ci[16];
-      const int j = li;   // lanes 16..63 repeat lanes 0..15
+      // elimination on this wave alone: lane j + 16 g holds rows 4g .. 4g+3 of
+      // column j of S in registers; in step k each lane takes its rows of the
+      // pivot column from lane k + 16 g and its element of the pivot row,
+      // a_kj, from lane j + 16 (k / 4) by lane shuffles, a_kk by readlane
+      const int j = li, g = lk;
+      float cr[4], ci[4];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int idx = i * 16 + j;
+      for (int a = 0; a < 4; ++a) {
+        const int i = 4 * g + a, idx = i * 16 + j;
         float sr = i == j ? 1.f : 0.f, si = 0.f;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
           sr += Mp[(w * 2) * 256 + idx];
           si += Mp[(w * 2 + 1) * 256 + idx];
         }
-        cr[i] = sr;
-        ci[i] = si;
+        cr[a] = sr;
+        ci[a] = si;
       }
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        float pr[16], pim[16];   // column k of the current matrix (from lane k)
+        const int kg = k >> 2, ka = k & 3;
+        // this lane's element in row slot ka (row 4 g + ka)
+        const float skr = ka == 0 ? cr[0] : ka == 1 ? cr[1] : ka == 2 ? cr[2] : cr[3];
+        const float ski = ka == 0 ? ci[0] : ka == 1 ? ci[1] : ka == 2 ? ci[2] : ci[3];
+        // a_kj of this lane's column, from the lane holding row k of it
+        const float akr = __shfl(skr, j + 16 * kg, 64), aki = __shfl(ski, j + 16 * kg, 64);
+        // a_kk, and this lane's rows of column k (from lane k + 16 g)
+        const float pkr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(skr), k + 16 * kg));
+        const float pki = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ski), k + 16 * kg));
+        float qr4[4], qi4[4];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          pr[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cr[i]), k));
-          pim[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ci[i]), k));
+        for (int a = 0; a < 4; ++a) {
+          qr4[a] = __shfl(cr[a], k + 16 * g, 64);
+          qi4[a] = __shfl(ci[a], k + 16 * g, 64);
         }
-        const float den = pr[k] * pr[k] + pim[k] * pim[k];
-        const float ivr = pr[k] / den, ivi = -pim[k] / den;   // 1 / a_kk
-        // a_kj / a_kk (this lane's element of the pivot row)
-        const float tr = cr[k] * ivr - ci[k] * ivi, ti = cr[k] * ivi + ci[k] * ivr;
+        const float den = pkr * pkr + pki * pki;
+        const float ivr = pkr / den, ivi = -pki / den;   // 1 / a_kk
+        const float tr = akr * ivr - aki * ivi, ti = akr * ivi + aki * ivr;   // a_kj / a_kk
         const bool pivcol = j == k;
+        const float fr = pivcol ? ivr : tr, fi = pivcol ? ivi : ti;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int a = 0; a < 4; ++a) {
+          const int i = 4 * g + a;
+          const float qpr = qr4[a], qpi = qi4[a];   // a_ik
           if (i == k) {
-            cr[i] = pivcol ? ivr : tr;
-            ci[i] = pivcol ? ivi : ti;
+            cr[a] = fr;
+            ci[a] = fi;
           } else {
             // column k: -a_ik / a_kk;  elsewhere: a_ij - a_ik a_kj / a_kk
-            const float fr = pivcol ? ivr : tr, fi = pivcol ? ivi : ti;
-            const float qr = pr[i] * fr - pim[i] * fi, qi = pr[i] * fi + pim[i] * fr;
-            cr[i] = pivcol ? -qr : cr[i] - qr;
-            ci[i] = pivcol ? -qi : ci[i] - qi;
+            const float qr = qpr * fr - qpi * fi, qi = qpr * fi + qpi * fr;
+            cr[a] = pivcol ? -qr : cr[a] - qr;
+            ci[a] = pivcol ? -qi : ci[a] - qi;
           }
         }
       }
-      if (lane < 16) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          Sr[i * 16 + j] = cr[i];
-          Si[i * 16 + j] = ci[i];
-        }
+      for (int a = 0; a < 4; ++a) {
+        Sr[(4 * g + a) * 16 + j] = cr[a];
+        Si[(4 * g + a) * 16 + j] = ci[a];
       }
     }
     __syncthreads();   // S^-1 in (Sr, Si)
