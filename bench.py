@@ -474,6 +474,9 @@ def main():
                     help="also run the serving form (0: skip; 2: only the configured 100,000-request mix runs)")
     ap.add_argument("--quality", type=int, default=1,
                     help="also measure test objective / PSNR before and after learning (0: skip)")
+    ap.add_argument("--launch-shape", type=str, default="", metavar="JSON",
+                    help="launch shape of the B=1 step, e.g. '{\"two_pass\": 2}', instead of the autotuner's "
+                         "(reproducible hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (hardware-counter calibration) and exit")
     args = ap.parse_args()
@@ -504,7 +507,11 @@ def main():
                iters_dict=wl.iters_dict, max_batch=1, precision="f32", device=dev)
     g.set_dictionary(synth.initial_dictionary(wl.K, wl.filt_h, wl.filt_w, wl.seed))
     # launch shapes of the code update for single samples (bitwise the same results for every shape)
-    tuned, _ = g.autotune(1)
+    if args.launch_shape:
+        g.set_tuning(**json.loads(args.launch_shape))
+        tuned = dict(g.tuning)
+    else:
+        tuned, _ = g.autotune(1)
 
     def step(i):
         x = xs[i % n_img:i % n_img + 1]
