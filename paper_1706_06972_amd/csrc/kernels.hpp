@@ -438,6 +438,10 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
   const bool ok = SPLIT ? jh < part : p < Pf;
   const int ph = Pf / WC, h = p / WC;
   const cx<T> tw1 = (SPLIT && ok) ? twH[h] : mk<T>(0, 0);   // w^h
+  // gam_p and x~_p are read by the threads that finish the reduction; they
+  // are fetched with the other loads, not after the barrier
+  const bool fin = kq == 0 && ok;
+  const T gp = fin ? gam[p] : (T)0;
   cx<T> a[KPT];
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
@@ -447,28 +451,46 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
   for (int sb = 0; sb < SB; ++sb) {
     const int b = by * SB + sb;
     if (b >= B) break;   // the same for the whole workgroup
+    const cx<T> xv = fin ? xh[(size_t)b * Pf + p] : mk<T>(0, 0);
     cx<T> s[KPT];
-    cx<T> acc = mk<T>(0, 0);
+    if (SPLIT) {
+      // every filter's E_0 and E_1 loads are issued before the first is used
+      // (a wait per filter would make KPT memory round trips of one)
+      cx<T> s1[KPT];
 #pragma unroll
-    for (int j = 0; j < KPT; ++j) {
-      const int k = kq + j * 16;
-      if (SPLIT) {
+      for (int j = 0; j < KPT; ++j) {
+        const int k = kq + j * 16;
+        const bool v = ok && k < K && !first;
         const cx<T>* e0 = S + ((size_t)b * K + k) * Pf + jh;
-        cx<T> v = mk<T>(0, 0);
-        if (ok && k < K && !first) {
-          v = cadd<T>(e0[0], cmul<T>(e0[part], tw1));
-          for (int r = 2, i = h; r < F; ++r) {   // i = h r mod PH
-            i += h;
-            if (i >= ph) i -= ph;
-            v = cadd<T>(v, cmul<T>(e0[(size_t)r * part], twH[i]));
+        s[j] = v ? e0[0] : mk<T>(0, 0);
+        s1[j] = v ? e0[part] : mk<T>(0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) s[j] = cadd<T>(s[j], cmul<T>(s1[j], tw1));
+      if (F > 2) {
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+          const int k = kq + j * 16;
+          if (ok && k < K && !first) {
+            const cx<T>* e0 = S + ((size_t)b * K + k) * Pf + jh;
+            for (int r = 2, i = h; r < F; ++r) {   // i = h r mod PH
+              i += h;
+              if (i >= ph) i -= ph;
+              s[j] = cadd<T>(s[j], cmul<T>(e0[(size_t)r * part], twH[i]));
+            }
           }
         }
-        s[j] = v;
-      } else {
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const int k = kq + j * 16;
         s[j] = (ok && k < K && !first) ? S[((size_t)b * K + k) * Pf + p] : mk<T>(0, 0);
       }
-      acc = cadd<T>(acc, cmul<T>(a[j], s[j]));
     }
+    cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) acc = cadd<T>(acc, cmul<T>(a[j], s[j]));
     red[kq][f] = acc;
     __syncthreads();
     if (kq == 0) {
@@ -476,7 +498,7 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
 #pragma unroll
       for (int i = 1; i < 16; ++i) tot = cadd<T>(tot, red[i][f]);
       cx<T> qv = mk<T>(0, 0);
-      if (ok) qv = cscale<T>(csub<T>(xh[(size_t)b * Pf + p], tot), gam[p]);
+      if (ok) qv = cscale<T>(csub<T>(xv, tot), gp);
       red[0][f] = qv;
     }
     __syncthreads();
