@@ -38,15 +38,28 @@ __device__ __forceinline__ void big_cols_body(cx<T>* buf, cx<T>* sH, int bx, lon
   const int tid = threadIdx.x;
   const int c0 = bx * CB;
   const size_t pb = (size_t)q * PH * WC;
-  for (int i = tid; i < PH; i += NT) sH[i] = twH[i];
   {
+    // the table and the block are fetched together and stored after all
+    // loads are issued (one memory round trip)
+    constexpr int NTH = (PH + NT - 1) / NT;
+    T thx[NTH], thy[NTH];   // real and imaginary parts apart: kept in registers
     cx<T> r[EPT];
+#pragma unroll
+    for (int i = 0; i < NTH; ++i)
+      if (PH % NT == 0 || tid + i * NT < PH) {
+        const cx<T> v = twH[tid + i * NT];
+        thx[i] = v.x;
+        thy[i] = v.y;
+      }
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const int e = tid + j * NT;
       const int u = e / CB, c = min(c0 + (e % CB), WC - 1);
       r[j] = src[pb + (size_t)u * WC + c];
     }
+#pragma unroll
+    for (int i = 0; i < NTH; ++i)
+      if (PH % NT == 0 || tid + i * NT < PH) sH[tid + i * NT] = mk<T>(thx[i], thy[i]);
 #pragma unroll
     for (int j = 0; j < EPT; ++j) buf[tid + j * NT] = r[j];
   }
@@ -153,9 +166,24 @@ __device__ __forceinline__ void big_code_rows_body(cx<T>* buf, cx<T>* sW, int bx
   const int r0 = bx * RB;
   const size_t so = q * PH * WC + (size_t)r0 * WC;   // spectrum rows
   const size_t ro = q * PH * PW + (size_t)r0 * PW;   // real rows
-  for (int i = tid; i < PW; i += NT) sW[i] = twW[i];
-  for (int e = tid; e < NE; e += NT) buf[e] = Y[so + e];
-  // this thread's W values are fetched while the rows are inverted
+  // the table and the rows are fetched into registers and stored after all
+  // loads (with this thread's W values, used after the inverse) are issued
+  constexpr int NTW = (PW + NT - 1) / NT, NEV = (NE + NT - 1) / NT;
+  T twx[NTW], twy[NTW], yx[NEV], yy[NEV];   // real and imaginary parts apart: kept in registers
+#pragma unroll
+  for (int i = 0; i < NTW; ++i)
+    if (PW % NT == 0 || tid + i * NT < PW) {
+      const cx<T> v = twW[tid + i * NT];
+      twx[i] = v.x;
+      twy[i] = v.y;
+    }
+#pragma unroll
+  for (int j = 0; j < NEV; ++j)
+    if (NE % NT == 0 || tid + j * NT < NE) {
+      const cx<T> v = Y[so + tid + j * NT];
+      yx[j] = v.x;
+      yy[j] = v.y;
+    }
   constexpr int WPT = (NR + NT - 1) / NT;
   T wv[WPT];
 #pragma unroll
@@ -163,6 +191,12 @@ __device__ __forceinline__ void big_code_rows_body(cx<T>* buf, cx<T>* sW, int bx
     const int e = tid + j * NT;
     wv[j] = (first || e >= NR) ? (T)0 : W[ro + min(e, NR - 1)];
   }
+#pragma unroll
+  for (int i = 0; i < NTW; ++i)
+    if (PW % NT == 0 || tid + i * NT < PW) sW[tid + i * NT] = mk<T>(twx[i], twy[i]);
+#pragma unroll
+  for (int j = 0; j < NEV; ++j)
+    if (NE % NT == 0 || tid + j * NT < NE) buf[tid + j * NT] = mk<T>(yx[j], yy[j]);
   __syncthreads();
   rows_c2r_lds<RB, PW, NT, T>(buf, sW, tid);
   const T scale = (T)1 / (T)(PH * PW);

@@ -140,6 +140,40 @@ __global__ __launch_bounds__(NT) void k_irfft2_crop(const cx<T>* __restrict__ sr
   }
 }
 
+// The twiddle tables through registers: fetch() issues their loads first, and
+// put() writes them to LDS after the plane's own loads have been issued, so
+// that waiting for the tables does not wait for those loads, and the two
+// fetches take one memory round trip instead of two.
+template <typename T, int PH, int PW, int NT>
+struct TableStage {
+  static constexpr int NH = (PH + NT - 1) / NT, NW = (PW + NT - 1) / NT;
+  T hx[NH], hy[NH], wx[NW], wy[NW];   // real and imaginary parts apart: kept in registers
+  __device__ __forceinline__ void fetch(const cx<T>* __restrict__ twH, const cx<T>* __restrict__ twW, int tid) {
+#pragma unroll
+    for (int i = 0; i < NH; ++i)
+      if (PH % NT == 0 || tid + i * NT < PH) {
+        const cx<T> v = twH[tid + i * NT];
+        hx[i] = v.x;
+        hy[i] = v.y;
+      }
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+      if (PW % NT == 0 || tid + i * NT < PW) {
+        const cx<T> v = twW[tid + i * NT];
+        wx[i] = v.x;
+        wy[i] = v.y;
+      }
+  }
+  __device__ __forceinline__ void put(cx<T>* sH, cx<T>* sW, int tid) const {
+#pragma unroll
+    for (int i = 0; i < NH; ++i)
+      if (PH % NT == 0 || tid + i * NT < PH) sH[tid + i * NT] = mk<T>(hx[i], hy[i]);
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+      if (PW % NT == 0 || tid + i * NT < PW) sW[tid + i * NT] = mk<T>(wx[i], wy[i]);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Code update, spatial half of one ADMM iteration, one workgroup per plane:
 //   Y = Re F^-1(Zh);  U = S_kappa(Y + W);  W <- Y + W - U;  S = F(U - W).
@@ -157,16 +191,23 @@ __device__ __forceinline__ void code_plane_body(cx<T>* buf, cx<T>* sH, cx<T>* sW
   using IO = PlaneIO<T, PH, PW, NT>;
   constexpr int VR = IO::VR, CR = IO::CR, NRV = IO::NRV;
   const int tid = threadIdx.x;
-  load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
+  TableStage<T, PH, PW, NT> tab;
+  tab.fetch(twH, twW, tid);
   IO::spec_in(buf, Zh + q * G::PF, tid);
   // the dual W of this plane is fetched while the inverse transform runs
   v4f* wv = reinterpret_cast<v4f*>(W + q * G::P);
   v4f wr[CR];
+  if (first) {   // outside the loop, so that the loads are not waited for one by one
 #pragma unroll
-  for (int j = 0; j < CR; ++j) {
-    const int e = tid + j * NT;
-    if (NRV % NT == 0 || e < NRV) wr[j] = first ? v4f{0, 0, 0, 0} : wv[e];
+    for (int j = 0; j < CR; ++j) wr[j] = v4f{0, 0, 0, 0};
+  } else {
+#pragma unroll
+    for (int j = 0; j < CR; ++j) {
+      const int e = tid + j * NT;
+      if (NRV % NT == 0 || e < NRV) wr[j] = wv[e];
+    }
   }
+  tab.put(sH, sW, tid);
   __syncthreads();
   irfft2_lds<PH, PW, NT, T>(buf, sH, sW, tid);
   const T scale = (T)1 / (T)G::P;
@@ -285,7 +326,8 @@ __device__ __forceinline__ void code_plane_split_body(cx<T>* buf, cx<T>* sH, cx<
   constexpr int U = CS < U0 ? CS : U0;       // vectors per thread per round of spectrum loads
   constexpr int NR = (CS + U - 1) / U;       // rounds
   const int tid = threadIdx.x;
-  load_tables<PH, PW, T>(sH, sW, twH, twW, tid, NT);
+  TableStage<T, PH, PW, NT> tab;
+  tab.fetch(twH, twW, tid);
   // spectrum rows h' + j PH/F (j < F) of the plane, U vectors per thread at a time
   const v4f* zs = reinterpret_cast<const v4f*>(Zh + q * G::PF);
   v4f zin[U][F];
@@ -303,14 +345,20 @@ __device__ __forceinline__ void code_plane_split_body(cx<T>* buf, cx<T>* sH, cx<
   // the dual on this workgroup's rows
   T* const Wq = W + q * G::P;
   v4f wr[CR];
+  if (first) {   // outside the loop, so that the loads are not waited for one by one
 #pragma unroll
-  for (int j = 0; j < CR; ++j) {
-    const int v = tid + j * NT;
-    if (NRV % NT == 0 || v < NRV) {
-      const int i = v * VR, m = i / PW;
-      wr[j] = first ? v4f{0, 0, 0, 0} : *reinterpret_cast<const v4f*>(Wq + (F * m + e) * PW + i % PW);
+    for (int j = 0; j < CR; ++j) wr[j] = v4f{0, 0, 0, 0};
+  } else {
+#pragma unroll
+    for (int j = 0; j < CR; ++j) {
+      const int v = tid + j * NT;
+      if (NRV % NT == 0 || v < NRV) {
+        const int i = v * VR, m = i / PW;
+        wr[j] = *reinterpret_cast<const v4f*>(Wq + (F * m + e) * PW + i % PW);
+      }
     }
   }
+  tab.put(sH, sW, tid);
   __syncthreads();   // tables
   v4f* d = reinterpret_cast<v4f*>(buf);
 #pragma unroll 1

@@ -232,10 +232,13 @@ __global__ __launch_bounds__(NT) void k_vstep_filter(const cx<T>* __restrict__ d
   {
     cx<T> dq[FPT], tqv[FPT];
 #pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      const int e = min(tid + j * NT, PF - 1);
-      dq[j] = d[base + e];
-      tqv[j] = first ? mk<T>(0, 0) : Th[base + e];
+    for (int j = 0; j < FPT; ++j) dq[j] = d[base + min(tid + j * NT, PF - 1)];
+    if (first) {   // outside the loop, so that the loads are not waited for one by one
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) tqv[j] = mk<T>(0, 0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) tqv[j] = Th[base + min(tid + j * NT, PF - 1)];
     }
 #pragma unroll
     for (int j = 0; j < FPT; ++j) {
@@ -386,10 +389,15 @@ __global__ __launch_bounds__(1024) void k_vstep_mfma(const float2* __restrict__ 
     const float2 th = twH[min(tid, PH - 1)], tw = twW[min(tid, PW - 1)];
     float2 dq[FPT], tq[FPT];
 #pragma unroll
-    for (int j = 0; j < FPT; ++j) {
-      const int e = min(tid + j * NT, PF - 1);
-      dq[j] = d[base + e];
-      tq[j] = first ? make_float2(0.f, 0.f) : Th[base + e];
+    for (int j = 0; j < FPT; ++j) dq[j] = d[base + min(tid + j * NT, PF - 1)];
+    // the test of first stays outside the loop: a branch around each load
+    // made the compiler wait for all loads in flight at every join
+    if (first) {
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) tq[j] = make_float2(0.f, 0.f);
+    } else {
+#pragma unroll
+      for (int j = 0; j < FPT; ++j) tq[j] = Th[base + min(tid + j * NT, PF - 1)];
     }
 #pragma unroll
     for (int tt = 0; tt < TPW; ++tt) {
