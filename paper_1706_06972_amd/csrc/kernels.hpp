@@ -516,16 +516,22 @@ __device__ __forceinline__ void zstep_body(cx<T> (*red)[ZF + 1], int bx, int by,
 #pragma unroll
       for (int j = 0; j < KPT; ++j) s[j] = cadd<T>(s[j], cmul<T>(s1[j], tw1));
       if (F > 2) {
+        // one residue at a time, every filter's load issued before the first
+        // is used (each filter still adds its terms in the order r = 2, 3, ..)
+        for (int r = 2, i = h; r < F; ++r) {   // i = h r mod PH
+          i += h;
+          if (i >= ph) i -= ph;
+          const cx<T> twr = ok ? twH[i] : mk<T>(0, 0);
+          cx<T> er[KPT];
 #pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-          const int k = kq + j * 16;
-          if (ok && k < K && !first) {
-            const cx<T>* e0 = S + ((size_t)b * K + k) * Pf + jh;
-            for (int r = 2, i = h; r < F; ++r) {   // i = h r mod PH
-              i += h;
-              if (i >= ph) i -= ph;
-              s[j] = cadd<T>(s[j], cmul<T>(e0[(size_t)r * part], twH[i]));
-            }
+          for (int j = 0; j < KPT; ++j) {
+            const int k = kq + j * 16;
+            er[j] = (ok && k < K && !first) ? S[((size_t)b * K + k) * Pf + jh + (size_t)r * part] : mk<T>(0, 0);
+          }
+#pragma unroll
+          for (int j = 0; j < KPT; ++j) {
+            const int k = kq + j * 16;
+            if (ok && k < K && !first) s[j] = cadd<T>(s[j], cmul<T>(er[j], twr));
           }
         }
       }
